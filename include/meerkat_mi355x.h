@@ -1,0 +1,199 @@
+/* meerkat_mi355x.h -- C-ABI of the MI355X dynamic slab-hash graph library.
+ *
+ * A directed graph on a fixed vertex set [0, n_vertices) is stored as one hash table per
+ * vertex: the destination id picks a bucket, and each bucket is a chain of 128-byte slabs
+ * (section 2 of the paper: SlabHash slabs with an EMPTY and a TOMBSTONE sentinel; section
+ * 3.1: head slabs of all vertices carved from one allocation, sized from the initial
+ * degree and the load factor; further slabs come from a device slab allocator).
+ *
+ * Conventions shared by every entry point
+ *   - Device pointers (prefix d_) are caller-owned device memory, typically torch tensors.
+ *     Host pointers have the prefix h_.  The library never allocates device memory: every
+ *     byte it uses lives in the caller's arena passed to mk_graph_create.  It allocates a
+ *     few pinned host words per graph (hipHostMalloc) for size read-backs.
+ *   - Every call is ordered on the given HIP stream.  Calls that must read a size back
+ *     (traversal frontier sizes, PageRank convergence, mk_graph_stats) synchronize that
+ *     stream; the update and query calls never synchronize.
+ *   - Vertex ids and weights are uint32.  Ids >= 0xFFFFFFFD are reserved sentinels
+ *     (EMPTY = 0xFFFFFFFE and TOMBSTONE = 0xFFFFFFFD, as in section 2; 0xFFFFFFFF is
+ *     INVALID) and are rejected.  Weights must be >= 1 for shortest paths.
+ *   - Errors are returned as mk_status; nothing aborts or throws across the ABI.  On any
+ *     error other than MK_ERR_HIP the graph is unchanged.  A graph is not thread-safe:
+ *     use one stream per graph.
+ */
+#ifndef MEERKAT_MI355X_H
+#define MEERKAT_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mk_graph mk_graph; /* opaque; host-side metadata + pointers into the arena */
+
+typedef enum {
+  MK_OK = 0,
+  MK_ERR_INVALID_ARG = 1,  /* null/misaligned pointer, size out of range, bad config      */
+  MK_ERR_OUT_OF_SLABS = 2, /* the slab pool could not hold the batch; nothing was applied */
+  MK_ERR_CAPACITY = 3,     /* arena too small, or a batch larger than the change log      */
+  MK_ERR_STATE = 4,        /* the operation needs a view that the graph was built without */
+  MK_ERR_HIP = 5           /* a HIP runtime call failed (the message is kept per graph)   */
+} mk_status;
+
+typedef enum {
+  MK_AUTO = 0,      /* incremental when the pending batches allow it, else recompute      */
+  MK_INCR = 1,      /* incremental if at all possible (falls back to recompute if not)    */
+  MK_RECOMPUTE = 2  /* recompute from scratch on the current graph                        */
+} mk_mode;
+
+enum {
+  MK_VIEW_FWD = 1, /* out-edges <dst, weight>: updates, queries, BFS, SSSP (always on)   */
+  MK_VIEW_REV = 2, /* in-edges <src, weight>: PageRank pull, decremental BFS/SSSP        */
+  MK_VIEW_UND = 4  /* undirected simple graph: triangle counting                         */
+};
+
+typedef struct {
+  uint32_t n_vertices;   /* fixed vertex count N (1 .. 2^30)                               */
+  uint32_t views;        /* MK_VIEW_* mask; MK_VIEW_FWD is implied                           */
+  float load_factor;     /* keys per bucket / slab capacity at build (the paper's load
+                            factor, section 3.1); 0 = one bucket per vertex (hashing off)   */
+  uint32_t hash_seed;    /* seed of the bucket hash                                         */
+  uint64_t pool_slabs;   /* chained slabs per view beyond the head slabs; 0 = derived from
+                            the edge-count hint with room for later inserts                  */
+  uint64_t log_capacity; /* update ops remembered for incremental algorithms (ring of
+                            batches); 0 = max(2^20, edge hint / 8)                           */
+} mk_config;
+
+typedef struct {
+  uint64_t n_arcs;            /* live arcs in the forward view                             */
+  uint64_t n_und_edges;       /* live undirected edges (0 without MK_VIEW_UND)             */
+  uint64_t head_slabs[3];     /* head slabs per view (fwd, rev, und)                       */
+  uint64_t pool_used[3];      /* chained slabs handed out per view                         */
+  uint64_t pool_capacity[3];  /* chained-slab capacity per view                            */
+  uint64_t arena_bytes_used;  /* bytes of the arena actually carved                        */
+  uint64_t batches_applied;   /* update batches applied since creation                     */
+} mk_stats;
+
+/* Bytes of arena needed for `cfg` and an initial edge count `n_edges_hint` (an upper bound
+ * of the arcs passed to mk_graph_create).  Returns 0 if the configuration is invalid. */
+size_t mk_arena_bytes(const mk_config* cfg, uint64_t n_edges_hint);
+
+/* Build a graph from an initial arc list (section 3.1 memory management: per-vertex
+ * bucket counts from the initial degree and the load factor, one exclusive scan for the
+ * head-slab offsets, then a bulk insert).
+ *   d_arena/arena_bytes : caller-owned device buffer of at least mk_arena_bytes(cfg, m)
+ *                         bytes, 256-byte aligned; it must outlive the graph.
+ *   d_src/d_dst/d_w     : m arcs (device, uint32 each); d_w may be NULL (weight 1).
+ *                         Duplicates keep one copy; invalid arcs are skipped.
+ *   out                 : receives the handle.  The call synchronizes `stream` once.
+ */
+mk_status mk_graph_create(const mk_config* cfg, void* d_arena, size_t arena_bytes,
+                          const uint32_t* d_src, const uint32_t* d_dst, const uint32_t* d_w,
+                          uint64_t m, hipStream_t stream, mk_graph** out);
+
+/* Release the host-side handle (the arena stays the caller's). NULL is accepted. */
+mk_status mk_graph_destroy(mk_graph* g);
+
+/* Batched edge insertion (the graph-operation discussion of the experimental section:
+ * hash the destination to one bucket of the source, walk that chain to its end to rule
+ * out a duplicate, store the arc in the first EMPTY lane, link a fresh slab from the
+ * allocator when the chain is full).  Every enabled view is updated in the same call.
+ *   d_src/d_dst/d_w : n arcs (device).  d_w may be NULL (weight 1).
+ *   d_status        : NULL or n bytes (device): 1 inserted, 0 already present (weight
+ *                     unchanged), 2 rejected (id >= N, self-loop or reserved id).  Copies
+ *                     of one arc inside a batch: exactly one copy reports 1.
+ * MK_ERR_OUT_OF_SLABS when the pool might not hold the batch (nothing applied);
+ * MK_ERR_CAPACITY when n exceeds the change-log capacity. */
+mk_status mk_insert_edges(mk_graph* g, const uint32_t* d_src, const uint32_t* d_dst,
+                          const uint32_t* d_w, uint64_t n, uint8_t* d_status, hipStream_t stream);
+
+/* Batched edge deletion (same discussion: walk the hashed chain until the arc is found and
+ * turn its lane into a TOMBSTONE; stop at the first EMPTY lane).  Status bytes as for
+ * insert: 1 deleted, 0 absent, 2 rejected.  An undirected edge {u,v} leaves the
+ * MK_VIEW_UND view only when neither (u,v) nor (v,u) remains after the batch. */
+mk_status mk_delete_edges(mk_graph* g, const uint32_t* d_src, const uint32_t* d_dst, uint64_t n,
+                          uint8_t* d_status, hipStream_t stream);
+
+/* Batched membership query (SearchEdge: probe only the hashed chain).
+ *   d_found : n bytes (device), 1 present / 0 absent (also 0 for invalid ids).
+ *   d_w     : NULL or n uint32 (device): the weight when present, else 0. */
+mk_status mk_query_edges(mk_graph* g, const uint32_t* d_src, const uint32_t* d_dst, uint64_t n,
+                         uint8_t* d_found, uint32_t* d_w, hipStream_t stream);
+
+/* Breadth-first search levels from `source` kept up to date across batches (section 4.2:
+ * BFS runs the SSSP kernels with unit weights).  A first call or a new source computes
+ * from scratch; later calls apply the pending batches incrementally (insert prologue:
+ * relax the inserted arcs; delete prologue: invalidate the dependence subtrees of
+ * deleted tree arcs and pull from valid in-neighbours, which needs MK_VIEW_REV, else a
+ * recompute) and then run the frontier epilogue to a fixed point.
+ *   d_level  : N uint32 (device): hop distance, 0xFFFFFFFF if unreachable.
+ *   d_parent : NULL or N uint32 (device): the smallest-id in-neighbour one level up;
+ *              `source` for the source; 0xFFFFFFFF if unreachable. */
+mk_status mk_incr_bfs(mk_graph* g, uint32_t source, uint32_t* d_level, uint32_t* d_parent,
+                      mk_mode mode, hipStream_t stream);
+
+/* Single-source shortest paths (section 4.2, the dynamic SSSP algorithm), maintained as
+ * for BFS with the arc weights.  The <distance, parent> pair of each vertex is one 64-bit
+ * word updated by atomic minimum, so among equal distances the smallest parent id wins.
+ *   d_dist   : N uint32 (device): distance (saturates at 0xFFFFFFFE), 0xFFFFFFFF if
+ *              unreachable.
+ *   d_parent : NULL or N uint32 (device), as for BFS. */
+mk_status mk_incr_sssp(mk_graph* g, uint32_t source, uint32_t* d_dist, uint32_t* d_parent,
+                       mk_mode mode, hipStream_t stream);
+
+/* Weakly connected components (section 4.4: union-find with full path compression).
+ * Inserted arcs are united incrementally; any pending deletion forces a recompute.
+ *   d_label : N uint32 (device): the smallest vertex id of the component. */
+mk_status mk_incr_wcc(mk_graph* g, uint32_t* d_label, mk_mode mode, hipStream_t stream);
+
+/* PageRank (section 4.1): PR'(v) = (1-d)/N + d * (sum over in-arcs u->v of PR(u)/out(u)
+ * + sum over zero-out-degree z of PR(z)/N), iterated from 1/N (first call, RECOMPUTE) or
+ * from the previous vector (incremental and decremental batches) until the L1 change of
+ * one iteration is <= tol_l1, stops decreasing for three iterations, or max_iter is hit.
+ * Needs MK_VIEW_REV.  Ranks are stored in FP32; sums and the L1 change use FP64.
+ *   d_rank  : N float (device).   d_iters : NULL or 1 uint32 (device): iterations run. */
+mk_status mk_incr_pagerank(mk_graph* g, float damping, double tol_l1, uint32_t max_iter,
+                           float* d_rank, uint32_t* d_iters, mk_mode mode, hipStream_t stream);
+
+/* Triangles of the undirected simple graph under the arc set (section 4.3).  After
+ * insertions T += (S1 - S2 + S3/3)/2 and after deletions T -= (S1 + S2 + S3/3)/2 with
+ * S1 = Count(G, G, B), S2 = Count(G, U, B), S3 = Count(U, U, B) over both directions of
+ * the effective batch B, G the graph after the batch and U the graph of the batch alone;
+ * a recompute counts every edge once from its lower-(degree, id) end.  Needs MK_VIEW_UND.
+ *   d_count : 1 uint64 (device). */
+mk_status mk_count_triangles(mk_graph* g, uint64_t* d_count, mk_mode mode, hipStream_t stream);
+
+/* Slab iterator export: write every live arc (order unspecified) to d_src/d_dst/d_w
+ * (device, capacity `cap` each; d_w may be NULL) and the count to *h_count.  Synchronizes.
+ * MK_ERR_CAPACITY if cap is too small (*h_count still receives the count). */
+mk_status mk_graph_export(mk_graph* g, uint32_t* d_src, uint32_t* d_dst, uint32_t* d_w,
+                          uint64_t cap, uint64_t* h_count, hipStream_t stream);
+
+/* Byte model of the batched operations (no change is made): the number of slabs that
+ * `op` (0 = query/delete, which stop at the arc or the first EMPTY lane; 1 = insert, which
+ * walks the hashed chain to its end) would read for each of the n arcs in `view` (0 fwd
+ * keyed by src, 1 rev keyed by dst, 2 und in both directions), summed into *h_slabs.  The
+ * benchmark turns it into algorithmic bytes.  Synchronizes.
+ * MK_ERR_STATE if the view is not enabled. */
+mk_status mk_probe_cost(mk_graph* g, int op, int view, const uint32_t* d_src, const uint32_t* d_dst,
+                        uint64_t n, uint64_t* h_slabs, hipStream_t stream);
+
+/* Occupancy and capacity figures (synchronizes). */
+mk_status mk_graph_stats(mk_graph* g, mk_stats* h_out, hipStream_t stream);
+
+/* Structural self-check of every chain of every view: no duplicate keys in a vertex's
+ * table, no EMPTY lane before a filled one inside a chain, next links in range, the key's
+ * bucket matches its hash, degree counters match the live lanes.  *h_bad receives the
+ * number of violations (0 when sound).  Synchronizes. */
+mk_status mk_graph_check(mk_graph* g, uint64_t* h_bad, hipStream_t stream);
+
+/* Human-readable name of a status; the last HIP error text for MK_ERR_HIP. */
+const char* mk_status_string(mk_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MEERKAT_MI355X_H */

@@ -1,0 +1,531 @@
+// Weakly connected components (section 4.4), PageRank (section 4.1) and triangle
+// counting (section 4.3) over the slab views.
+//
+// All-vertex walks follow the paper's IterationScheme1 (one vertex per lane group); the
+// few vertices with more than kHeavyBuckets buckets are walked by a whole block so that a
+// power-law hub does not serialize one group.
+#include <cstring>
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
+
+#include <algorithm>
+#include <cmath>
+
+#include "mk_internal.h"
+
+using namespace mk;
+
+namespace {
+
+constexpr uint32_t kWalkBlocks = 4096;
+constexpr int kPrSyncEvery = 4;
+
+inline uint32_t blocks_for(uint64_t n, uint32_t cap = 4096) {
+  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((n + kBlock - 1) / kBlock, cap));
+}
+
+// Vertices of a view with more than kHeavyBuckets buckets.
+__global__ void k_collect_heavy(const uint2* dir, uint32_t nv, uint32_t* out, uint32_t* cnt) {
+  const uint64_t lane = threadIdx.x & 63;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x - lane; base < nv;
+       base += stride) {
+    const uint64_t v = base + lane;
+    const bool heavy = v < nv && dir[v].y > kHeavyBuckets;
+    wave_push(out, cnt, heavy, (uint32_t)v);
+  }
+}
+
+__global__ void k_zero_u32(uint32_t* p, uint32_t n) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
+// ================================================================= union-find (WCC)
+// Hooking rule: the larger root is hooked under the smaller one by CAS, so every parent
+// pointer goes to a smaller id and the final root of a component is its minimum id.
+__device__ inline uint32_t uf_find(uint32_t* P, uint32_t x) {
+  while (true) {
+    const uint32_t p = ld_u32_coherent(P + x);
+    if (p == x) return x;
+    const uint32_t gp = ld_u32_coherent(P + p);
+    if (gp != p) __hip_atomic_store(P + x, gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);  // halving
+    x = gp;
+  }
+}
+
+__device__ inline void uf_union(uint32_t* P, uint32_t a, uint32_t b) {
+  while (true) {
+    a = uf_find(P, a);
+    b = uf_find(P, b);
+    if (a == b) return;
+    if (a < b) {
+      const uint32_t t = a;
+      a = b;
+      b = t;
+    }
+    const uint32_t r = atomicCAS(P + a, a, b);  // hook the larger root under the smaller
+    if (r == a) return;
+    a = r;  // a was hooked meanwhile: continue from its true parent (a smaller id)
+  }
+}
+
+__global__ void k_wcc_init(uint32_t* P, uint32_t nv) {
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) P[v] = v;
+}
+
+__global__ void __launch_bounds__(kBlock) k_wcc_all(DView F, uint32_t* P, uint32_t nv,
+                                                    const uint32_t* heavy, const uint32_t* nheavy) {
+  const uint32_t g0 = (blockIdx.x * kBlock + threadIdx.x) / kGroup;
+  const uint32_t ng = gridDim.x * kGroupsPerBlock;
+  auto body = [&](uint32_t u, uint64_t x) {
+    const uint32_t v = (uint32_t)x;
+    if (glane() < kKeysPerSlab && valid_key(v)) uf_union(P, u, v);
+  };
+  for (uint32_t u = g0; u < nv; u += ng) {
+    if (F.dir[u].y > kHeavyBuckets) continue;
+    for_each_slab<false>(F, u, [&](uint64_t x) { body(u, x); });
+  }
+  const uint32_t nh = *nheavy, gib = threadIdx.x / kGroup;
+  for (uint32_t j = blockIdx.x; j < nh; j += gridDim.x) {
+    const uint32_t u = heavy[j];
+    for_each_slab_strided<false>(F, F.dir[u], gib, kGroupsPerBlock, [&](uint64_t x) { body(u, x); });
+  }
+}
+
+__global__ void k_wcc_batch(uint32_t* P, Log lg, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    if (lg.st[i] == 1) uf_union(P, lg.s[i], lg.d[i]);
+}
+
+__global__ void k_wcc_compress(uint32_t* P, uint32_t nv, uint32_t* label) {
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
+    const uint32_t r = uf_find(P, v);
+    __hip_atomic_store(P + v, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__global__ void k_copy_u32(const uint32_t* a, uint32_t* b, uint32_t n) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) b[i] = a[i];
+}
+
+// ================================================================= PageRank
+__device__ inline double block_sum(double v, double* lds) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) lds[w] = v;
+  __syncthreads();
+  double s = 0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += lds[i];
+  return s;  // valid in thread 0
+}
+
+__global__ void k_pr_fill(float* x, uint32_t nv, float v) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += gridDim.x * blockDim.x) x[i] = v;
+}
+
+// Contribution per vertex C[u] = PR[u] / out[u] (the FindContributionPerVertex kernel),
+// plus the FP64 sum of the ranks of zero-out-degree vertices (FindTeleportProb).
+__global__ void __launch_bounds__(kBlock) k_pr_contrib(const float* __restrict__ x,
+                                                       const uint32_t* __restrict__ outdeg,
+                                                       float* __restrict__ c, uint32_t nv,
+                                                       double* dang, const uint32_t* state) {
+  __shared__ double lds[kBlock / 64];
+  if (state[0]) return;
+  double local = 0;
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
+    const uint32_t o = outdeg[v];
+    const float xv = x[v];
+    c[v] = o ? xv / (float)o : 0.f;
+    if (!o) local += xv;
+  }
+  const double s = block_sum(local, lds);
+  if (threadIdx.x == 0 && s != 0.0) atomicAdd(dang, s);
+}
+
+// Pull over in-arcs (reverse view): PR'[v] = (1-d)/N + d * (sum C[u] + dangling/N),
+// and the FP64 L1 change sum |PR'[v] - PR[v]|.
+__global__ void __launch_bounds__(kBlock) k_pr_gather(DView R, const float* __restrict__ c,
+                                                      const float* __restrict__ x,
+                                                      float* __restrict__ y, uint32_t nv, float damping,
+                                                      const double* dang, double* delta,
+                                                      const uint32_t* heavy, const uint32_t* nheavy,
+                                                      const uint32_t* state) {
+  __shared__ double lds[kBlock / 64];
+  __shared__ double part[kGroupsPerBlock];
+  if (state[0]) return;
+  const double base = (1.0 - (double)damping) / nv + (double)damping * (*dang) / nv;
+  double local = 0;
+  const uint32_t g0 = (blockIdx.x * kBlock + threadIdx.x) / kGroup;
+  const uint32_t ng = gridDim.x * kGroupsPerBlock;
+  for (uint32_t v = g0; v < nv; v += ng) {
+    if (R.dir[v].y > kHeavyBuckets) continue;
+    double s = 0;
+    for_each_slab<false>(R, v, [&](uint64_t w) {
+      const uint32_t u = (uint32_t)w;
+      if (glane() < kKeysPerSlab && valid_key(u)) s += (double)c[u];
+    });
+    s = gsum(s);
+    if (glane() == 0) {
+      const float nvl = (float)(base + (double)damping * s);
+      y[v] = nvl;
+      local += fabs((double)nvl - (double)x[v]);
+    }
+  }
+  const uint32_t nh = *nheavy, gib = threadIdx.x / kGroup;
+  for (uint32_t j = blockIdx.x; j < nh; j += gridDim.x) {
+    const uint32_t v = heavy[j];
+    double s = 0;
+    for_each_slab_strided<false>(R, R.dir[v], gib, kGroupsPerBlock, [&](uint64_t w) {
+      const uint32_t u = (uint32_t)w;
+      if (glane() < kKeysPerSlab && valid_key(u)) s += (double)c[u];
+    });
+    s = gsum(s);
+    __syncthreads();
+    if (glane() == 0) part[gib] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0;
+      for (int i = 0; i < kGroupsPerBlock; ++i) t += part[i];
+      const float nvl = (float)(base + (double)damping * t);
+      y[v] = nvl;
+      local += fabs((double)nvl - (double)x[v]);
+    }
+  }
+  const double s = block_sum(local, lds);
+  if (threadIdx.x == 0 && s != 0.0) atomicAdd(delta, s);
+}
+
+// Convergence bookkeeping for one iteration (single thread): stop at delta <= tol, when
+// the change has not improved for three iterations (the FP32 noise floor), or at max_iter.
+__global__ void k_pr_check(Counters* C, int slot, double tol, uint32_t max_iter) {
+  if (threadIdx.x != 0) return;
+  uint32_t* st = C->pr_state;
+  if (st[0]) return;
+  const double d = C->pr_acc[2 * slot + 1];
+  st[1] += 1;
+  C->pr_last = d;
+  if (d < C->pr_best * 0.999) {
+    C->pr_best = d;
+    st[2] = 0;
+  } else {
+    st[2] += 1;
+  }
+  if (d <= tol || st[2] >= 3 || st[1] >= max_iter) st[0] = 1;
+  const int clr = (slot + 2) & 3;
+  C->pr_acc[2 * clr] = 0.0;
+  C->pr_acc[2 * clr + 1] = 0.0;
+}
+
+__global__ void k_pr_start(Counters* C) {
+  if (threadIdx.x != 0) return;
+  for (int i = 0; i < 8; ++i) C->pr_acc[i] = 0.0;
+  C->pr_state[0] = 0;
+  C->pr_state[1] = 0;
+  C->pr_state[2] = 0;
+  C->pr_last = 0;
+  C->pr_best = 1e300;
+}
+
+// Copy the final vector (buffer iters % 2) to the persistent state and the output.
+__global__ void k_pr_final(const Counters* C, const float* a, const float* b, float* keep, float* out,
+                           uint32_t nv, uint32_t* iters_out) {
+  const uint32_t it = C->pr_state[1];
+  const float* src = (it & 1) ? b : a;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += gridDim.x * blockDim.x) {
+    const float v = src[i];
+    if (keep != src) keep[i] = v;
+    out[i] = v;
+  }
+  if (iters_out && blockIdx.x == 0 && threadIdx.x == 0) *iters_out = it;
+}
+
+// ================================================================= triangle counting
+__device__ inline bool lane_has(const DView& V, uint32_t u, uint32_t key) {
+  const uint2 de = V.dir[u];
+  uint32_t s = de.x + bucket_of(key, de.y, V.hash_a, V.hash_b);
+  while (s != kInvalid) {
+    const uint32_t* sp = reinterpret_cast<const uint32_t*>(slab_ptr(V, s));
+    for (int j = 0; j < kKeysPerSlab; ++j) {
+      const uint32_t k = sp[2 * j];
+      if (k == key) return true;
+      if (k == kEmptyKey) return false;
+    }
+    s = sp[30];
+  }
+  return false;
+}
+
+__device__ inline bool ranks_before(const uint32_t* deg, uint32_t a, uint32_t b) {
+  const uint32_t da = deg[a], db = deg[b];
+  return da < db || (da == db && a < b);
+}
+
+// |N(a) intersect N(b)| counted by the calling group: walk N(a), each lane probes its
+// neighbour in b's table.  Returns the group total in every lane.
+__device__ inline uint64_t group_intersect(const DView& U, uint32_t a, uint32_t b) {
+  uint64_t c = 0;
+  for_each_slab<false>(U, a, [&](uint64_t x) {
+    const uint32_t k = (uint32_t)x;
+    if (glane() < kKeysPerSlab && valid_key(k) && k != b) c += lane_has(U, b, k);
+  });
+  return gsum_u64(c);
+}
+
+// Static count: every undirected edge {u, v} once, from its lower-(degree, id) end.
+__global__ void __launch_bounds__(kBlock) k_tc_static(DView U, uint32_t nv, const uint32_t* heavy,
+                                                      const uint32_t* nheavy,
+                                                      unsigned long long* acc) {
+  uint64_t local = 0;
+  auto per_vertex = [&](uint32_t u, uint32_t b0, uint32_t stride) {
+    const uint2 de = U.dir[u];
+    for_each_slab_strided<false>(U, de, b0, stride, [&](uint64_t x) {
+      const uint32_t v = (uint32_t)x;
+      uint32_t todo = gballot(glane() < kKeysPerSlab && valid_key(v) && ranks_before(U.deg, u, v));
+      while (todo) {
+        const int l = __builtin_ctz(todo);
+        todo &= todo - 1;
+        const uint32_t vv = gbcast(v, l);
+        const uint64_t c = group_intersect(U, u, vv);
+        if (glane() == 0) local += c;
+      }
+    });
+  };
+  const uint32_t g0 = (blockIdx.x * kBlock + threadIdx.x) / kGroup;
+  const uint32_t ng = gridDim.x * kGroupsPerBlock;
+  for (uint32_t u = g0; u < nv; u += ng) {
+    if (U.dir[u].y > kHeavyBuckets) continue;
+    per_vertex(u, 0, 1);
+  }
+  const uint32_t nh = *nheavy, gib = threadIdx.x / kGroup;
+  for (uint32_t j = blockIdx.x; j < nh; j += gridDim.x) per_vertex(heavy[j], gib, kGroupsPerBlock);
+  if (glane() == 0 && local) atomicAdd(acc, (unsigned long long)local);
+}
+
+// Keys of the batch graph: both directions of each effective undirected change, or a
+// sentinel (vertex N) that sorts last.
+__global__ void k_tc_keys(Log lg, uint64_t n, uint32_t nv, uint64_t* keys) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t k0 = (uint64_t)nv << 32, k1 = k0;
+    if (lg.uf[i]) {
+      const uint32_t a = min(lg.s[i], lg.d[i]), b = max(lg.s[i], lg.d[i]);
+      k0 = ((uint64_t)a << 32) | b;
+      k1 = ((uint64_t)b << 32) | a;
+    }
+    keys[2 * i] = k0;
+    keys[2 * i + 1] = k1;
+  }
+}
+
+__device__ inline uint64_t lower_bound_u64(const uint64_t* a, uint64_t n, uint64_t key) {
+  uint64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const uint64_t mid = (lo + hi) >> 1;
+    if (a[mid] < key) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// S1, S2 and S3 of the batch identity, one group per batch arc (u, v):
+//   S1 += |N_G(u) & N_G(v)|, S2 += |N_G(u) & N_B(v)|, S3 += |N_B(u) & N_B(v)|
+// with G the graph after the batch and B the graph of the batch alone.
+__global__ void __launch_bounds__(kBlock) k_tc_batch(DView U, const uint64_t* keys, uint64_t nk,
+                                                     uint32_t nv, unsigned long long* S) {
+  const uint64_t g0 = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kGroup;
+  const uint64_t ng = (uint64_t)gridDim.x * kGroupsPerBlock;
+  uint64_t s1 = 0, s2 = 0, s3 = 0;
+  const int gl = glane();
+  for (uint64_t i = g0; i < nk; i += ng) {
+    const uint64_t key = keys[i];
+    const uint32_t u = (uint32_t)(key >> 32), v = (uint32_t)key;
+    if (u >= nv) break;  // sentinels sort last
+    // S1: walk the smaller side, probe the other
+    const bool u_small = U.deg[u] <= U.deg[v];
+    const uint64_t c1 = group_intersect(U, u_small ? u : v, u_small ? v : u);
+    // batch neighbourhoods from the sorted key list
+    const uint64_t vlo = lower_bound_u64(keys, nk, (uint64_t)v << 32);
+    const uint64_t vhi = lower_bound_u64(keys, nk, ((uint64_t)v + 1) << 32);
+    const uint64_t ulo = lower_bound_u64(keys, nk, (uint64_t)u << 32);
+    const uint64_t uhi = lower_bound_u64(keys, nk, ((uint64_t)u + 1) << 32);
+    uint64_t c2 = 0, c3 = 0;
+    for (uint64_t j = vlo + gl; j < vhi; j += kGroup) {
+      const uint32_t x = (uint32_t)keys[j];
+      if (x == u) continue;
+      c2 += lane_has(U, u, x);
+      const uint64_t p = lower_bound_u64(keys + ulo, uhi - ulo, ((uint64_t)u << 32) | x);
+      c3 += (p < uhi - ulo) && keys[ulo + p] == (((uint64_t)u << 32) | x);
+    }
+    c2 = gsum_u64(c2);
+    c3 = gsum_u64(c3);
+    if (gl == 0) {
+      s1 += c1;
+      s2 += c2;
+      s3 += c3;
+    }
+  }
+  if (gl == 0) {
+    if (s1) atomicAdd(S + 0, (unsigned long long)s1);
+    if (s2) atomicAdd(S + 1, (unsigned long long)s2);
+    if (s3) atomicAdd(S + 2, (unsigned long long)s3);
+  }
+}
+
+__global__ void k_tc_begin(Counters* C, bool reset_total) {
+  if (threadIdx.x != 0) return;
+  C->tc_s[0] = C->tc_s[1] = C->tc_s[2] = 0;
+  C->u64tmp[0] = 0;
+  if (reset_total) C->tc_total = 0;
+}
+
+// insert: T += (S1 - S2 + S3/3) / 2;  delete: T -= (S1 + S2 + S3/3) / 2;  static: T = sum / 3
+__global__ void k_tc_finish(Counters* C, int kind, unsigned long long* out) {
+  if (threadIdx.x != 0) return;
+  const unsigned long long s1 = C->tc_s[0], s2 = C->tc_s[1], s3 = C->tc_s[2];
+  if (kind == 0) C->tc_total += (s1 - s2 + s3 / 3) / 2;
+  else if (kind == 1) C->tc_total -= (s1 + s2 + s3 / 3) / 2;
+  else C->tc_total = C->u64tmp[0] / 3;
+  if (out) *out = C->tc_total;
+}
+
+Log log_at(const mk_graph* g, uint64_t off) {
+  Log l = g->log;
+  l.s += off;
+  l.d += off;
+  l.w += off;
+  l.st += off;
+  l.uf += off;
+  return l;
+}
+
+}  // namespace
+
+extern "C" {
+
+mk_status mk_incr_wcc(mk_graph* g, uint32_t* d_label, mk_mode mode, hipStream_t stream) {
+  if (!g || !d_label) return MK_ERR_INVALID_ARG;
+  const uint32_t N = g->n;
+  Pending p = pending_for(g, g->wcc);
+  const bool full = mode == MK_RECOMPUTE || !g->wcc.valid || p.lost || (p.kinds & 2);
+  uint32_t* P = g->wcc_parent;
+  if (full) {
+    uint32_t* nh = &g->ctr->pad0[1];
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, nh, 1u);
+    hipLaunchKernelGGL(k_collect_heavy, dim3(blocks_for(N)), dim3(kBlock), 0, stream,
+                       g->view[VF].dir, N, g->fq[2], nh);
+    hipLaunchKernelGGL(k_wcc_init, dim3(blocks_for(N)), dim3(kBlock), 0, stream, P, N);
+    hipLaunchKernelGGL(k_wcc_all, dim3(kWalkBlocks), dim3(kBlock), 0, stream, g->view[VF].d, P, N,
+                       g->fq[2], nh);
+  } else {
+    for (const BatchRec* b : p.list)
+      hipLaunchKernelGGL(k_wcc_batch, dim3(blocks_for(b->n)), dim3(kBlock), 0, stream, P,
+                         log_at(g, b->off), b->n);
+  }
+  if (full || !p.list.empty())
+    hipLaunchKernelGGL(k_wcc_compress, dim3(blocks_for(N)), dim3(kBlock), 0, stream, P, N, d_label);
+  hipLaunchKernelGGL(k_copy_u32, dim3(blocks_for(N)), dim3(kBlock), 0, stream, P, d_label, N);
+  MK_LAUNCH(g, "wcc");
+  g->wcc.valid = true;
+  mark_seen(g, g->wcc);
+  return MK_OK;
+}
+
+mk_status mk_incr_pagerank(mk_graph* g, float damping, double tol_l1, uint32_t max_iter,
+                           float* d_rank, uint32_t* d_iters, mk_mode mode, hipStream_t stream) {
+  if (!g || !d_rank || !(damping >= 0.f && damping < 1.f) || max_iter == 0) return MK_ERR_INVALID_ARG;
+  if (!g->view[VR].on) return MK_ERR_STATE;
+  const uint32_t N = g->n;
+  Pending p = pending_for(g, g->pr);
+  const bool warm = mode != MK_RECOMPUTE && g->pr.valid && !p.lost;
+  if (warm && p.list.empty()) {
+    hipLaunchKernelGGL(k_pr_start, dim3(1), dim3(64), 0, stream, g->ctr);
+    hipLaunchKernelGGL(k_pr_final, dim3(blocks_for(N)), dim3(kBlock), 0, stream, g->ctr, g->pr_x,
+                       g->pr_y, g->pr_x, d_rank, N, d_iters);
+    MK_LAUNCH(g, "pagerank copy");
+    return MK_OK;
+  }
+  if (!warm)
+    hipLaunchKernelGGL(k_pr_fill, dim3(blocks_for(N)), dim3(kBlock), 0, stream, g->pr_x, N, 1.f / N);
+  uint32_t* nh = &g->ctr->pad0[2];
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, nh, 1u);
+  hipLaunchKernelGGL(k_collect_heavy, dim3(blocks_for(N)), dim3(kBlock), 0, stream, g->view[VR].dir,
+                     N, g->heavy_rev, nh);
+  hipLaunchKernelGGL(k_pr_start, dim3(1), dim3(64), 0, stream, g->ctr);
+  MK_LAUNCH(g, "pagerank setup");
+  float* buf[2] = {g->pr_x, g->pr_y};
+  uint32_t it = 0;
+  while (true) {
+    for (int k = 0; k < kPrSyncEvery; ++k, ++it) {
+      const int slot = it & 3;
+      const float* x = buf[it & 1];
+      float* y = buf[(it + 1) & 1];
+      hipLaunchKernelGGL(k_pr_contrib, dim3(blocks_for(N, 2048)), dim3(kBlock), 0, stream, x,
+                         g->view[VF].d.deg, g->pr_c, N, &g->ctr->pr_acc[2 * slot], g->ctr->pr_state);
+      hipLaunchKernelGGL(k_pr_gather, dim3(kWalkBlocks), dim3(kBlock), 0, stream, g->view[VR].d,
+                         g->pr_c, x, y, N, damping, &g->ctr->pr_acc[2 * slot],
+                         &g->ctr->pr_acc[2 * slot + 1], g->heavy_rev, nh, g->ctr->pr_state);
+      hipLaunchKernelGGL(k_pr_check, dim3(1), dim3(64), 0, stream, g->ctr, slot, tol_l1, max_iter);
+      MK_LAUNCH(g, "pagerank iteration");
+    }
+    MK_HIP(g, hipMemcpyAsync(g->h_pin, g->ctr->pr_state, 8, hipMemcpyDeviceToHost, stream));
+    MK_HIP(g, hipStreamSynchronize(stream));
+    if (reinterpret_cast<const uint32_t*>(g->h_pin)[0]) break;
+  }
+  hipLaunchKernelGGL(k_pr_final, dim3(blocks_for(N)), dim3(kBlock), 0, stream, g->ctr, g->pr_x,
+                     g->pr_y, g->pr_x, d_rank, N, d_iters);
+  MK_LAUNCH(g, "pagerank final");
+  g->pr.valid = true;
+  mark_seen(g, g->pr);
+  return MK_OK;
+}
+
+mk_status mk_count_triangles(mk_graph* g, uint64_t* d_count, mk_mode mode, hipStream_t stream) {
+  if (!g || !d_count) return MK_ERR_INVALID_ARG;
+  if (!g->view[VU].on) return MK_ERR_STATE;
+  const uint32_t N = g->n;
+  const DView U = g->view[VU].d;
+  Pending p = pending_for(g, g->tc);
+  const bool full = mode == MK_RECOMPUTE || !g->tc.valid || p.lost || p.kinds == 3;
+  unsigned long long* out = reinterpret_cast<unsigned long long*>(d_count);
+  if (full) {
+    uint32_t* nh = &g->ctr->pad0[3];
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, nh, 1u);
+    hipLaunchKernelGGL(k_collect_heavy, dim3(blocks_for(N)), dim3(kBlock), 0, stream, U.dir, N,
+                       g->fq[2], nh);
+    hipLaunchKernelGGL(k_tc_begin, dim3(1), dim3(64), 0, stream, g->ctr, true);
+    hipLaunchKernelGGL(k_tc_static, dim3(kWalkBlocks), dim3(kBlock), 0, stream, U, N, g->fq[2], nh,
+                       &g->ctr->u64tmp[0]);
+    hipLaunchKernelGGL(k_tc_finish, dim3(1), dim3(64), 0, stream, g->ctr, 2, out);
+  } else if (p.list.empty()) {
+    hipLaunchKernelGGL(k_tc_finish, dim3(1), dim3(64), 0, stream, g->ctr, 3, out);
+  } else {
+    // all pending batches are of one kind: their union is one effective batch
+    uint64_t nk = 0;
+    for (const BatchRec* b : p.list) {
+      hipLaunchKernelGGL(k_tc_keys, dim3(blocks_for(b->n)), dim3(kBlock), 0, stream,
+                         log_at(g, b->off), b->n, N, g->tc_keys[0] + nk);
+      nk += 2 * b->n;
+    }
+    if (nk > 2 * g->log_cap) return MK_ERR_CAPACITY;
+    unsigned end_bit = 32;
+    while (end_bit < 64 && ((uint64_t)N >> (end_bit - 32)) != 0) ++end_bit;
+    size_t tb = g->sort_tmp_bytes;
+    if (rocprim::radix_sort_keys(g->sort_tmp, tb, g->tc_keys[0], g->tc_keys[1], (size_t)nk, 0,
+                                 end_bit, stream) != hipSuccess)
+      return MK_ERR_HIP;
+    hipLaunchKernelGGL(k_tc_begin, dim3(1), dim3(64), 0, stream, g->ctr, false);
+    hipLaunchKernelGGL(k_tc_batch, dim3(grid_for_groups(std::min<uint64_t>(nk, 1u << 20))),
+                       dim3(kBlock), 0, stream, U, g->tc_keys[1], nk, N, g->ctr->tc_s);
+    hipLaunchKernelGGL(k_tc_finish, dim3(1), dim3(64), 0, stream, g->ctr,
+                       p.kinds == 1 ? 0 : 1, out);
+  }
+  MK_LAUNCH(g, "triangles");
+  g->tc.valid = true;
+  mark_seen(g, g->tc);
+  return MK_OK;
+}
+
+}  // extern "C"

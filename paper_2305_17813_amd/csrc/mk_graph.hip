@@ -1,0 +1,859 @@
+// Graph construction, batched updates and queries, export, statistics and self-check.
+//
+// Section 3.1 (memory management): every vertex gets bucket_count[v] head slabs from its
+// initial degree and the load factor; an exclusive scan of the bucket counts gives each
+// vertex's first head slab inside one contiguous head-slab region.  Chained slabs come
+// from a per-view pool behind a device bump counter (the SlabAlloc role of figure 1).
+// The graph-operation discussion of the experimental section fixes the semantics of
+// insert (store only if absent, at the end of the hashed chain, linking a new slab when
+// the chain is full), delete (flip the found lane to TOMBSTONE, stop when found) and
+// search (probe the hashed chain only).
+#include <cstring>
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
+
+#include <algorithm>
+#include <cstring>
+
+#include "mk_internal.h"
+
+using namespace mk;
+
+namespace mk {
+
+mk_status hip_fail(mk_graph* g, hipError_t e, const char* what) {
+  if (g) g->last_err = std::string(what) + ": " + hipGetErrorString(e);
+  return MK_ERR_HIP;
+}
+
+Pending pending_for(const mk_graph* g, const AlgoState& st) {
+  Pending p;
+  if (st.seen_seq < g->dropped_seq) p.lost = true;
+  for (const auto& b : g->batches)
+    if (b.seq > st.seen_seq) {
+      p.list.push_back(&b);
+      p.kinds |= (b.kind == kInsertBatch) ? 1 : 2;
+    }
+  return p;
+}
+
+void mark_seen(mk_graph* g, AlgoState& st) { st.seen_seq = g->next_seq - 1; }
+
+}  // namespace mk
+
+// ============================================================ device: updates
+namespace {
+
+// Insert <key, w> into u's table.  Returns 1 inserted, 0 already present, 3 pool empty.
+// Progress never depends on a load being fresh: every failed CAS returns the word's true
+// value, and `floor` (lanes of this slab known to be filled) only grows, so a slab is
+// retried at most 15 times.
+__device__ int insert_key(const DView& V, uint32_t u, uint32_t key, uint32_t w) {
+  const uint2 de = V.dir[u];
+  uint32_t s = de.x + bucket_of(key, de.y, V.hash_a, V.hash_b);
+  const uint64_t mine = ((uint64_t)w << 32) | key;
+  const int gl = glane();
+  uint32_t spare = kInvalid;
+  int floor = 0;
+  while (true) {
+    uint64_t* sp = slab_ptr(V, s);
+    const uint64_t x = ld_word<true>(sp + gl);
+    const uint32_t k = (uint32_t)x;
+    if (gballot(gl < kKeysPerSlab && k == key)) return 0;
+    const uint32_t em = gballot(gl < kKeysPerSlab && gl >= floor && k == kEmptyKey);
+    if (em) {
+      // the lowest EMPTY lane of the chain: claim it, or learn who did
+      const int e = __builtin_ctz(em);
+      uint64_t old = 0;
+      if (gl == e) old = cas64(sp + e, kEmptyWord, mine);
+      old = gbcast64(old, e);
+      if (old == kEmptyWord) return 1;
+      if ((uint32_t)old == key) return 0;
+      floor = e + 1;  // another key took the lane: look at the rest of this slab again
+      continue;
+    }
+    const uint64_t link = gbcast64(x, 15);
+    if ((uint32_t)link != kInvalid) {
+      s = (uint32_t)link;
+      floor = 0;
+      continue;
+    }
+    // Full tail: fill a fresh slab with the key in lane 0, publish it, then link it.
+    if (spare == kInvalid) {
+      uint32_t got = 0;
+      if (gl == 0) got = atomicAdd(V.pool_ctr, 1u);
+      got = gbcast(got, 0);
+      if (got >= V.pool_cap) return 3;
+      spare = V.pool_base + got;
+    }
+    uint64_t* np = slab_ptr(V, spare);
+    __hip_atomic_store(np + gl, gl == 0 ? mine : (gl == 15 ? kNextNone : kEmptyWord),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    uint64_t old = 0;
+    if (gl == 15) old = cas64(sp + 15, kNextNone, (kNextNone & 0xFFFFFFFF00000000ull) | spare);
+    old = gbcast64(old, 15);
+    if (old == kNextNone) return 1;
+    s = (uint32_t)old;  // lost the race: continue in the winner's slab, keep the spare
+    floor = 0;
+  }
+}
+
+// Delete key from u's table.  Returns 1 deleted, 0 absent; *w_out gets the weight.
+__device__ int delete_key(const DView& V, uint32_t u, uint32_t key, uint32_t* w_out) {
+  const uint2 de = V.dir[u];
+  uint32_t s = de.x + bucket_of(key, de.y, V.hash_a, V.hash_b);
+  const int gl = glane();
+  while (true) {
+    uint64_t* sp = slab_ptr(V, s);
+    const uint64_t x = ld_word<true>(sp + gl);
+    const uint32_t k = (uint32_t)x;
+    const uint32_t hit = gballot(gl < kKeysPerSlab && k == key);
+    if (hit) {
+      const int e = __builtin_ctz(hit);
+      uint64_t old = 0;
+      if (gl == e) old = cas64(sp + e, x, kTombWord);
+      const uint64_t seen = gbcast64(x, e);
+      old = gbcast64(old, e);
+      *w_out = (uint32_t)(seen >> 32);
+      return old == seen ? 1 : 0;
+    }
+    if (gballot(gl < kKeysPerSlab && k == kEmptyKey)) return 0;
+    s = gbcast(k, 15);
+    if (s == kInvalid) return 0;
+  }
+}
+
+__device__ inline bool bad_arc(uint32_t s, uint32_t d, uint32_t nv) {
+  return s >= nv || d >= nv || s == d;  // nv <= 2^30, so reserved ids are >= nv
+}
+
+__global__ void __launch_bounds__(kBlock) k_insert(DView F, DView R, DView U, uint32_t views,
+                                                   const uint32_t* __restrict__ src,
+                                                   const uint32_t* __restrict__ dst,
+                                                   const uint32_t* __restrict__ w, uint64_t n,
+                                                   uint32_t nv, uint8_t* status, Log log,
+                                                   uint32_t* overflow) {
+  const uint64_t op = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kGroup;
+  if (op >= n) return;
+  const uint32_t s = src[op], d = dst[op];
+  const uint32_t wt = w ? w[op] : 1u;
+  int st;
+  uint8_t uf = 0;
+  const bool lead = glane() == 0;
+  if (bad_arc(s, d, nv)) {
+    st = 2;
+  } else {
+    st = insert_key(F, s, d, wt);
+    if (st == 1) {
+      if (lead) atomicAdd(F.deg + s, 1u);
+      if (views & MK_VIEW_REV) {
+        const int r = insert_key(R, d, s, wt);
+        if (r == 1 && lead) atomicAdd(R.deg + d, 1u);
+        if (r == 3 && lead) atomicOr(overflow, 2u);
+      }
+      if (views & MK_VIEW_UND) {
+        const uint32_t a = min(s, d), b = max(s, d);
+        const int r1 = insert_key(U, a, b, 1u);  // the canonical direction decides who logs
+        const int r2 = insert_key(U, b, a, 1u);
+        uf = r1 == 1;
+        if (lead) {
+          if (r1 == 1) atomicAdd(U.deg + a, 1u);
+          if (r2 == 1) atomicAdd(U.deg + b, 1u);
+          if (r1 == 3 || r2 == 3) atomicOr(overflow, 4u);
+        }
+      }
+    } else if (st == 3) {
+      if (lead) atomicOr(overflow, 1u);
+    }
+  }
+  if (lead) {
+    if (status) status[op] = (uint8_t)st;
+    if (log.s) {
+      log.s[op] = s;
+      log.d[op] = d;
+      log.w[op] = wt;
+      log.st[op] = (uint8_t)st;
+      log.uf[op] = uf;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_delete(DView F, DView R, uint32_t views,
+                                                   const uint32_t* __restrict__ src,
+                                                   const uint32_t* __restrict__ dst, uint64_t n,
+                                                   uint32_t nv, uint8_t* status, Log log) {
+  const uint64_t op = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kGroup;
+  if (op >= n) return;
+  const uint32_t s = src[op], d = dst[op];
+  int st;
+  uint32_t wt = 0;
+  const bool lead = glane() == 0;
+  if (bad_arc(s, d, nv)) {
+    st = 2;
+  } else {
+    st = delete_key(F, s, d, &wt);
+    if (st == 1) {
+      if (lead) atomicSub(F.deg + s, 1u);
+      if (views & MK_VIEW_REV) {
+        uint32_t w2;
+        if (delete_key(R, d, s, &w2) == 1 && lead) atomicSub(R.deg + d, 1u);
+      }
+    }
+  }
+  if (lead) {
+    if (status) status[op] = (uint8_t)st;
+    if (log.s) {
+      log.s[op] = s;
+      log.d[op] = d;
+      log.w[op] = wt;
+      log.st[op] = (uint8_t)st;
+      log.uf[op] = 0;
+    }
+  }
+}
+
+// Second pass of a delete batch on the undirected view: {u,v} goes only if the reverse
+// arc is absent once the whole batch has been applied to the forward view.
+__global__ void __launch_bounds__(kBlock) k_delete_und(DView F, DView U, uint64_t n, Log log) {
+  const uint64_t op = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kGroup;
+  if (op >= n) return;
+  if (log.st[op] != 1) return;
+  const uint32_t s = log.s[op], d = log.d[op];
+  if (probe<false>(F, d, s) != kEmptyWord) return;
+  const uint32_t a = min(s, d), b = max(s, d);
+  uint32_t w;
+  const int r1 = delete_key(U, a, b, &w);
+  const int r2 = delete_key(U, b, a, &w);
+  if (glane() == 0) {
+    if (r1 == 1) atomicSub(U.deg + a, 1u);
+    if (r2 == 1) atomicSub(U.deg + b, 1u);
+    log.uf[op] = r1 == 1;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_query(DView F, const uint32_t* __restrict__ src,
+                                                  const uint32_t* __restrict__ dst, uint64_t n,
+                                                  uint32_t nv, uint8_t* __restrict__ found,
+                                                  uint32_t* __restrict__ wout) {
+  const uint64_t op = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kGroup;
+  if (op >= n) return;
+  const uint32_t s = src[op], d = dst[op];
+  uint64_t x = kEmptyWord;
+  if (!bad_arc(s, d, nv)) x = probe<false>(F, s, d);
+  if (glane() == 0) {
+    const bool f = x != kEmptyWord;
+    found[op] = f;
+    if (wout) wout[op] = f ? (uint32_t)(x >> 32) : 0u;
+  }
+}
+
+// ============================================================ device: build
+__global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_fill_slabs(uint64_t* words, uint64_t n_words) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_words;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    words[i] = (i & 15) == 15 ? kNextNone : kEmptyWord;
+}
+
+__global__ void k_count_deg(const uint32_t* __restrict__ src, const uint32_t* __restrict__ dst,
+                            uint64_t m, uint32_t nv, uint32_t* cf, uint32_t* cr, uint32_t* cu) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t s = src[i], d = dst[i];
+    if (bad_arc(s, d, nv)) continue;
+    atomicAdd(cf + s, 1u);
+    if (cr) atomicAdd(cr + d, 1u);
+    if (cu) {
+      atomicAdd(cu + s, 1u);
+      atomicAdd(cu + d, 1u);
+    }
+  }
+}
+
+// bucket_count[v] = max(1, ceil(deg0(v) / (load_factor * 15))), 1 when hashing is off.
+__global__ void k_plan(const uint32_t* cnt, uint32_t nv, float keys_per_bucket, uint32_t* nb) {
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
+    uint32_t b = 1;
+    if (keys_per_bucket > 0.f) b = max(1u, (uint32_t)ceilf((float)cnt[v] / keys_per_bucket));
+    nb[v] = b;
+  }
+}
+
+__global__ void k_pack_dir(const uint32_t* base, const uint32_t* nb, uint32_t nv, uint2* dir,
+                           unsigned long long* total) {
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
+    dir[v] = make_uint2(base[v], nb[v]);
+    if (v == nv - 1) *total = (unsigned long long)base[v] + nb[v];
+  }
+}
+
+// ============================================================ device: export / stats / check
+__global__ void __launch_bounds__(kBlock) k_export(DView F, uint32_t nv, uint32_t* os, uint32_t* od,
+                                                   uint32_t* ow, unsigned long long cap,
+                                                   unsigned long long* count) {
+  const uint64_t g0 = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kGroup;
+  const uint64_t ng = (uint64_t)gridDim.x * kGroupsPerBlock;
+  for (uint64_t v = g0; v < nv; v += ng) {
+    for_each_slab<false>(F, (uint32_t)v, [&](uint64_t x) {
+      const uint32_t k = (uint32_t)x;
+      const bool p = glane() < kKeysPerSlab && valid_key(k);
+      const uint64_t m = __ballot(p);
+      if (m == 0) return;
+      const int leader = __builtin_ctzll(m);
+      unsigned long long base = 0;
+      if (lane64() == leader) base = atomicAdd(count, (unsigned long long)__popcll(m));
+      base = __shfl(base, leader);
+      const unsigned long long at = base + lanes_below(m);
+      if (p && at < cap) {
+        os[at] = (uint32_t)v;
+        od[at] = k;
+        if (ow) ow[at] = (uint32_t)(x >> 32);
+      }
+    });
+  }
+}
+
+__global__ void k_sum_u32(const uint32_t* a, uint32_t n, unsigned long long* out) {
+  unsigned long long acc = 0;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    acc += a[i];
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if (lane64() == 0 && acc) atomicAdd(out, acc);
+}
+
+// One group per vertex: audit every chain of the vertex's table.
+__global__ void __launch_bounds__(kBlock) k_check(DView V, uint32_t nv, uint32_t pool_used,
+                                                  unsigned long long* bad) {
+  const uint64_t g0 = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kGroup;
+  const uint64_t ng = (uint64_t)gridDim.x * kGroupsPerBlock;
+  const int gl = glane();
+  for (uint64_t vv = g0; vv < nv; vv += ng) {
+    const uint32_t v = (uint32_t)vv;
+    const uint2 de = V.dir[v];
+    uint32_t live = 0, errs = 0;
+    for (uint32_t b = 0; b < de.y; ++b) {
+      bool seen_empty = false;
+      uint32_t s = de.x + b, hops = 0;
+      while (s != kInvalid) {
+        if (++hops > (1u << 24)) { errs++; break; }  // a cycle
+        const uint64_t x = slab_ptr(V, s)[gl];
+        const uint32_t k = (uint32_t)x;
+        const bool data = gl < kKeysPerSlab;
+        const bool isv = data && valid_key(k);
+        // prefix rule: no filled lane after an EMPTY lane in chain order
+        const uint32_t em = gballot(data && k == kEmptyKey);
+        const uint32_t filled = gballot(data && k != kEmptyKey);
+        if (seen_empty && filled) errs++;
+        if (em) {
+          const uint32_t first_empty = __builtin_ctz(em);
+          if (filled >> first_empty) errs++;
+          seen_empty = true;
+        }
+        if (data && !isv && k != kEmptyKey && x != kTombWord) errs += gl == 0 ? 1 : 0;
+        if (isv && bucket_of(k, de.y, V.hash_a, V.hash_b) != b) errs++;
+        // duplicates: count this lane's key over the whole chain
+        if (isv) {
+          uint32_t occ = 0;
+          uint32_t t = de.x + b, hops2 = 0;
+          while (t != kInvalid && ++hops2 < (1u << 24)) {
+            const uint64_t* tp = slab_ptr(V, t);
+            for (int j = 0; j < kKeysPerSlab; ++j) occ += (uint32_t)tp[j] == k;
+            t = (uint32_t)tp[15];
+            if (t != kInvalid && (t < V.pool_base || t >= V.pool_base + pool_used)) break;
+          }
+          if (occ != 1) errs++;
+        }
+        live += __popc(gballot(isv));
+        const uint32_t nx = gbcast(k, 15);
+        if (nx != kInvalid && (nx < V.pool_base || nx >= V.pool_base + pool_used)) {
+          if (gl == 0) errs++;
+          break;
+        }
+        if (em && nx != kInvalid && gl == 0) errs++;  // an EMPTY lane is only in the tail
+        s = nx;
+      }
+    }
+    for (int o = 8; o > 0; o >>= 1) errs += __shfl_xor(errs, o, kGroup);
+    if (gl == 0) {
+      if (live != V.deg[v]) errs++;
+      if (errs) atomicAdd(bad, (unsigned long long)errs);
+    }
+  }
+}
+
+
+// Byte model: slabs one probe walks (op 0: until found / first EMPTY / end; op 1: to the
+// end of the chain unless the key is found first).
+__device__ inline uint32_t walk_cost(const DView& V, uint32_t u, uint32_t key, int op) {
+  const uint2 de = V.dir[u];
+  uint32_t s = de.x + bucket_of(key, de.y, V.hash_a, V.hash_b);
+  const int gl = glane();
+  uint32_t slabs = 0;
+  while (true) {
+    const uint64_t x = slab_ptr(V, s)[gl];
+    const uint32_t k = (uint32_t)x;
+    ++slabs;
+    if (gballot(gl < kKeysPerSlab && k == key)) return slabs;
+    if (gballot(gl < kKeysPerSlab && k == kEmptyKey)) return slabs;
+    s = gbcast(k, 15);
+    if (s == kInvalid) return slabs;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_probe_cost(DView V, int op, int view,
+                                                       const uint32_t* __restrict__ src,
+                                                       const uint32_t* __restrict__ dst, uint64_t n,
+                                                       uint32_t nv, unsigned long long* acc) {
+  const uint64_t i = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kGroup;
+  if (i >= n) return;
+  const uint32_t s = src[i], d = dst[i];
+  if (bad_arc(s, d, nv)) return;
+  uint32_t c;
+  if (view == 0) c = walk_cost(V, s, d, op);
+  else if (view == 1) c = walk_cost(V, d, s, op);
+  else c = walk_cost(V, s, d, op) + walk_cost(V, d, s, op);
+  if (glane() == 0) atomicAdd(acc, (unsigned long long)c);
+}
+
+inline uint32_t grid_stride_blocks(uint64_t n, uint32_t cap = 8192) {
+  uint64_t b = (n + kBlock - 1) / kBlock;
+  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(b, cap));
+}
+
+// ============================================================ host: arena layout
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+bool config_ok(const mk_config* c) {
+  return c && c->n_vertices >= 1 && c->n_vertices <= (1u << 30) && c->load_factor >= 0.f &&
+         c->load_factor <= 64.f;
+}
+
+uint64_t view_arcs(int v, uint64_t m) { return v == VU ? 2 * m : m; }
+
+uint64_t head_bound(const mk_config* c, uint64_t arcs) {
+  if (c->load_factor <= 0.f) return c->n_vertices;
+  const double per = (double)c->load_factor * kKeysPerSlab;
+  return (uint64_t)c->n_vertices + (uint64_t)std::ceil((double)arcs / per) + 1;
+}
+
+uint64_t pool_default(const mk_config* c, uint64_t arcs) {
+  if (c->pool_slabs) return c->pool_slabs;
+  uint64_t headroom = std::max<uint64_t>(65536, std::min<uint64_t>(1ull << 22, arcs / 2));
+  return (arcs + kKeysPerSlab - 1) / kKeysPerSlab + headroom;
+}
+
+uint64_t log_default(const mk_config* c, uint64_t m) {
+  if (c->log_capacity) return c->log_capacity;
+  return std::max<uint64_t>(1ull << 21, m / 8);
+}
+
+// Carve (or, with base == nullptr, just measure) every region of the arena.
+bool layout(const mk_config* c, uint64_t m, char* base, mk_graph* g, size_t* total) {
+  Carver cv{base};
+  const uint32_t N = c->n_vertices;
+  const uint32_t views = c->views | MK_VIEW_FWD;
+  for (int v = 0; v < 3; ++v) {
+    const bool on = views & (1u << v);
+    if (!on) continue;
+    const uint64_t arcs = view_arcs(v, m);
+    const uint64_t hb = head_bound(c, arcs), pc = pool_default(c, arcs);
+    if (hb + pc >= 0xFFFFFFF0ull) return false;  // slab indices are u32
+    uint64_t* slab = cv.take<uint64_t>((hb + pc) * kGroup);
+    uint2* dir = cv.take<uint2>(N);
+    uint32_t* deg = cv.take<uint32_t>(N);
+    uint32_t* pctr = cv.take<uint32_t>(64);
+    if (g) {
+      ViewHost& vh = g->view[v];
+      vh.on = true;
+      vh.dir = dir;
+      vh.head_reserved = hb;
+      vh.pool_cap = pc;
+      vh.d.dir = dir;
+      vh.d.slab = slab;
+      vh.d.deg = deg;
+      vh.d.pool_ctr = pctr;
+      vh.d.pool_cap = (uint32_t)pc;
+    }
+  }
+  const uint64_t L = log_default(c, m);
+  Log lg;
+  lg.s = cv.take<uint32_t>(L);
+  lg.d = cv.take<uint32_t>(L);
+  lg.w = cv.take<uint32_t>(L);
+  lg.st = cv.take<uint8_t>(L);
+  lg.uf = cv.take<uint8_t>(L);
+  Counters* ctr = cv.take<Counters>(1);
+  uint32_t* fq[4];
+  for (auto& q : fq) q = cv.take<uint32_t>(N);
+  uint32_t* mark = cv.take<uint32_t>(N);
+  uint32_t* inval = cv.take<uint32_t>(N);
+  uint64_t* bfsD = cv.take<uint64_t>(N);
+  uint64_t* ssspD = cv.take<uint64_t>(N);
+  uint32_t* par = cv.take<uint32_t>(N);
+  float* px = cv.take<float>(N);
+  float* py = cv.take<float>(N);
+  float* pc = cv.take<float>(N);
+  uint32_t* hv = cv.take<uint32_t>(N);
+  uint64_t* tk0 = nullptr;
+  uint64_t* tk1 = nullptr;
+  size_t sort_bytes = 0, scan_bytes = 0;
+  if (views & MK_VIEW_UND) {
+    tk0 = cv.take<uint64_t>(2 * L);
+    tk1 = cv.take<uint64_t>(2 * L);
+    if (rocprim::radix_sort_keys(nullptr, sort_bytes, (uint64_t*)nullptr, (uint64_t*)nullptr,
+                                 (size_t)(2 * L), 0, 64) != hipSuccess)
+      return false;
+  }
+  void* sort_tmp = cv.take<char>(sort_bytes + 256);
+  if (rocprim::exclusive_scan(nullptr, scan_bytes, (uint32_t*)nullptr, (uint32_t*)nullptr, 0u,
+                              (size_t)N, rocprim::plus<uint32_t>()) != hipSuccess)
+    return false;
+  void* scan_tmp = cv.take<char>(scan_bytes + 256);
+  if (g) {
+    g->log = lg;
+    g->log_cap = L;
+    g->ctr = ctr;
+    for (int i = 0; i < 4; ++i) g->fq[i] = fq[i];
+    g->mark = mark;
+    g->inval = inval;
+    g->bfs_D = bfsD;
+    g->sssp_D = ssspD;
+    g->wcc_parent = par;
+    g->pr_x = px;
+    g->pr_y = py;
+    g->pr_c = pc;
+    g->heavy_rev = hv;
+    g->tc_keys[0] = tk0;
+    g->tc_keys[1] = tk1;
+    g->sort_tmp = sort_tmp;
+    g->sort_tmp_bytes = sort_bytes;
+    g->scan_tmp = scan_tmp;
+    g->scan_tmp_bytes = scan_bytes;
+  }
+  *total = cv.off + 256;
+  return true;
+}
+
+uint64_t hash_const(uint32_t seed, uint64_t salt) {
+  uint64_t z = ((uint64_t)seed << 1) + salt;  // SplitMix64 finaliser as a seed mixer
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+mk_status refresh_pool(mk_graph* g, hipStream_t stream) {
+  for (int v = 0; v < 3; ++v)
+    if (g->view[v].on)
+      MK_HIP(g, hipMemcpyAsync(g->h_pin + v, g->view[v].d.pool_ctr, sizeof(uint32_t),
+                               hipMemcpyDeviceToHost, stream));
+  MK_HIP(g, hipStreamSynchronize(stream));
+  for (int v = 0; v < 3; ++v)
+    if (g->view[v].on)
+      g->view[v].pool_used_est = std::min<uint64_t>((uint32_t)g->h_pin[v], g->view[v].pool_cap);
+  return MK_OK;
+}
+
+// Make sure every enabled view's pool can take `n` more inserts (at most one new slab per
+// arc and view; two for the undirected view).
+mk_status ensure_pool(mk_graph* g, uint64_t n, hipStream_t stream) {
+  auto fits = [&]() {
+    for (int v = 0; v < 3; ++v) {
+      const ViewHost& vh = g->view[v];
+      if (!vh.on) continue;
+      const uint64_t need = v == VU ? 2 * n : n;
+      if (vh.pool_used_est + need > vh.pool_cap) return false;
+    }
+    return true;
+  };
+  if (fits()) return MK_OK;
+  mk_status st = refresh_pool(g, stream);
+  if (st != MK_OK) return st;
+  return fits() ? MK_OK : MK_ERR_OUT_OF_SLABS;
+}
+
+// Reserve n log entries for a new batch, dropping the oldest batches it overwrites.
+uint64_t reserve_log(mk_graph* g, uint64_t n) {
+  if (g->log_tail + n > g->log_cap) g->log_tail = 0;
+  const uint64_t lo = g->log_tail, hi = lo + n;
+  while (!g->batches.empty()) {
+    const BatchRec& b = g->batches.front();
+    const bool overlap = b.off < hi && lo < b.off + b.n;
+    bool later_overlap = false;
+    for (const auto& o : g->batches)
+      if (o.off < hi && lo < o.off + o.n) later_overlap = true;
+    if (!overlap && !later_overlap) break;
+    g->dropped_seq = b.seq;
+    g->batches.pop_front();
+  }
+  return lo;
+}
+
+Log log_at(const mk_graph* g, uint64_t off) {
+  Log l = g->log;
+  l.s += off;
+  l.d += off;
+  l.w += off;
+  l.st += off;
+  l.uf += off;
+  return l;
+}
+
+DView dv(const mk_graph* g, int v) { return g->view[v].on ? g->view[v].d : g->view[VF].d; }
+
+}  // namespace
+
+// ============================================================ C-ABI
+extern "C" {
+
+size_t mk_arena_bytes(const mk_config* cfg, uint64_t n_edges_hint) {
+  if (!config_ok(cfg)) return 0;
+  size_t total = 0;
+  if (!layout(cfg, n_edges_hint, nullptr, nullptr, &total)) return 0;
+  return total;
+}
+
+mk_status mk_graph_create(const mk_config* cfg, void* d_arena, size_t arena_bytes,
+                          const uint32_t* d_src, const uint32_t* d_dst, const uint32_t* d_w,
+                          uint64_t m, hipStream_t stream, mk_graph** out) {
+  if (!out || !config_ok(cfg) || !d_arena || ((uintptr_t)d_arena & 255)) return MK_ERR_INVALID_ARG;
+  if (m && (!d_src || !d_dst)) return MK_ERR_INVALID_ARG;
+  *out = nullptr;
+  size_t need = 0;
+  if (!layout(cfg, m, nullptr, nullptr, &need)) return MK_ERR_INVALID_ARG;
+  if (arena_bytes < need) return MK_ERR_CAPACITY;
+  mk_graph* g = new mk_graph();
+  g->cfg = *cfg;
+  g->cfg.views |= MK_VIEW_FWD;
+  g->n = cfg->n_vertices;
+  g->arena = (char*)d_arena;
+  g->arena_bytes = arena_bytes;
+  layout(&g->cfg, m, g->arena, g, &g->used);
+  auto fail = [&](mk_status s) {
+    if (g->h_pin) (void)hipHostFree(g->h_pin);
+    delete g;
+    return s;
+  };
+  if (hipHostMalloc((void**)&g->h_pin, 64 * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess)
+    return fail(MK_ERR_HIP);
+  const uint32_t N = g->n;
+  const uint32_t nb_blocks = grid_stride_blocks(N);
+  for (int v = 0; v < 3; ++v) {
+    ViewHost& vh = g->view[v];
+    if (!vh.on) continue;
+    vh.d.hash_a = hash_const(cfg->hash_seed, 0x1000 + v) | 1ull;
+    vh.d.hash_b = hash_const(cfg->hash_seed, 0x2000 + v);
+    hipLaunchKernelGGL(k_fill_u32, dim3(nb_blocks), dim3(kBlock), 0, stream, vh.d.deg, N, 0u);
+  }
+  (void)hipMemsetAsync(g->ctr, 0, sizeof(Counters), stream);
+  if (m)
+    hipLaunchKernelGGL(k_count_deg, dim3(grid_stride_blocks(m)), dim3(kBlock), 0, stream, d_src,
+                       d_dst, m, N, g->view[VF].d.deg, g->view[VR].on ? g->view[VR].d.deg : nullptr,
+                       g->view[VU].on ? g->view[VU].d.deg : nullptr);
+  const float kpb = cfg->load_factor > 0.f ? cfg->load_factor * kKeysPerSlab : 0.f;
+  for (int v = 0; v < 3; ++v) {
+    ViewHost& vh = g->view[v];
+    if (!vh.on) continue;
+    hipLaunchKernelGGL(k_plan, dim3(nb_blocks), dim3(kBlock), 0, stream, vh.d.deg, N, kpb, g->fq[0]);
+    size_t tb = g->scan_tmp_bytes;
+    if (rocprim::exclusive_scan(g->scan_tmp, tb, g->fq[0], g->fq[1], 0u, (size_t)N,
+                                rocprim::plus<uint32_t>(), stream) != hipSuccess)
+      return fail(MK_ERR_HIP);
+    hipLaunchKernelGGL(k_pack_dir, dim3(nb_blocks), dim3(kBlock), 0, stream, g->fq[1], g->fq[0], N,
+                       vh.dir, &g->ctr->u64tmp[v]);
+  }
+  if (hipMemcpyAsync(g->h_pin, g->ctr->u64tmp, 3 * sizeof(uint64_t), hipMemcpyDeviceToHost,
+                     stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess)
+    return fail(MK_ERR_HIP);
+  for (int v = 0; v < 3; ++v) {
+    ViewHost& vh = g->view[v];
+    if (!vh.on) continue;
+    vh.n_head = g->h_pin[v];
+    if (vh.n_head > vh.head_reserved) return fail(MK_ERR_CAPACITY);
+    vh.d.pool_base = (uint32_t)vh.n_head;
+    hipLaunchKernelGGL(k_fill_slabs, dim3(grid_stride_blocks((vh.n_head + vh.pool_cap) * kGroup)),
+                       dim3(kBlock), 0, stream, vh.d.slab, (vh.n_head + vh.pool_cap) * kGroup);
+    hipLaunchKernelGGL(k_fill_u32, dim3(nb_blocks), dim3(kBlock), 0, stream, vh.d.deg, N, 0u);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, stream, vh.d.pool_ctr, 64, 0u);
+  }
+  hipLaunchKernelGGL(k_fill_u32, dim3(nb_blocks), dim3(kBlock), 0, stream, g->mark, N, 0u);
+  if (m) {
+    hipLaunchKernelGGL(k_insert, dim3(grid_for_groups(m)), dim3(kBlock), 0, stream, dv(g, VF),
+                       dv(g, VR), dv(g, VU), g->cfg.views, d_src, d_dst, d_w, m, N, nullptr, Log{},
+                       &g->ctr->pad0[0]);
+  }
+  if (hipGetLastError() != hipSuccess) return fail(MK_ERR_HIP);
+  if (refresh_pool(g, stream) != MK_OK) return fail(MK_ERR_HIP);
+  *out = g;
+  return MK_OK;
+}
+
+mk_status mk_graph_destroy(mk_graph* g) {
+  if (!g) return MK_OK;
+  if (g->h_pin) (void)hipHostFree(g->h_pin);
+  delete g;
+  return MK_OK;
+}
+
+mk_status mk_insert_edges(mk_graph* g, const uint32_t* d_src, const uint32_t* d_dst,
+                          const uint32_t* d_w, uint64_t n, uint8_t* d_status, hipStream_t stream) {
+  if (!g) return MK_ERR_INVALID_ARG;
+  if (n == 0) return MK_OK;
+  if (!d_src || !d_dst) return MK_ERR_INVALID_ARG;
+  if (n > g->log_cap) return MK_ERR_CAPACITY;
+  mk_status st = ensure_pool(g, n, stream);
+  if (st != MK_OK) return st;
+  const uint64_t off = reserve_log(g, n);
+  hipLaunchKernelGGL(k_insert, dim3(grid_for_groups(n)), dim3(kBlock), 0, stream, dv(g, VF),
+                     dv(g, VR), dv(g, VU), g->cfg.views, d_src, d_dst, d_w, n, g->n, d_status,
+                     log_at(g, off), &g->ctr->pad0[0]);
+  MK_LAUNCH(g, "k_insert");
+  for (int v = 0; v < 3; ++v)
+    if (g->view[v].on) g->view[v].pool_used_est += v == VU ? 2 * n : n;
+  g->batches.push_back(BatchRec{kInsertBatch, off, n, g->next_seq++});
+  g->log_tail = off + n;
+  g->batches_applied++;
+  return MK_OK;
+}
+
+mk_status mk_delete_edges(mk_graph* g, const uint32_t* d_src, const uint32_t* d_dst, uint64_t n,
+                          uint8_t* d_status, hipStream_t stream) {
+  if (!g) return MK_ERR_INVALID_ARG;
+  if (n == 0) return MK_OK;
+  if (!d_src || !d_dst) return MK_ERR_INVALID_ARG;
+  if (n > g->log_cap) return MK_ERR_CAPACITY;
+  const uint64_t off = reserve_log(g, n);
+  const Log lg = log_at(g, off);
+  hipLaunchKernelGGL(k_delete, dim3(grid_for_groups(n)), dim3(kBlock), 0, stream, dv(g, VF),
+                     dv(g, VR), g->cfg.views, d_src, d_dst, n, g->n, d_status, lg);
+  MK_LAUNCH(g, "k_delete");
+  if (g->view[VU].on) {
+    hipLaunchKernelGGL(k_delete_und, dim3(grid_for_groups(n)), dim3(kBlock), 0, stream, dv(g, VF),
+                       dv(g, VU), n, lg);
+    MK_LAUNCH(g, "k_delete_und");
+  }
+  g->batches.push_back(BatchRec{kDeleteBatch, off, n, g->next_seq++});
+  g->log_tail = off + n;
+  g->batches_applied++;
+  return MK_OK;
+}
+
+mk_status mk_query_edges(mk_graph* g, const uint32_t* d_src, const uint32_t* d_dst, uint64_t n,
+                         uint8_t* d_found, uint32_t* d_w, hipStream_t stream) {
+  if (!g) return MK_ERR_INVALID_ARG;
+  if (n == 0) return MK_OK;
+  if (!d_src || !d_dst || !d_found) return MK_ERR_INVALID_ARG;
+  hipLaunchKernelGGL(k_query, dim3(grid_for_groups(n)), dim3(kBlock), 0, stream, dv(g, VF), d_src,
+                     d_dst, n, g->n, d_found, d_w);
+  MK_LAUNCH(g, "k_query");
+  return MK_OK;
+}
+
+mk_status mk_graph_export(mk_graph* g, uint32_t* d_src, uint32_t* d_dst, uint32_t* d_w,
+                          uint64_t cap, uint64_t* h_count, hipStream_t stream) {
+  if (!g || !h_count || (cap && (!d_src || !d_dst))) return MK_ERR_INVALID_ARG;
+  unsigned long long* cnt = &g->ctr->u64tmp[3];
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, stream, (uint32_t*)cnt, 2, 0u);
+  hipLaunchKernelGGL(k_export, dim3(grid_for_groups(std::min<uint64_t>(g->n, 1u << 20))),
+                     dim3(kBlock), 0, stream, dv(g, VF), g->n, d_src, d_dst, d_w,
+                     (unsigned long long)cap, cnt);
+  MK_LAUNCH(g, "k_export");
+  MK_HIP(g, hipMemcpyAsync(g->h_pin, cnt, 8, hipMemcpyDeviceToHost, stream));
+  MK_HIP(g, hipStreamSynchronize(stream));
+  *h_count = g->h_pin[0];
+  return g->h_pin[0] > cap ? MK_ERR_CAPACITY : MK_OK;
+}
+
+mk_status mk_graph_stats(mk_graph* g, mk_stats* h_out, hipStream_t stream) {
+  if (!g || !h_out) return MK_ERR_INVALID_ARG;
+  std::memset(h_out, 0, sizeof(*h_out));
+  unsigned long long* acc = &g->ctr->u64tmp[0];
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, stream, (uint32_t*)acc, 4, 0u);
+  hipLaunchKernelGGL(k_sum_u32, dim3(grid_stride_blocks(g->n, 1024)), dim3(kBlock), 0, stream,
+                     g->view[VF].d.deg, g->n, acc);
+  if (g->view[VU].on)
+    hipLaunchKernelGGL(k_sum_u32, dim3(grid_stride_blocks(g->n, 1024)), dim3(kBlock), 0, stream,
+                       g->view[VU].d.deg, g->n, acc + 1);
+  MK_LAUNCH(g, "k_sum_u32");
+  MK_HIP(g, hipMemcpyAsync(g->h_pin + 8, acc, 16, hipMemcpyDeviceToHost, stream));
+  mk_status st = refresh_pool(g, stream);
+  if (st != MK_OK) return st;
+  h_out->n_arcs = g->h_pin[8];
+  h_out->n_und_edges = g->h_pin[9] / 2;
+  for (int v = 0; v < 3; ++v) {
+    if (!g->view[v].on) continue;
+    h_out->head_slabs[v] = g->view[v].n_head;
+    h_out->pool_used[v] = g->view[v].pool_used_est;
+    h_out->pool_capacity[v] = g->view[v].pool_cap;
+  }
+  h_out->arena_bytes_used = g->used;
+  h_out->batches_applied = g->batches_applied;
+  return MK_OK;
+}
+
+mk_status mk_graph_check(mk_graph* g, uint64_t* h_bad, hipStream_t stream) {
+  if (!g || !h_bad) return MK_ERR_INVALID_ARG;
+  mk_status st = refresh_pool(g, stream);
+  if (st != MK_OK) return st;
+  unsigned long long* bad = &g->ctr->u64tmp[2];
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, stream, (uint32_t*)bad, 2, 0u);
+  for (int v = 0; v < 3; ++v) {
+    if (!g->view[v].on) continue;
+    hipLaunchKernelGGL(k_check, dim3(grid_for_groups(std::min<uint64_t>(g->n, 1u << 20))),
+                       dim3(kBlock), 0, stream, g->view[v].d, g->n,
+                       (uint32_t)g->view[v].pool_used_est, bad);
+    MK_LAUNCH(g, "k_check");
+  }
+  MK_HIP(g, hipMemcpyAsync(g->h_pin, bad, 8, hipMemcpyDeviceToHost, stream));
+  MK_HIP(g, hipStreamSynchronize(stream));
+  *h_bad = g->h_pin[0];
+  return MK_OK;
+}
+
+mk_status mk_probe_cost(mk_graph* g, int op, int view, const uint32_t* d_src, const uint32_t* d_dst,
+                        uint64_t n, uint64_t* h_slabs, hipStream_t stream) {
+  if (!g || !h_slabs || view < 0 || view > 2 || op < 0 || op > 1) return MK_ERR_INVALID_ARG;
+  if (!g->view[view].on) return MK_ERR_STATE;
+  *h_slabs = 0;
+  if (n == 0) return MK_OK;
+  if (!d_src || !d_dst) return MK_ERR_INVALID_ARG;
+  unsigned long long* acc = &g->ctr->u64tmp[1];
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, stream, (uint32_t*)acc, 2, 0u);
+  hipLaunchKernelGGL(k_probe_cost, dim3(grid_for_groups(n)), dim3(kBlock), 0, stream, g->view[view].d,
+                     op, view, d_src, d_dst, n, g->n, acc);
+  MK_LAUNCH(g, "k_probe_cost");
+  MK_HIP(g, hipMemcpyAsync(g->h_pin, acc, 8, hipMemcpyDeviceToHost, stream));
+  MK_HIP(g, hipStreamSynchronize(stream));
+  *h_slabs = g->h_pin[0];
+  return MK_OK;
+}
+
+const char* mk_status_string(mk_status s) {
+  switch (s) {
+    case MK_OK: return "ok";
+    case MK_ERR_INVALID_ARG: return "invalid argument";
+    case MK_ERR_OUT_OF_SLABS: return "slab pool exhausted (nothing applied)";
+    case MK_ERR_CAPACITY: return "capacity exceeded";
+    case MK_ERR_STATE: return "the graph lacks a view this operation needs";
+    case MK_ERR_HIP: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

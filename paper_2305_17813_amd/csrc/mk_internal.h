@@ -1,0 +1,128 @@
+// Host-side graph object shared by the library's translation units.
+#pragma once
+#include <deque>
+#include <string>
+#include <vector>
+
+#include "meerkat_mi355x.h"
+#include "mk_device.h"
+
+namespace mk {
+
+enum { VF = 0, VR = 1, VU = 2 };
+enum BatchKind { kInsertBatch = 0, kDeleteBatch = 1 };
+
+// One applied update batch, remembered for the incremental algorithms.  Its ops live in
+// the change log at [off, off + n) with their endpoints, weight, per-op status and the
+// "undirected edge changed" flag.
+struct BatchRec {
+  int kind;
+  uint64_t off, n, seq;
+};
+
+struct Log {
+  uint32_t *s = nullptr, *d = nullptr, *w = nullptr;
+  uint8_t *st = nullptr, *uf = nullptr;
+};
+
+struct ViewHost {
+  bool on = false;
+  DView d{};
+  uint2* dir = nullptr;
+  uint64_t head_reserved = 0;  // head slabs the arena reserves (upper bound)
+  uint64_t n_head = 0;         // head slabs in use
+  uint64_t pool_cap = 0;       // chained slabs
+  uint64_t pool_used_est = 0;  // host-side upper bound of the pool counter
+};
+
+struct AlgoState {
+  bool valid = false;      // holds a result for the graph as of batch `seen_seq`
+  uint32_t source = 0;
+  uint64_t seen_seq = 0;   // every batch with seq <= seen_seq is reflected
+};
+
+struct Counters {          // device-side scalars, one 4 KiB block
+  uint32_t frontier[8];    // rotating frontier sizes (light and heavy queues)
+  uint32_t inval;          // invalidated-vertex list size
+  uint32_t pad0[7];
+  unsigned long long tc_s[3];  // S1, S2, S3 of the triangle batch identity
+  unsigned long long tc_total; // current triangle count
+  unsigned long long u64tmp[4];
+  double pr_acc[8];        // PageRank sums: [2i] dangling, [2i+1] L1 change (rotating)
+  uint32_t pr_state[8];    // [0] done flag, [1] iterations run, [2] stall count
+  double pr_last;          // last L1 change
+  double pr_best;          // smallest L1 change seen
+};
+
+}  // namespace mk
+
+struct mk_graph {
+  mk_config cfg{};
+  uint32_t n = 0;
+  mk::ViewHost view[3];
+  char* arena = nullptr;
+  size_t arena_bytes = 0, used = 0;
+
+  // change log (ring of batches)
+  mk::Log log{};
+  uint64_t log_cap = 0, log_tail = 0;
+  std::deque<mk::BatchRec> batches;
+  uint64_t next_seq = 1;      // seq of the next applied batch
+  uint64_t dropped_seq = 0;   // batches with seq <= dropped_seq are no longer in the log
+
+  // traversal scratch
+  mk::Counters* ctr = nullptr;
+  uint32_t* fq[4] = {nullptr, nullptr, nullptr, nullptr};  // light cur/next, heavy cur/next
+  uint32_t* mark = nullptr;
+  uint32_t* inval = nullptr;
+  uint32_t stamp = 0;
+  uint32_t rot = 0;           // frontier counter rotation
+
+  uint64_t* bfs_D = nullptr;
+  uint64_t* sssp_D = nullptr;
+  mk::AlgoState bfs, sssp, wcc, pr, tc;
+  uint32_t* wcc_parent = nullptr;
+  float* pr_x = nullptr;      // current ranks
+  float* pr_y = nullptr;      // next ranks
+  float* pr_c = nullptr;      // contribution per vertex
+  uint32_t* heavy_rev = nullptr;  // rev-view vertices walked by a block
+  uint32_t n_heavy_rev = 0;
+  bool heavy_rev_ok = false;
+
+  uint64_t* tc_keys[2] = {nullptr, nullptr};
+  void* sort_tmp = nullptr;
+  size_t sort_tmp_bytes = 0;
+  void* scan_tmp = nullptr;
+  size_t scan_tmp_bytes = 0;
+
+  uint64_t* h_pin = nullptr;  // pinned host words for read-backs
+  uint64_t batches_applied = 0;
+  std::string last_err;
+};
+
+namespace mk {
+mk_status hip_fail(mk_graph* g, hipError_t e, const char* what);
+#define MK_HIP(g, call)                                  \
+  do {                                                   \
+    hipError_t _e = (call);                              \
+    if (_e != hipSuccess) return mk::hip_fail(g, _e, #call); \
+  } while (0)
+#define MK_LAUNCH(g, what)                                   \
+  do {                                                       \
+    hipError_t _e = hipGetLastError();                       \
+    if (_e != hipSuccess) return mk::hip_fail(g, _e, what);  \
+  } while (0)
+
+inline uint32_t grid_for_groups(uint64_t groups) {
+  return (uint32_t)((groups + kGroupsPerBlock - 1) / kGroupsPerBlock);
+}
+
+// Pending batches for an algorithm: those with seq > st.seen_seq.
+struct Pending {
+  bool lost = false;        // some pending batch fell out of the log
+  int kinds = 0;            // bit 0: an insert batch is pending, bit 1: a delete batch
+  std::vector<const BatchRec*> list;
+};
+Pending pending_for(const mk_graph* g, const AlgoState& st);
+void mark_seen(mk_graph* g, AlgoState& st);
+}  // namespace mk

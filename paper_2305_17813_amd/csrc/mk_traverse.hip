@@ -1,0 +1,367 @@
+// Dynamic BFS and SSSP (section 4.2, the batch-dynamic SSSP algorithm; BFS uses the same
+// kernels with unit weights).
+//
+// Each vertex keeps a 64-bit tree node <distance, parent> (the footnote on the packed
+// pair) updated by a 64-bit atomic minimum, so among equal distances the smallest parent
+// id wins and the fixed point is unique.  A batch is applied by a prologue followed by
+// the common frontier epilogue:
+//   insert prologue : relax every effective inserted arc (u, v, w) with a finite u;
+//   delete prologue : invalidate v for each deleted tree arc (parent(v) == u), invalidate
+//                     the whole dependence subtree below it, then pull each invalidated
+//                     vertex's best candidate from its valid in-neighbours (reverse view);
+//                     this is the decremental frontier of valid -> invalid arcs;
+//   epilogue        : expand the frontier until it is empty.
+//
+// Differences from the paper's kernels (same fixed point): the frontier holds vertices,
+// not edges (a per-iteration stamp keeps each vertex once); subtree invalidation walks
+// the tree top-down through the forward view instead of walking every vertex's parent
+// chain to the source; vertices with many buckets are expanded by a whole block.
+#include <algorithm>
+
+#include "mk_internal.h"
+
+using namespace mk;
+
+namespace {
+
+constexpr uint32_t kExpandBlocks = 2048;  // 256 CUs x 8 resident blocks
+constexpr int kSyncEvery = 4;            // frontier launches between size read-backs
+
+__device__ inline uint64_t tree_node(uint64_t dist, uint32_t parent) {
+  if (dist >= 0xFFFFFFFFull) dist = 0xFFFFFFFEull;  // saturate below INF
+  return (dist << 32) | parent;
+}
+
+__device__ inline void push_vertex(const uint2* dir, uint32_t* Lq, uint32_t* Lc, uint32_t* Hq,
+                                   uint32_t* Hc, uint32_t* mark, uint32_t stamp, bool p, uint32_t v) {
+  bool take = false;
+  if (p) take = atomicExch(mark + v, stamp) != stamp;
+  bool heavy = false;
+  if (take) heavy = dir[v].y > kHeavyBuckets;
+  wave_push(Lq, Lc, take && !heavy, v);
+  wave_push(Hq, Hc, take && heavy, v);
+}
+
+struct Queues {
+  const uint32_t* Lcur;
+  const uint32_t* Hcur;
+  uint32_t* Lnext;
+  uint32_t* Hnext;
+  uint32_t* cnt;  // [0..2] light sizes, [3..5] heavy sizes (rotating)
+  int icur, inext, iclear;
+};
+
+// Relax every out-arc of u held in one slab word per lane.
+template <bool kUnit>
+__device__ inline void relax_word(const DView& F, uint64_t* D, uint32_t u, uint64_t du, uint64_t x,
+                                  const Queues& q, uint32_t* mark, uint32_t stamp) {
+  const uint32_t v = (uint32_t)x;
+  bool improve = false;
+  if (glane() < kKeysPerSlab && valid_key(v)) {
+    const uint64_t w = kUnit ? 1ull : (x >> 32);
+    const uint64_t cand = tree_node(du + w, u);
+    if (cand < D[v]) improve = amin64(D + v, cand) > cand;
+  }
+  push_vertex(F.dir, q.Lnext, q.cnt + q.inext, q.Hnext, q.cnt + 3 + q.inext, mark, stamp, improve, v);
+}
+
+template <bool kUnit>
+__global__ void __launch_bounds__(kBlock) k_expand(DView F, uint64_t* D, Queues q, uint32_t* mark,
+                                                   uint32_t stamp) {
+  const uint32_t nl = q.cnt[q.icur], nh = q.cnt[3 + q.icur];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    q.cnt[q.iclear] = 0;
+    q.cnt[3 + q.iclear] = 0;
+  }
+  if (nl == 0 && nh == 0) return;
+  const uint32_t g0 = (blockIdx.x * kBlock + threadIdx.x) / kGroup;
+  const uint32_t ng = gridDim.x * kGroupsPerBlock;
+  for (uint32_t i = g0; i < nl; i += ng) {
+    const uint32_t u = q.Lcur[i];
+    const uint64_t du = ld_u64_coherent(D + u) >> 32;
+    for_each_slab<false>(F, u, [&](uint64_t x) { relax_word<kUnit>(F, D, u, du, x, q, mark, stamp); });
+  }
+  const uint32_t gib = threadIdx.x / kGroup;
+  for (uint32_t j = blockIdx.x; j < nh; j += gridDim.x) {
+    const uint32_t u = q.Hcur[j];
+    const uint64_t du = ld_u64_coherent(D + u) >> 32;
+    for_each_slab_strided<false>(F, F.dir[u], gib, kGroupsPerBlock, [&](uint64_t x) {
+      relax_word<kUnit>(F, D, u, du, x, q, mark, stamp);
+    });
+  }
+}
+
+__global__ void k_trav_init(uint64_t* D, uint32_t nv, uint32_t src) {
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x)
+    D[v] = v == src ? (uint64_t)src : kTreeNone;
+}
+
+// Reset the rotating counters so that slot 0 is the current frontier.
+__global__ void k_queue_reset(uint32_t* cnt, uint32_t* inval_cnt) {
+  if (threadIdx.x < 6) cnt[threadIdx.x] = 0;
+  if (threadIdx.x == 0 && inval_cnt) *inval_cnt = 0;
+}
+
+__global__ void k_seed_source(DView F, uint32_t src, uint32_t* Lq, uint32_t* Hq, uint32_t* cnt,
+                              uint32_t* mark, uint32_t stamp) {
+  if (threadIdx.x != 0) return;
+  mark[src] = stamp;
+  if (F.dir[src].y > kHeavyBuckets) {
+    Hq[0] = src;
+    cnt[3] = 1;
+  } else {
+    Lq[0] = src;
+    cnt[0] = 1;
+  }
+}
+
+// Insert prologue: relax each effective inserted arc.
+template <bool kUnit>
+__global__ void k_relax_batch(DView F, uint64_t* D, Log lg, uint64_t n, uint32_t* Lq, uint32_t* Hq,
+                              uint32_t* cnt, uint32_t* mark, uint32_t stamp) {
+  // whole waves step together so that the wave-wide push sees every lane
+  const uint64_t lane = threadIdx.x & 63;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x - lane; base < n;
+       base += stride) {
+    const uint64_t i = base + lane;
+    bool improve = false;
+    uint32_t v = 0;
+    if (i < n && lg.st[i] == 1) {
+      const uint32_t u = lg.s[i];
+      v = lg.d[i];
+      const uint64_t du = ld_u64_coherent(D + u);
+      if (du != kTreeNone) {
+        const uint64_t cand = tree_node((du >> 32) + (kUnit ? 1u : lg.w[i]), u);
+        if (cand < D[v]) improve = amin64(D + v, cand) > cand;
+      }
+    }
+    push_vertex(F.dir, Lq, cnt, Hq, cnt + 3, mark, stamp, improve, v);
+  }
+}
+
+// Delete prologue, step 1: a deleted arc (u, v) of the dependence tree invalidates v.
+__global__ void k_invalidate(DView F, uint64_t* D, Log lg, uint64_t n, uint32_t* Lq, uint32_t* Hq,
+                             uint32_t* cnt, uint32_t* inval, uint32_t* inval_cnt, uint32_t* mark,
+                             uint32_t stamp) {
+  const uint64_t lane = threadIdx.x & 63;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x - lane; base < n;
+       base += stride) {
+    const uint64_t i = base + lane;
+    bool hit = false;
+    uint32_t v = 0;
+    if (i < n && lg.st[i] == 1) {
+      const uint32_t u = lg.s[i];
+      v = lg.d[i];
+      const uint64_t dv = ld_u64_coherent(D + v);
+      if (dv != kTreeNone && (uint32_t)dv == u) hit = cas64(D + v, dv, kTreeNone) == dv;
+    }
+    wave_push(inval, inval_cnt, hit, v);
+    push_vertex(F.dir, Lq, cnt, Hq, cnt + 3, mark, stamp, hit, v);
+  }
+}
+
+// Delete prologue, step 2: invalidate the subtree below each invalidated vertex x (its
+// tree children are the out-neighbours y whose parent is x).
+__device__ inline void inval_word(const DView& F, uint64_t* D, uint32_t x_parent, uint64_t w,
+                                  const Queues& q, uint32_t* inval, uint32_t* inval_cnt,
+                                  uint32_t* mark, uint32_t stamp) {
+  const uint32_t y = (uint32_t)w;
+  bool hit = false;
+  if (glane() < kKeysPerSlab && valid_key(y)) {
+    const uint64_t dy = ld_u64_coherent(D + y);
+    if (dy != kTreeNone && (uint32_t)dy == x_parent) hit = cas64(D + y, dy, kTreeNone) == dy;
+  }
+  wave_push(inval, inval_cnt, hit, y);
+  push_vertex(F.dir, q.Lnext, q.cnt + q.inext, q.Hnext, q.cnt + 3 + q.inext, mark, stamp, hit, y);
+}
+
+__global__ void __launch_bounds__(kBlock) k_propagate(DView F, uint64_t* D, Queues q, uint32_t* inval,
+                                                      uint32_t* inval_cnt, uint32_t* mark,
+                                                      uint32_t stamp) {
+  const uint32_t nl = q.cnt[q.icur], nh = q.cnt[3 + q.icur];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    q.cnt[q.iclear] = 0;
+    q.cnt[3 + q.iclear] = 0;
+  }
+  if (nl == 0 && nh == 0) return;
+  const uint32_t g0 = (blockIdx.x * kBlock + threadIdx.x) / kGroup;
+  const uint32_t ng = gridDim.x * kGroupsPerBlock;
+  for (uint32_t i = g0; i < nl; i += ng) {
+    const uint32_t x = q.Lcur[i];
+    for_each_slab<false>(F, x, [&](uint64_t w) { inval_word(F, D, x, w, q, inval, inval_cnt, mark, stamp); });
+  }
+  const uint32_t gib = threadIdx.x / kGroup;
+  for (uint32_t j = blockIdx.x; j < nh; j += gridDim.x) {
+    const uint32_t x = q.Hcur[j];
+    for_each_slab_strided<false>(F, F.dir[x], gib, kGroupsPerBlock, [&](uint64_t w) {
+      inval_word(F, D, x, w, q, inval, inval_cnt, mark, stamp);
+    });
+  }
+}
+
+// Delete prologue, step 3: each invalidated vertex takes the best candidate offered by
+// its still-valid in-neighbours (reverse view) and, if reached, joins the frontier.
+template <bool kUnit>
+__global__ void __launch_bounds__(kBlock) k_dec_pull(DView F, DView R, uint64_t* D,
+                                                     const uint32_t* inval, const uint32_t* inval_cnt,
+                                                     uint32_t* Lq, uint32_t* Hq, uint32_t* cnt,
+                                                     uint32_t* mark, uint32_t stamp) {
+  const uint32_t n = *inval_cnt;
+  const uint32_t g0 = (blockIdx.x * kBlock + threadIdx.x) / kGroup;
+  const uint32_t ng = gridDim.x * kGroupsPerBlock;
+  for (uint32_t i = g0; i < n; i += ng) {
+    const uint32_t y = inval[i];
+    uint64_t best = kTreeNone;
+    for_each_slab<false>(R, y, [&](uint64_t x) {
+      const uint32_t u = (uint32_t)x;
+      if (glane() < kKeysPerSlab && valid_key(u)) {
+        const uint64_t du = ld_u64_coherent(D + u);
+        if (du != kTreeNone) {
+          const uint64_t cand = tree_node((du >> 32) + (kUnit ? 1ull : (x >> 32)), u);
+          best = cand < best ? cand : best;
+        }
+      }
+    });
+    best = gmin_u64(best);
+    bool improve = false;
+    if (glane() == 0 && best != kTreeNone) improve = amin64(D + y, best) > best;
+    push_vertex(F.dir, Lq, cnt, Hq, cnt + 3, mark, stamp, improve, y);
+  }
+}
+
+__global__ void k_split(const uint64_t* D, uint32_t nv, uint32_t* dist, uint32_t* parent) {
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
+    const uint64_t x = D[v];
+    dist[v] = (uint32_t)(x >> 32);
+    if (parent) parent[v] = (uint32_t)x;
+  }
+}
+
+inline uint32_t blocks_for(uint64_t n, uint32_t cap = 4096) {
+  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((n + kBlock - 1) / kBlock, cap));
+}
+
+Queues queues(mk_graph* g, uint64_t it) {
+  Queues q;
+  const int a = (int)(it & 1);
+  q.Lcur = g->fq[a];
+  q.Lnext = g->fq[a ^ 1];
+  q.Hcur = g->fq[2 + a];
+  q.Hnext = g->fq[2 + (a ^ 1)];
+  q.cnt = g->ctr->frontier;
+  q.icur = (int)(it % 3);
+  q.inext = (int)((it + 1) % 3);
+  q.iclear = (int)((it + 2) % 3);
+  return q;
+}
+
+// Run frontier iterations (expand or propagate) until the frontier is empty.  Iteration
+// `it` reads slot it%3; the frontier of iteration 0 sits in fq[0] / fq[2] and slot 0.
+template <class Launch>
+mk_status run_frontier(mk_graph* g, hipStream_t stream, Launch&& launch, uint64_t* iters_out) {
+  uint64_t it = 0;
+  while (true) {
+    for (int k = 0; k < kSyncEvery; ++k, ++it) {
+      launch(queues(g, it), ++g->stamp);
+      MK_LAUNCH(g, "frontier kernel");
+    }
+    const int slot = (int)(it % 3);
+    MK_HIP(g, hipMemcpyAsync(g->h_pin, g->ctr->frontier, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                             stream));
+    MK_HIP(g, hipStreamSynchronize(stream));
+    const uint32_t* c = reinterpret_cast<const uint32_t*>(g->h_pin);
+    if (c[slot] == 0 && c[3 + slot] == 0) break;
+  }
+  if (iters_out) *iters_out = it;
+  // leave the frontier of "iteration 0" empty for the next user
+  return MK_OK;
+}
+
+template <bool kUnit>
+mk_status traverse(mk_graph* g, AlgoState& st, uint64_t* D, uint32_t source, uint32_t* d_out,
+                   uint32_t* d_parent, mk_mode mode, hipStream_t stream) {
+  if (source >= g->n || !d_out) return MK_ERR_INVALID_ARG;
+  const DView F = g->view[VF].d;
+  const uint32_t N = g->n;
+  Pending p = pending_for(g, st);
+  const bool can_dec = g->view[VR].on;
+  bool full = mode == MK_RECOMPUTE || !st.valid || st.source != source || p.lost || p.kinds == 3 ||
+              (p.kinds == 2 && !can_dec);
+  uint32_t* Lq0 = g->fq[0];
+  uint32_t* Hq0 = g->fq[2];
+  uint32_t* cnt = g->ctr->frontier;
+  const uint32_t stamp0 = ++g->stamp;
+  bool run = true;
+  hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, stream, cnt, &g->ctr->inval);
+  if (full) {
+    hipLaunchKernelGGL(k_trav_init, dim3(blocks_for(N)), dim3(kBlock), 0, stream, D, N, source);
+    hipLaunchKernelGGL(k_seed_source, dim3(1), dim3(64), 0, stream, F, source, Lq0, Hq0, cnt,
+                       g->mark, stamp0);
+  } else if (p.list.empty()) {
+    run = false;
+  } else if (p.kinds == 1) {
+    for (const BatchRec* b : p.list) {
+      Log lg = g->log;
+      lg.s += b->off; lg.d += b->off; lg.w += b->off; lg.st += b->off; lg.uf += b->off;
+      hipLaunchKernelGGL(k_relax_batch<kUnit>, dim3(blocks_for(b->n)), dim3(kBlock), 0, stream, F,
+                         D, lg, b->n, Lq0, Hq0, cnt, g->mark, stamp0);
+    }
+  } else {  // deletions only
+    for (const BatchRec* b : p.list) {
+      Log lg = g->log;
+      lg.s += b->off; lg.d += b->off; lg.w += b->off; lg.st += b->off; lg.uf += b->off;
+      hipLaunchKernelGGL(k_invalidate, dim3(blocks_for(b->n)), dim3(kBlock), 0, stream, F, D, lg,
+                         b->n, Lq0, Hq0, cnt, g->inval, &g->ctr->inval, g->mark, stamp0);
+    }
+    MK_LAUNCH(g, "k_invalidate");
+    mk_status s = run_frontier(
+        g, stream,
+        [&](Queues q, uint32_t stamp) {
+          hipLaunchKernelGGL(k_propagate, dim3(kExpandBlocks), dim3(kBlock), 0, stream, F, D, q,
+                             g->inval, &g->ctr->inval, g->mark, stamp);
+        },
+        nullptr);
+    if (s != MK_OK) return s;
+    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, stream, cnt, nullptr);
+    const uint32_t stamp1 = ++g->stamp;
+    hipLaunchKernelGGL(k_dec_pull<kUnit>, dim3(kExpandBlocks), dim3(kBlock), 0, stream, F,
+                       g->view[VR].d, D, g->inval, &g->ctr->inval, Lq0, Hq0, cnt, g->mark, stamp1);
+  }
+  MK_LAUNCH(g, "traversal prologue");
+  if (run) {
+    mk_status s = run_frontier(
+        g, stream,
+        [&](Queues q, uint32_t stamp) {
+          hipLaunchKernelGGL(k_expand<kUnit>, dim3(kExpandBlocks), dim3(kBlock), 0, stream, F, D, q,
+                             g->mark, stamp);
+        },
+        nullptr);
+    if (s != MK_OK) return s;
+  }
+  hipLaunchKernelGGL(k_split, dim3(blocks_for(N)), dim3(kBlock), 0, stream, D, N, d_out, d_parent);
+  MK_LAUNCH(g, "k_split");
+  st.valid = true;
+  st.source = source;
+  mark_seen(g, st);
+  return MK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mk_status mk_incr_bfs(mk_graph* g, uint32_t source, uint32_t* d_level, uint32_t* d_parent,
+                      mk_mode mode, hipStream_t stream) {
+  if (!g) return MK_ERR_INVALID_ARG;
+  return traverse<true>(g, g->bfs, g->bfs_D, source, d_level, d_parent, mode, stream);
+}
+
+mk_status mk_incr_sssp(mk_graph* g, uint32_t source, uint32_t* d_dist, uint32_t* d_parent,
+                       mk_mode mode, hipStream_t stream) {
+  if (!g) return MK_ERR_INVALID_ARG;
+  return traverse<false>(g, g->sssp, g->sssp_D, source, d_dist, d_parent, mode, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,205 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle, element by element.
+
+Integers (statuses, membership, weights, BFS levels, SSSP distances, parents, component
+labels, triangle counts) must be bit-exact; PageRank must be within 1e-6 in L1.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2305_17813_amd import inputs as I
+from paper_2305_17813_amd import native
+from parity import Pair, say, u32
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    native.load()
+
+
+def make_pair(g: I.EdgeList, source=0, **kw):
+    return Pair(g.n, g.src, g.dst, g.w, source=source, **kw)
+
+
+def test_er_4096_end_to_end():
+    """ER digraph 4,096 / 32,768: insert 1,024, delete 1,024, 4,096 queries; BFS and SSSP
+    from vertex 0 (and WCC, PageRank, triangles) after each batch."""
+    say("case: ER 4096 end to end")
+    g = I.er_4k()
+    p = make_pair(g, source=0)
+    p.check_structure()
+    p.check_all()
+    wl = I.Workload(g, 11)
+    s, d, w = wl.insert_batch(1024)
+    st = p.insert(s, d, w)
+    assert int((st == 1).sum()) == 1024
+    p.check_all()
+    s, d = wl.delete_batch(1024)
+    st = p.delete(s, d)
+    assert int((st == 1).sum()) == 1024
+    p.check_all()
+    qs, qd = wl.query_batch(4096)
+    p.query(qs, qd)
+    p.check_structure()
+
+
+@pytest.mark.parametrize("scale", [10, 12])
+def test_rmat_batches(scale):
+    say(f"case: rmat scale {scale}")
+    g = I.rmat_s(scale)
+    src = I.max_out_degree_vertex(g)
+    p = make_pair(g, source=src)
+    p.check_all()
+    wl = I.Workload(g, 5)
+    for b in [100, 1000, 3000]:
+        s, d, w = wl.insert_batch(b)
+        p.insert(s, d, w)
+        p.check_all()
+        s, d = wl.delete_batch(b)
+        p.delete(s, d)
+        p.check_all()
+    qs, qd = wl.query_batch(20000)
+    p.query(qs, qd)
+    p.check_structure()
+
+
+def test_grid_road_like():
+    say("case: grid 64x64")
+    g = I.grid_side(64)
+    p = make_pair(g, source=0)
+    p.check_all()
+    wl = I.Workload(g, 8)
+    for b in [10, 100, 400]:
+        s, d, w = wl.insert_batch(b)
+        p.insert(s, d, w)
+        p.check_all()
+        s, d = wl.delete_batch(b)
+        p.delete(s, d)
+        p.check_all()
+    p.check_structure()
+
+
+def test_one_source_long_chains_and_reinsert():
+    """Every op on one source (one chain of hundreds of slabs): contention on one tail,
+    slab linking races, tombstones, delete then re-insert."""
+    say("case: one source long chain")
+    n = 6000
+    p = Pair(n, [1], [2], [5], source=0)
+    rng = np.random.default_rng(3)
+    dst = rng.permutation(np.arange(1, n))[:5000]
+    p.insert(np.zeros(5000, np.int64), dst, rng.integers(1, 100, 5000))
+    p.check_structure()
+    p.check_all(algos=("bfs", "sssp", "wcc", "tc"))
+    p.delete(np.zeros(2500, np.int64), dst[::2])
+    p.check_structure()
+    p.insert(np.zeros(5000, np.int64), dst, np.full(5000, 7))  # half present, half re-inserted
+    p.check_structure()
+    p.query(np.zeros(n, np.int64), np.arange(n))
+    p.check_all(algos=("bfs", "sssp", "wcc", "tc"))
+
+
+def test_in_batch_duplicates_exactly_one_applies():
+    say("case: in-batch duplicates")
+    g = I.er_graph(512, 2000, 77)
+    p = make_pair(g)
+    rng = np.random.default_rng(4)
+    s = rng.integers(0, 512, 3000)
+    d = rng.integers(0, 512, 3000)
+    s = np.concatenate([s, s, s, s])
+    d = np.concatenate([d, d, d, d])
+    w = np.full(s.size, 9)
+    p.insert(s, d, w, exact_status=False)
+    p.check_structure()
+    p.delete(s, d, exact_status=False)
+    p.check_structure()
+    p.check_all()
+
+
+def test_rejections_and_queries_of_invalid_ids():
+    say("case: rejections")
+    p = Pair(100, [0, 1], [1, 2], [3, 4])
+    s = [0, 5, 100, 0xFFFFFFFD, 7, 3]
+    d = [0, 101, 3, 4, 0xFFFFFFFE, 4]
+    st = p.insert(s, d, [1] * 6)
+    assert list(st) == [2, 2, 2, 2, 2, 1]
+    p.query(s, d)
+    st = p.delete(s, d)
+    assert list(st) == [2, 2, 2, 2, 2, 1]
+
+
+def test_out_of_slabs_is_clean():
+    """A tiny pool makes the pre-check refuse the batch; nothing is applied."""
+    say("case: out of slabs")
+    g = I.er_graph(256, 1000, 5)
+    p = make_pair(g, pool_slabs=64)
+    s = np.zeros(600, np.int64)
+    d = np.arange(1, 601) % 256
+    with pytest.raises(native.MkError) as e:
+        p.g.insert_edges(s, d, np.ones(600))
+    assert e.value.status == 2
+    p.check_structure()  # still equal to the oracle, which saw nothing
+
+
+def test_hashing_off_single_bucket():
+    say("case: hashing off")
+    g = I.rmat_s(10)
+    p = make_pair(g, source=I.max_out_degree_vertex(g), load_factor=0.0)
+    wl = I.Workload(g, 1)
+    s, d, w = wl.insert_batch(500)
+    p.insert(s, d, w)
+    p.check_all()
+    s, d = wl.delete_batch(500)
+    p.delete(s, d)
+    p.check_all()
+    p.check_structure()
+
+
+def test_several_pending_batches_then_one_call():
+    say("case: several pending batches")
+    g = I.rmat_s(11)
+    p = make_pair(g, source=I.max_out_degree_vertex(g))
+    p.check_all()
+    wl = I.Workload(g, 2)
+    for _ in range(3):  # same kind: combined incremental update
+        s, d, w = wl.insert_batch(300)
+        p.insert(s, d, w)
+    p.check_all()
+    for _ in range(3):
+        s, d = wl.delete_batch(300)
+        p.delete(s, d)
+    p.check_all()
+    s, d, w = wl.insert_batch(300)  # mixed kinds: recompute
+    p.insert(s, d, w)
+    s, d = wl.delete_batch(300)
+    p.delete(s, d)
+    p.check_all()
+
+
+def test_recompute_and_incremental_agree_and_are_deterministic():
+    say("case: modes and determinism")
+    g = I.rmat_s(11)
+    src = I.max_out_degree_vertex(g)
+    outs = []
+    for rep in range(2):
+        p = make_pair(g, source=src)
+        p.g.sssp(src)
+        wl = I.Workload(g, 4)
+        s, d, w = wl.insert_batch(700)
+        p.insert(s, d, w)
+        a = [u32(x) for x in p.g.sssp(src, native.INCR)]
+        b = [u32(x) for x in p.g.sssp(src, native.RECOMPUTE)]
+        assert all(np.array_equal(x, y) for x, y in zip(a, b))
+        outs.append(a + [u32(p.g.wcc()), u32(p.g.bfs(src)[0])])
+    assert all(np.array_equal(x, y) for x, y in zip(outs[0], outs[1]))
+
+
+def test_generators_identical_on_gpu_and_cpu():
+    say("case: generator device equality")
+    a = I.rmat_graph(10, 8, 123, device="cpu")
+    b = I.rmat_graph(10, 8, 123, device=DEV)
+    assert torch.equal(a.src, b.src.cpu()) and torch.equal(a.dst, b.dst.cpu())
+    assert torch.equal(a.w, b.w.cpu())
