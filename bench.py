@@ -1,0 +1,285 @@
+#!/usr/bin/env python
+"""Benchmark of the dynamic slab-hash graph on one MI355X.
+
+Workload: an R-MAT power-law digraph of scale 22 (4,194,304 vertices, edge factor 16,
+a,b,c,d = .57,.19,.19,.05, u32 ids, u32 weights uniform in [1,100]), seeded and
+synthetic, built in HBM before timing.  One step is one pass of the whole hot path:
+
+    insert a batch of B new arcs (uniform endpoints)
+      -> incremental BFS, SSSP, WCC, PageRank, triangle count
+    delete a batch of B arcs drawn from the present ones
+      -> incremental BFS, SSSP, WCC (recompute after deletes), PageRank, triangle count
+    query Q arcs (half present)
+
+All batches are generated and moved to HBM before the timed region.  `value` is edge
+updates per second over the insert and delete kernels of the timed steps; every phase is
+timed with HIP events on the stream the library launches on.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+METRIC = "edge updates/s + queries/s at R-MAT s22; incr. SSSP ms/batch; HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--scale", type=int, default=22)
+    ap.add_argument("--batch", type=int, default=1_000_000)
+    ap.add_argument("--queries", type=int, default=1 << 20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=1_000_000,
+                    help="inserts and deletes the oracle applies for the CPU baseline")
+    ap.add_argument("--seed", type=int, default=0x4D45524B + 1)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        log("bench.py runs on exactly one GPU: multi-GPU sharding is a design only.")
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2305_17813_amd import inputs as I
+    from paper_2305_17813_amd import native
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.time()
+    g_in = I.rmat_graph(args.scale, 16, args.seed, device=dev)
+    torch.cuda.synchronize()
+    log(f"[bench] R-MAT s{args.scale}: {g_in.n} vertices, {g_in.m} arcs generated in {time.time()-t0:.1f}s")
+    src_v = I.max_out_degree_vertex(g_in)
+    B, Q = args.batch, args.queries
+    stream = torch.cuda.current_stream(dev)
+    t0 = time.time()
+    G = native.Graph(g_in.n, g_in.src, g_in.dst, g_in.w, views=7, load_factor=0.7,
+                     log_capacity=max(1 << 22, 4 * B), device=dev, stream=stream)
+    torch.cuda.synchronize()
+    build_s = time.time() - t0
+    st = G.stats()
+    log(f"[bench] graph built in {build_s:.2f}s; arena {G.arena_bytes/2**30:.2f} GiB; stats {st}")
+
+    # pre-generate every batch (inputs resident in HBM before timing)
+    wl = I.Workload(g_in, args.seed + 7)
+    steps = []
+    for _ in range(args.warmup + args.steps):
+        s, d, w = wl.insert_batch(B)
+        ds, dd = wl.delete_batch(B)
+        qs, qd = wl.query_batch(Q)
+        steps.append(tuple(native.as_u32(x, dev) for x in (s, d, w, ds, dd, qs, qd)))
+    torch.cuda.synchronize()
+    log(f"[bench] {len(steps)} steps of batches generated")
+
+    # static results first (the state the incremental algorithms start from)
+    t0 = time.time()
+    G.bfs(src_v)
+    G.sssp(src_v)
+    G.wcc()
+    G.pagerank()
+    tri0 = int(G.triangles().item())
+    torch.cuda.synchronize()
+    log(f"[bench] static BFS/SSSP/WCC/PR/TC in {time.time()-t0:.2f}s; triangles={tri0}")
+
+    phases = ["insert", "bfs_i", "sssp_i", "wcc_i", "pr_i", "tc_i",
+              "delete", "bfs_d", "sssp_d", "wcc_d", "pr_d", "tc_d", "query"]
+    times = {p: [] for p in phases}
+    pr_iters = []
+
+    def run_step(k, timed):
+        s, d, w, ds, dd, qs, qd = steps[k]
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(phases) + 1)]
+        ev[0].record(stream)
+        G.insert_edges(s, d, w, status=False)
+        ev[1].record(stream)
+        G.bfs(src_v, parents=True)
+        ev[2].record(stream)
+        G.sssp(src_v, parents=True)
+        ev[3].record(stream)
+        G.wcc()
+        ev[4].record(stream)
+        _, it1 = G.pagerank()
+        ev[5].record(stream)
+        G.triangles()
+        ev[6].record(stream)
+        G.delete_edges(ds, dd, status=False)
+        ev[7].record(stream)
+        G.bfs(src_v, parents=True)
+        ev[8].record(stream)
+        G.sssp(src_v, parents=True)
+        ev[9].record(stream)
+        G.wcc()
+        ev[10].record(stream)
+        _, it2 = G.pagerank()
+        ev[11].record(stream)
+        G.triangles()
+        ev[12].record(stream)
+        G.query_edges(qs, qd)
+        ev[13].record(stream)
+        if timed:
+            return ev, (it1, it2)
+        return None, None
+
+    for k in range(args.warmup):
+        run_step(k, False)
+    torch.cuda.synchronize()
+    log("[bench] warmup done")
+
+    # byte model of the first timed step's kernels, on the graph as the step will find it
+    s, d, w, ds, dd, qs, qd = steps[args.warmup]
+    slabs = {
+        "i_fwd": G.probe_cost(1, 0, s, d), "i_rev": G.probe_cost(1, 1, s, d),
+        "i_und": G.probe_cost(1, 2, s, d), "d_fwd": G.probe_cost(0, 0, ds, dd),
+        "d_rev": G.probe_cost(0, 1, ds, dd), "d_und": G.probe_cost(0, 2, ds, dd),
+        "q_fwd": G.probe_cost(0, 0, qs, qd),
+    }
+    evs = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(args.warmup, args.warmup + args.steps):
+        evs.append(run_step(k, True))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    for ev, its in evs:
+        for i, p in enumerate(phases):
+            times[p].append(ev[i].elapsed_time(ev[i + 1]))
+        pr_iters.append([int(x.item()) for x in its])
+    log(f"[bench] timed {args.steps} steps in {wall:.2f}s")
+
+    K = args.steps
+    t_ins = sum(times["insert"]) / 1e3
+    t_del = sum(times["delete"]) / 1e3
+    t_q = sum(times["query"]) / 1e3
+    updates_per_s = 2 * B * K / (t_ins + t_del)
+    queries_per_s = Q * K / t_q
+    med = lambda xs: float(np.median(xs))
+
+    # per op: read the op (8 or 12 B), directory entries (8 B per probe), the walked slabs
+    # (128 B each), the CAS / tombstone word (8 B per view), degree counters (4 B per view),
+    # the status byte and the change-log record (14 B)
+    q_bytes = Q * (8 + 8 + 1 + 4) + 128 * slabs["q_fwd"]
+    i_bytes = B * (12 + 1 + 14 + 4 * (8 + 8 + 4)) + 128 * (slabs["i_fwd"] + slabs["i_rev"] + slabs["i_und"])
+    d_bytes = B * (8 + 1 + 14 + 2 * (8 + 8 + 4)) + 128 * (slabs["d_fwd"] + slabs["d_rev"]) \
+        + B * (8 + 2 * (8 + 8 + 4)) + 128 * slabs["d_und"]
+    ins_ms = med(times["insert"])
+    q_ms = med(times["query"])
+    del_ms = med(times["delete"])
+    roof = {
+        "kernel": "k_insert (fwd+rev+und views)",
+        "bound": "hbm",
+        "achieved": i_bytes / (ins_ms / 1e3) / 1e9,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "traffic": None,
+        "bytes_per_launch": i_bytes,
+        "launch_ms": ins_ms,
+    }
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    rooflines = {
+        "k_query": {"achieved": q_bytes / (q_ms / 1e3) / 1e9, "bytes_per_launch": q_bytes, "launch_ms": q_ms,
+                    "slabs_per_op": slabs["q_fwd"] / Q},
+        "k_delete+k_delete_und": {"achieved": d_bytes / (del_ms / 1e3) / 1e9, "bytes_per_launch": d_bytes,
+                                  "launch_ms": del_ms},
+        "k_insert": {"achieved": roof["achieved"], "bytes_per_launch": i_bytes, "launch_ms": ins_ms,
+                     "slabs_per_op": {k: slabs[k] / B for k in ("i_fwd", "i_rev", "i_und")}},
+    }
+    for r in rooflines.values():
+        r["frac"] = r["achieved"] / HBM_PEAK_GBS
+
+    incr = {p: med(times[p]) for p in phases if p not in ("insert", "delete", "query")}
+    result = {
+        "metric": METRIC,
+        "value": updates_per_s,
+        "unit": "edge updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"R-MAT scale {args.scale}, edge factor 16, a/b/c/d=.57/.19/.19/.05, u32 ids, "
+                        f"u32 weights U[1,100]; per step {B} inserts + {B} deletes + {Q} queries "
+                        f"(50% present); incremental BFS/SSSP/WCC/PageRank/triangles after each batch",
+            "n_vertices": g_in.n, "n_arcs": g_in.m, "batch": B, "queries": Q,
+            "views": "fwd+rev+und", "load_factor": 0.7, "source": src_v,
+        },
+        "queries_per_s": queries_per_s,
+        "insert_ms_per_batch": ins_ms,
+        "delete_ms_per_batch": del_ms,
+        "query_ms_per_batch": q_ms,
+        "incr_sssp_ms_per_batch": (incr["sssp_i"] + incr["sssp_d"]) / 2,
+        "incr_ms_per_batch": incr,
+        "pagerank_iters": pr_iters,
+        "build_s": build_s,
+        "roofline": roof,
+        "rooflines": rooflines,
+    }
+
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(g_in, steps[args.warmup], src_v, args, wall * 1e3 / K)
+    print(json.dumps(result))
+
+
+def cpu_baseline(g_in, step, src_v, args, gpu_ms_per_step):
+    """The CPU oracle (single thread) applying a bounded sample of the same workload."""
+    import numpy as np
+    import oracle
+
+    oracle.build()
+    t0 = time.time()
+    src = g_in.src.to("cpu").numpy().astype(np.uint32)
+    dst = g_in.dst.to("cpu").numpy().astype(np.uint32)
+    w = g_in.w.to("cpu").numpy().astype(np.uint32)
+    o = oracle.OracleGraph(g_in.n, src, dst, w)
+    load_s = time.time() - t0
+    s, d, ww, ds, dd, qs, qd = [x.cpu().numpy().view(np.uint32) for x in step]
+    k = min(args.cpu_sample, s.size)
+    t0 = time.perf_counter()
+    o.insert(s[:k], d[:k], ww[:k])
+    o.delete(ds[:k], dd[:k])
+    t_upd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    o.query(qs, qd)
+    t_q = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    o.sssp(src_v)
+    t_sssp = time.perf_counter() - t0
+    log(f"[bench] oracle: load {load_s:.1f}s, {2*k} updates {t_upd:.2f}s, {qs.size} queries {t_q:.2f}s, "
+        f"Dijkstra {t_sssp:.2f}s")
+    return {
+        "value": 2 * k / t_upd,
+        "unit": "edge updates/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{k} inserts + {k} deletes of the first timed step applied to the sorted-adjacency "
+                  f"oracle holding the scale-{args.scale} graph (single thread); also {qs.size} queries "
+                  f"and one from-scratch Dijkstra",
+        "queries_per_s": qs.size / t_q,
+        "sssp_recompute_ms": t_sssp * 1e3,
+        "host_cpus": os.cpu_count(),
+    }
+
+
+if __name__ == "__main__":
+    main()
