@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=1_000_000,
                     help="inserts and deletes the oracle applies for the CPU baseline")
     ap.add_argument("--seed", type=int, default=0x4D45524B + 1)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 1 GiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -62,6 +64,15 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.calibrate_copy:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device=dev).fill_(1)
+        c = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            c.copy_(a)  # reads 1 GiB and writes 1 GiB per launch
+        torch.cuda.synchronize()
+        del a, c
+        log("[bench] calibration copies done (3 x 1 GiB)")
     t0 = time.time()
     g_in = I.rmat_graph(args.scale, 16, args.seed, device=dev)
     torch.cuda.synchronize()

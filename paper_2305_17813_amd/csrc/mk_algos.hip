@@ -25,13 +25,13 @@ inline uint32_t blocks_for(uint64_t n, uint32_t cap = 4096) {
 }
 
 // Vertices of a view with more than kHeavyBuckets buckets.
-__global__ void k_collect_heavy(const uint2* dir, uint32_t nv, uint32_t* out, uint32_t* cnt) {
+__global__ void k_collect_heavy(const uint32_t* nbk, uint32_t nv, uint32_t* out, uint32_t* cnt) {
   const uint64_t lane = threadIdx.x & 63;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x - lane; base < nv;
        base += stride) {
     const uint64_t v = base + lane;
-    const bool heavy = v < nv && dir[v].y > kHeavyBuckets;
+    const bool heavy = v < nv && nbk[v] > kHeavyBuckets;
     wave_push(out, cnt, heavy, (uint32_t)v);
   }
 }
@@ -77,18 +77,18 @@ __global__ void __launch_bounds__(kBlock) k_wcc_all(DView F, uint32_t* P, uint32
                                                     const uint32_t* heavy, const uint32_t* nheavy) {
   const uint32_t g0 = (blockIdx.x * kBlock + threadIdx.x) / kGroup;
   const uint32_t ng = gridDim.x * kGroupsPerBlock;
-  auto body = [&](uint32_t u, uint64_t x) {
+  auto body = [&](uint32_t u, uint64_t x, bool data) {
     const uint32_t v = (uint32_t)x;
-    if (glane() < kKeysPerSlab && valid_key(v)) uf_union(P, u, v);
+    if (data && valid_key(v)) uf_union(P, u, v);
   };
   for (uint32_t u = g0; u < nv; u += ng) {
-    if (F.dir[u].y > kHeavyBuckets) continue;
-    for_each_slab<false>(F, u, [&](uint64_t x) { body(u, x); });
+    if (F.nbk[u] > kHeavyBuckets || F.deg[u] == 0) continue;
+    for_each_slab(F, u, [&](uint64_t x, bool data) { body(u, x, data); });
   }
   const uint32_t nh = *nheavy, gib = threadIdx.x / kGroup;
   for (uint32_t j = blockIdx.x; j < nh; j += gridDim.x) {
     const uint32_t u = heavy[j];
-    for_each_slab_strided<false>(F, F.dir[u], gib, kGroupsPerBlock, [&](uint64_t x) { body(u, x); });
+    for_each_slab_strided(F, u, gib, kGroupsPerBlock, [&](uint64_t x, bool data) { body(u, x, data); });
   }
 }
 
@@ -161,13 +161,15 @@ __global__ void __launch_bounds__(kBlock) k_pr_gather(DView R, const float* __re
   const uint32_t g0 = (blockIdx.x * kBlock + threadIdx.x) / kGroup;
   const uint32_t ng = gridDim.x * kGroupsPerBlock;
   for (uint32_t v = g0; v < nv; v += ng) {
-    if (R.dir[v].y > kHeavyBuckets) continue;
+    if (R.nbk[v] > kHeavyBuckets) continue;
     double s = 0;
-    for_each_slab<false>(R, v, [&](uint64_t w) {
-      const uint32_t u = (uint32_t)w;
-      if (glane() < kKeysPerSlab && valid_key(u)) s += (double)c[u];
-    });
-    s = gsum(s);
+    if (R.deg[v] != 0) {  // vertices without in-arcs need no slab read
+      for_each_slab(R, v, [&](uint64_t w, bool data) {
+        const uint32_t u = (uint32_t)w;
+        if (data && valid_key(u)) s += (double)c[u];
+      });
+      s = gsum(s);
+    }
     if (glane() == 0) {
       const float nvl = (float)(base + (double)damping * s);
       y[v] = nvl;
@@ -178,9 +180,9 @@ __global__ void __launch_bounds__(kBlock) k_pr_gather(DView R, const float* __re
   for (uint32_t j = blockIdx.x; j < nh; j += gridDim.x) {
     const uint32_t v = heavy[j];
     double s = 0;
-    for_each_slab_strided<false>(R, R.dir[v], gib, kGroupsPerBlock, [&](uint64_t w) {
+    for_each_slab_strided(R, v, gib, kGroupsPerBlock, [&](uint64_t w, bool data) {
       const uint32_t u = (uint32_t)w;
-      if (glane() < kKeysPerSlab && valid_key(u)) s += (double)c[u];
+      if (data && valid_key(u)) s += (double)c[u];
     });
     s = gsum(s);
     __syncthreads();
@@ -243,21 +245,6 @@ __global__ void k_pr_final(const Counters* C, const float* a, const float* b, fl
 }
 
 // ================================================================= triangle counting
-__device__ inline bool lane_has(const DView& V, uint32_t u, uint32_t key) {
-  const uint2 de = V.dir[u];
-  uint32_t s = de.x + bucket_of(key, de.y, V.hash_a, V.hash_b);
-  while (s != kInvalid) {
-    const uint32_t* sp = reinterpret_cast<const uint32_t*>(slab_ptr(V, s));
-    for (int j = 0; j < kKeysPerSlab; ++j) {
-      const uint32_t k = sp[2 * j];
-      if (k == key) return true;
-      if (k == kEmptyKey) return false;
-    }
-    s = sp[30];
-  }
-  return false;
-}
-
 __device__ inline bool ranks_before(const uint32_t* deg, uint32_t a, uint32_t b) {
   const uint32_t da = deg[a], db = deg[b];
   return da < db || (da == db && a < b);
@@ -267,9 +254,9 @@ __device__ inline bool ranks_before(const uint32_t* deg, uint32_t a, uint32_t b)
 // neighbour in b's table.  Returns the group total in every lane.
 __device__ inline uint64_t group_intersect(const DView& U, uint32_t a, uint32_t b) {
   uint64_t c = 0;
-  for_each_slab<false>(U, a, [&](uint64_t x) {
+  for_each_slab(U, a, [&](uint64_t x, bool data) {
     const uint32_t k = (uint32_t)x;
-    if (glane() < kKeysPerSlab && valid_key(k) && k != b) c += lane_has(U, b, k);
+    if (data && valid_key(k) && k != b) c += lane_has(U, b, k);
   });
   return gsum_u64(c);
 }
@@ -280,10 +267,9 @@ __global__ void __launch_bounds__(kBlock) k_tc_static(DView U, uint32_t nv, cons
                                                       unsigned long long* acc) {
   uint64_t local = 0;
   auto per_vertex = [&](uint32_t u, uint32_t b0, uint32_t stride) {
-    const uint2 de = U.dir[u];
-    for_each_slab_strided<false>(U, de, b0, stride, [&](uint64_t x) {
+    for_each_slab_strided(U, u, b0, stride, [&](uint64_t x, bool data) {
       const uint32_t v = (uint32_t)x;
-      uint32_t todo = gballot(glane() < kKeysPerSlab && valid_key(v) && ranks_before(U.deg, u, v));
+      uint32_t todo = gballot(data && valid_key(v) && ranks_before(U.deg, u, v));
       while (todo) {
         const int l = __builtin_ctz(todo);
         todo &= todo - 1;
@@ -296,7 +282,7 @@ __global__ void __launch_bounds__(kBlock) k_tc_static(DView U, uint32_t nv, cons
   const uint32_t g0 = (blockIdx.x * kBlock + threadIdx.x) / kGroup;
   const uint32_t ng = gridDim.x * kGroupsPerBlock;
   for (uint32_t u = g0; u < nv; u += ng) {
-    if (U.dir[u].y > kHeavyBuckets) continue;
+    if (U.nbk[u] > kHeavyBuckets || U.deg[u] < 2) continue;
     per_vertex(u, 0, 1);
   }
   const uint32_t nh = *nheavy, gib = threadIdx.x / kGroup;
@@ -343,9 +329,13 @@ __global__ void __launch_bounds__(kBlock) k_tc_batch(DView U, const uint64_t* ke
     const uint64_t key = keys[i];
     const uint32_t u = (uint32_t)(key >> 32), v = (uint32_t)key;
     if (u >= nv) break;  // sentinels sort last
-    // S1: walk the smaller side, probe the other
-    const bool u_small = U.deg[u] <= U.deg[v];
-    const uint64_t c1 = group_intersect(U, u_small ? u : v, u_small ? v : u);
+    // S1 and S3 are symmetric in (u, v): count them once, on the canonical direction
+    const bool canon = u < v;
+    uint64_t c1 = 0;
+    if (canon) {
+      const bool u_small = U.deg[u] <= U.deg[v];  // walk the smaller side, probe the other
+      c1 = 2 * group_intersect(U, u_small ? u : v, u_small ? v : u);
+    }
     // batch neighbourhoods from the sorted key list
     const uint64_t vlo = lower_bound_u64(keys, nk, (uint64_t)v << 32);
     const uint64_t vhi = lower_bound_u64(keys, nk, ((uint64_t)v + 1) << 32);
@@ -356,8 +346,11 @@ __global__ void __launch_bounds__(kBlock) k_tc_batch(DView U, const uint64_t* ke
       const uint32_t x = (uint32_t)keys[j];
       if (x == u) continue;
       c2 += lane_has(U, u, x);
-      const uint64_t p = lower_bound_u64(keys + ulo, uhi - ulo, ((uint64_t)u << 32) | x);
-      c3 += (p < uhi - ulo) && keys[ulo + p] == (((uint64_t)u << 32) | x);
+      if (canon) {
+        const uint64_t want = ((uint64_t)u << 32) | x;
+        const uint64_t p = lower_bound_u64(keys + ulo, uhi - ulo, want);
+        c3 += 2 * ((p < uhi - ulo) && keys[ulo + p] == want);
+      }
     }
     c2 = gsum_u64(c2);
     c3 = gsum_u64(c3);
@@ -415,7 +408,7 @@ mk_status mk_incr_wcc(mk_graph* g, uint32_t* d_label, mk_mode mode, hipStream_t 
     uint32_t* nh = &g->ctr->pad0[1];
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, nh, 1u);
     hipLaunchKernelGGL(k_collect_heavy, dim3(blocks_for(N)), dim3(kBlock), 0, stream,
-                       g->view[VF].dir, N, g->fq[2], nh);
+                       g->view[VF].nbk, N, g->fq[2], nh);
     hipLaunchKernelGGL(k_wcc_init, dim3(blocks_for(N)), dim3(kBlock), 0, stream, P, N);
     hipLaunchKernelGGL(k_wcc_all, dim3(kWalkBlocks), dim3(kBlock), 0, stream, g->view[VF].d, P, N,
                        g->fq[2], nh);
@@ -451,7 +444,7 @@ mk_status mk_incr_pagerank(mk_graph* g, float damping, double tol_l1, uint32_t m
     hipLaunchKernelGGL(k_pr_fill, dim3(blocks_for(N)), dim3(kBlock), 0, stream, g->pr_x, N, 1.f / N);
   uint32_t* nh = &g->ctr->pad0[2];
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, nh, 1u);
-  hipLaunchKernelGGL(k_collect_heavy, dim3(blocks_for(N)), dim3(kBlock), 0, stream, g->view[VR].dir,
+  hipLaunchKernelGGL(k_collect_heavy, dim3(blocks_for(N)), dim3(kBlock), 0, stream, g->view[VR].nbk,
                      N, g->heavy_rev, nh);
   hipLaunchKernelGGL(k_pr_start, dim3(1), dim3(64), 0, stream, g->ctr);
   MK_LAUNCH(g, "pagerank setup");
@@ -493,7 +486,7 @@ mk_status mk_count_triangles(mk_graph* g, uint64_t* d_count, mk_mode mode, hipSt
   if (full) {
     uint32_t* nh = &g->ctr->pad0[3];
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, nh, 1u);
-    hipLaunchKernelGGL(k_collect_heavy, dim3(blocks_for(N)), dim3(kBlock), 0, stream, U.dir, N,
+    hipLaunchKernelGGL(k_collect_heavy, dim3(blocks_for(N)), dim3(kBlock), 0, stream, U.nbk, N,
                        g->fq[2], nh);
     hipLaunchKernelGGL(k_tc_begin, dim3(1), dim3(64), 0, stream, g->ctr, true);
     hipLaunchKernelGGL(k_tc_static, dim3(kWalkBlocks), dim3(kBlock), 0, stream, U, N, g->fq[2], nh,

@@ -3,8 +3,15 @@
 // Slab geometry (the paper's section 2 slab, redesigned for wave64): one slab is
 // 128 bytes = one L2 line = 16 words of 8 bytes.  A *group* of 16 lanes (one DPP row)
 // reads a slab with one coalesced dwordx2 per lane, so a wave64 runs four independent
-// probes at once.  Word l (l < 15) holds the pair <key, weight> (key in the low half);
-// word 15 holds <next slab index, unused>.  Keys are unordered within a slab.
+// probes at once.  Data words hold the pair <key, weight> (key in the low half); word 15
+// holds <next slab index, meta>.  Keys are unordered within a slab.
+//
+// Head slabs (section 3.1, redesigned so that a probe needs no directory lookup): slab v
+// is the *primary* slab of vertex v and starts bucket 0.  Its word 15 carries the bucket
+// count nb in the meta half.  When nb > 1, word 14 of the primary slab holds the index
+// of the vertex's extra head slabs (buckets 1 .. nb-1, contiguous), so bucket 0 keeps 14
+// data words and every other slab 15.  A vertex with one bucket is therefore probed with
+// a single 128-byte access; any other with at most two.
 //
 // Sentinels (section 2 footnotes): EMPTY key 0xFFFFFFFE (the whole EMPTY word is
 // 0xFFFFFFFF_FFFFFFFE, i.e. UINT64_MAX-1), TOMBSTONE word <0xFFFFFFFD, 0xFFFFFFFD>,
@@ -25,18 +32,18 @@ constexpr uint32_t kTombKey = 0xFFFFFFFDu;
 constexpr uint32_t kInvalid = 0xFFFFFFFFu;
 constexpr uint64_t kEmptyWord = 0xFFFFFFFFFFFFFFFEull;
 constexpr uint64_t kTombWord = 0xFFFFFFFDFFFFFFFDull;
-constexpr uint64_t kNextNone = 0xFFFFFFFFFFFFFFFFull;
+constexpr uint64_t kNextNone = 0xFFFFFFFFFFFFFFFFull;  // word 15 of a non-primary slab
 constexpr uint64_t kTreeNone = 0xFFFFFFFFFFFFFFFFull;  // <INF, INVALID> tree node
 constexpr int kGroup = 16;          // lanes per slab probe
-constexpr int kKeysPerSlab = 15;    // data words per slab
+constexpr int kKeysPerSlab = 15;    // data words per slab (14 in a multi-bucket primary slab)
 constexpr int kBlock = 256;         // threads per block (4 waves, 16 groups)
 constexpr int kGroupsPerBlock = kBlock / kGroup;
 constexpr uint32_t kHeavyBuckets = 16;  // vertices with more buckets are walked by a block
 
 // One view of the graph (forward, reverse or undirected), passed by value to kernels.
 struct DView {
-  const uint2* dir;     // per vertex: x = first head slab, y = bucket count
-  uint64_t* slab;       // slab s occupies words [16 s, 16 s + 16)
+  uint64_t* slab;       // slab s occupies words [16 s, 16 s + 16); slab v is v's primary
+  const uint32_t* nbk;  // bucket count per vertex (a copy of the primary slabs' meta)
   uint32_t* pool_ctr;   // chained slabs handed out so far
   uint32_t pool_base;   // index of the first chained (pool) slab
   uint32_t pool_cap;    // number of pool slabs
@@ -51,6 +58,9 @@ __device__ __host__ inline uint32_t bucket_of(uint32_t key, uint32_t nb, uint64_
 }
 
 __device__ __host__ inline bool valid_key(uint32_t k) { return k < kTombKey; }
+__device__ __host__ inline uint64_t primary_link(uint32_t nb, uint32_t next) {
+  return ((uint64_t)nb << 32) | next;
+}
 
 // ----------------------------------------------------------------- lane helpers
 __device__ inline int lane64() { return (int)__lane_id(); }
@@ -108,15 +118,12 @@ __device__ inline void wave_push(uint32_t* q, uint32_t* ctr, bool p, uint32_t v)
 }
 
 // ----------------------------------------------------------------- memory access
-// Mutating kernels read slab words with agent-scope atomic loads so that a wave on one
-// XCD sees words written by a wave on another XCD (separate L2s); read-only kernels use
-// ordinary cached loads.
-template <bool kCoherent>
+// Slab words are read with relaxed atomic loads of wavefront scope: ordinary cached
+// loads for the hardware, but the compiler may not merge or hoist them across the CASes
+// of a retry loop.  The update protocol never relies on a load being fresh: a stale word
+// only makes a CAS fail, and the CAS returns the true value.
 __device__ inline uint64_t ld_word(const uint64_t* p) {
-  if constexpr (kCoherent)
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  else
-    return *p;
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
 __device__ inline uint32_t ld_u32_coherent(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -135,52 +142,189 @@ __device__ inline uint64_t* slab_ptr(const DView& V, uint32_t s) {
   return V.slab + (uint64_t)s * kGroup;
 }
 
+// The first slab of the bucket of `key` in u's table, its data-word count, and this
+// lane's word of it (one access for single-bucket vertices, two otherwise).
+struct Head {
+  uint32_t s;
+  int nd;
+  uint64_t x;
+};
+__device__ inline Head head_of(const DView& V, uint32_t u, uint32_t key) {
+  const int gl = glane();
+  const uint64_t x = ld_word(slab_ptr(V, u) + gl);
+  const uint32_t nb = (uint32_t)(gbcast64(x, 15) >> 32);
+  if (nb <= 1) return Head{u, kKeysPerSlab, x};
+  const uint32_t b = bucket_of(key, nb, V.hash_a, V.hash_b);
+  if (b == 0) return Head{u, kKeysPerSlab - 1, x};
+  const uint32_t s = gbcast((uint32_t)x, 14) + b - 1;
+  return Head{s, kKeysPerSlab, ld_word(slab_ptr(V, s) + gl)};
+}
+
 // ----------------------------------------------------------------- slab iterator
-// Walk every slab of vertex v (all buckets, each chain to its end), calling f(word) on
-// the 16 lanes of the group for each slab; lanes 0..14 hold the data words.  This is
-// the SlabIterator of section 3.4 (a BucketIterator per bucket, one after the other).
-template <bool kCoherent, class F>
+// Walk every slab of vertex v (all buckets, each chain to its end), calling
+// f(word, is_data) on the 16 lanes of the group for each slab.  This is the SlabIterator
+// of section 3.4 (a BucketIterator per bucket, one after the other).
+template <class F>
+__device__ inline void walk_chain(const DView& V, uint32_t s, uint64_t x, int nd, F&& f) {
+  const int gl = glane();
+  while (true) {
+    f(x, gl < nd);
+    s = gbcast((uint32_t)x, 15);
+    if (s == kInvalid) return;
+    x = ld_word(slab_ptr(V, s) + gl);
+    nd = kKeysPerSlab;
+  }
+}
+
+template <class F>
 __device__ inline void for_each_slab(const DView& V, uint32_t v, F&& f) {
-  const uint2 de = V.dir[v];
-  for (uint32_t b = 0; b < de.y; ++b) {
-    uint32_t s = de.x + b;
-    while (s != kInvalid) {
-      const uint64_t x = ld_word<kCoherent>(slab_ptr(V, s) + glane());
-      f(x);
-      s = gbcast((uint32_t)x, 15);
-    }
+  const int gl = glane();
+  const uint64_t x = ld_word(slab_ptr(V, v) + gl);
+  const uint32_t nb = (uint32_t)(gbcast64(x, 15) >> 32);
+  const uint32_t xb = nb > 1 ? gbcast((uint32_t)x, 14) : 0u;
+  walk_chain(V, v, x, nb > 1 ? kKeysPerSlab - 1 : kKeysPerSlab, f);
+  for (uint32_t b = 1; b < nb; ++b) {
+    const uint32_t s = xb + b - 1;
+    walk_chain(V, s, ld_word(slab_ptr(V, s) + gl), kKeysPerSlab, f);
   }
 }
 
 // Walk the buckets b0, b0+stride, ... of vertex v (used when a block shares one vertex).
-template <bool kCoherent, class F>
-__device__ inline void for_each_slab_strided(const DView& V, uint2 de, uint32_t b0, uint32_t stride,
+template <class F>
+__device__ inline void for_each_slab_strided(const DView& V, uint32_t v, uint32_t b0, uint32_t stride,
                                              F&& f) {
-  for (uint32_t b = b0; b < de.y; b += stride) {
-    uint32_t s = de.x + b;
-    while (s != kInvalid) {
-      const uint64_t x = ld_word<kCoherent>(slab_ptr(V, s) + glane());
-      f(x);
-      s = gbcast((uint32_t)x, 15);
+  const int gl = glane();
+  const uint64_t x = ld_word(slab_ptr(V, v) + gl);
+  const uint32_t nb = (uint32_t)(gbcast64(x, 15) >> 32);
+  const uint32_t xb = nb > 1 ? gbcast((uint32_t)x, 14) : 0u;
+  for (uint32_t b = b0; b < nb; b += stride) {
+    if (b == 0) {
+      walk_chain(V, v, x, nb > 1 ? kKeysPerSlab - 1 : kKeysPerSlab, f);
+    } else {
+      const uint32_t s = xb + b - 1;
+      walk_chain(V, s, ld_word(slab_ptr(V, s) + gl), kKeysPerSlab, f);
     }
   }
 }
 
 // Group-cooperative membership probe (SearchEdge): walk only the hashed chain of `u`.
 // Returns the data word when found, or kEmptyWord when absent.
-template <bool kCoherent>
 __device__ inline uint64_t probe(const DView& V, uint32_t u, uint32_t key) {
-  const uint2 de = V.dir[u];
-  uint32_t s = de.x + bucket_of(key, de.y, V.hash_a, V.hash_b);
+  Head h = head_of(V, u, key);
   const int gl = glane();
+  uint64_t x = h.x;
+  int nd = h.nd;
   while (true) {
-    const uint64_t x = ld_word<kCoherent>(slab_ptr(V, s) + gl);
     const uint32_t k = (uint32_t)x;
-    const uint32_t hit = gballot(gl < kKeysPerSlab && k == key);
+    const uint32_t hit = gballot(gl < nd && k == key);
     if (hit) return gbcast64(x, __builtin_ctz(hit));
-    if (gballot(gl < kKeysPerSlab && k == kEmptyKey)) return kEmptyWord;
-    s = gbcast(k, 15);
+    if (gballot(gl < nd && k == kEmptyKey)) return kEmptyWord;
+    const uint32_t s = gbcast(k, 15);
     if (s == kInvalid) return kEmptyWord;
+    x = ld_word(slab_ptr(V, s) + gl);
+    nd = kKeysPerSlab;
+  }
+}
+
+// Single-lane membership test (each lane probes its own key; used where every lane of a
+// group has a different key, as in triangle counting).
+__device__ inline bool lane_has(const DView& V, uint32_t u, uint32_t key) {
+  const uint32_t* p = reinterpret_cast<const uint32_t*>(slab_ptr(V, u));
+  const uint32_t nb = p[31];
+  uint32_t s = u;
+  int nd = kKeysPerSlab;
+  if (nb > 1) {
+    const uint32_t b = bucket_of(key, nb, V.hash_a, V.hash_b);
+    if (b == 0) nd = kKeysPerSlab - 1;
+    else s = p[28] + b - 1;
+  }
+  while (true) {
+    const uint32_t* sp = reinterpret_cast<const uint32_t*>(slab_ptr(V, s));
+    for (int j = 0; j < nd; ++j) {
+      const uint32_t k = sp[2 * j];
+      if (k == key) return true;
+      if (k == kEmptyKey) return false;
+    }
+    s = sp[30];
+    if (s == kInvalid) return false;
+    nd = kKeysPerSlab;
+  }
+}
+
+
+// ----------------------------------------------------------------- one op per lane
+// Batched insert/delete/query ops are independent and latency-bound, so each lane runs
+// its own op and reads the whole slab itself (8 x 16-byte loads): a wave keeps 64 probes
+// in flight instead of the 4 a 16-lane group gives.
+struct Slab {
+  uint64_t w[16];
+};
+
+__device__ inline void load_slab(const DView& V, uint32_t s, Slab& sl) {
+  const uint4* q = reinterpret_cast<const uint4*>(slab_ptr(V, s));
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const uint4 v = q[i];
+    sl.w[2 * i] = ((uint64_t)v.y << 32) | v.x;
+    sl.w[2 * i + 1] = ((uint64_t)v.w << 32) | v.z;
+  }
+}
+
+// Load the first slab of the bucket of `key` in u's table; returns its index and sets
+// nd (data words) and *extra (1 when a second head access was needed).
+__device__ inline uint32_t lane_head(const DView& V, uint32_t u, uint32_t key, Slab& sl, int& nd,
+                                     uint32_t* extra = nullptr) {
+  load_slab(V, u, sl);
+  const uint32_t nb = (uint32_t)(sl.w[15] >> 32);
+  nd = kKeysPerSlab;
+  if (extra) *extra = 0;
+  if (nb <= 1) return u;
+  const uint32_t b = bucket_of(key, nb, V.hash_a, V.hash_b);
+  if (b == 0) {
+    nd = kKeysPerSlab - 1;
+    return u;
+  }
+  const uint32_t s = (uint32_t)sl.w[14] + b - 1;
+  load_slab(V, s, sl);
+  if (extra) *extra = 1;
+  return s;
+}
+
+// Scan the data words [0, nd) of a slab: index and word of `key` (or -1), and the lowest
+// EMPTY word at or above `floor` (or -1).
+__device__ inline void scan_slab(const Slab& sl, int nd, uint32_t key, int floor, int& hit,
+                                 uint64_t& hitw, int& empty) {
+  hit = -1;
+  empty = -1;
+  hitw = kEmptyWord;
+#pragma unroll
+  for (int i = kKeysPerSlab - 1; i >= 0; --i) {
+    if (i < nd) {
+      const uint32_t k = (uint32_t)sl.w[i];
+      if (k == key) {
+        hit = i;
+        hitw = sl.w[i];
+      }
+      if (k == kEmptyKey && i >= floor) empty = i;
+    }
+  }
+}
+
+// Lane-level SearchEdge: the data word of `key` in u's table, or kEmptyWord.
+__device__ inline uint64_t lane_probe(const DView& V, uint32_t u, uint32_t key) {
+  Slab sl;
+  int nd;
+  lane_head(V, u, key, sl, nd);
+  while (true) {
+    int hit, empty;
+    uint64_t hitw;
+    scan_slab(sl, nd, key, 0, hit, hitw, empty);
+    if (hit >= 0) return hitw;
+    if (empty >= 0) return kEmptyWord;
+    const uint32_t s = (uint32_t)sl.w[15];
+    if (s == kInvalid) return kEmptyWord;
+    load_slab(V, s, sl);
+    nd = kKeysPerSlab;
   }
 }
 

@@ -44,83 +44,79 @@ void mark_seen(mk_graph* g, AlgoState& st) { st.seen_seq = g->next_seq - 1; }
 // ============================================================ device: updates
 namespace {
 
-// Insert <key, w> into u's table.  Returns 1 inserted, 0 already present, 3 pool empty.
-// Progress never depends on a load being fresh: every failed CAS returns the word's true
-// value, and `floor` (lanes of this slab known to be filled) only grows, so a slab is
-// retried at most 15 times.
+// Insert <key, w> into u's table (one lane).  Returns 1 inserted, 0 already present,
+// 3 pool empty.  Progress never depends on a load being fresh: every failed CAS returns
+// the word's true value and `floor` (words of this slab known to be filled) only grows, so
+// a slab is retried at most 15 times.
 __device__ int insert_key(const DView& V, uint32_t u, uint32_t key, uint32_t w) {
-  const uint2 de = V.dir[u];
-  uint32_t s = de.x + bucket_of(key, de.y, V.hash_a, V.hash_b);
+  Slab sl;
+  int nd;
+  uint32_t s = lane_head(V, u, key, sl, nd);
   const uint64_t mine = ((uint64_t)w << 32) | key;
-  const int gl = glane();
   uint32_t spare = kInvalid;
   int floor = 0;
   while (true) {
     uint64_t* sp = slab_ptr(V, s);
-    const uint64_t x = ld_word<true>(sp + gl);
-    const uint32_t k = (uint32_t)x;
-    if (gballot(gl < kKeysPerSlab && k == key)) return 0;
-    const uint32_t em = gballot(gl < kKeysPerSlab && gl >= floor && k == kEmptyKey);
-    if (em) {
-      // the lowest EMPTY lane of the chain: claim it, or learn who did
-      const int e = __builtin_ctz(em);
-      uint64_t old = 0;
-      if (gl == e) old = cas64(sp + e, kEmptyWord, mine);
-      old = gbcast64(old, e);
+    int hit, empty;
+    uint64_t hitw;
+    scan_slab(sl, nd, key, floor, hit, hitw, empty);
+    if (hit >= 0) return 0;
+    if (empty >= 0) {
+      // the lowest EMPTY word of the chain: claim it, or learn who did
+      const uint64_t old = cas64(sp + empty, kEmptyWord, mine);
       if (old == kEmptyWord) return 1;
       if ((uint32_t)old == key) return 0;
-      floor = e + 1;  // another key took the lane: look at the rest of this slab again
+      floor = empty + 1;  // another key took the word: look at the rest of this slab again
+      load_slab(V, s, sl);
       continue;
     }
-    const uint64_t link = gbcast64(x, 15);
+    const uint64_t link = sl.w[15];
     if ((uint32_t)link != kInvalid) {
       s = (uint32_t)link;
       floor = 0;
+      nd = kKeysPerSlab;
+      load_slab(V, s, sl);
       continue;
     }
-    // Full tail: fill a fresh slab with the key in lane 0, publish it, then link it.
+    // Full tail: put the key in word 0 of a fresh slab, then link the slab.  Pool slabs
+    // were filled with EMPTY words and an INVALID link at creation, so word 0 is the only
+    // word to write; writing it with an atomic exchange (performed where the CASes are)
+    // and waiting for its result orders it before the link without an L2 write-back.
     if (spare == kInvalid) {
-      uint32_t got = 0;
-      if (gl == 0) got = atomicAdd(V.pool_ctr, 1u);
-      got = gbcast(got, 0);
+      const uint32_t got = atomicAdd(V.pool_ctr, 1u);
       if (got >= V.pool_cap) return 3;
       spare = V.pool_base + got;
     }
-    uint64_t* np = slab_ptr(V, spare);
-    __hip_atomic_store(np + gl, gl == 0 ? mine : (gl == 15 ? kNextNone : kEmptyWord),
-                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    uint64_t old = 0;
-    if (gl == 15) old = cas64(sp + 15, kNextNone, (kNextNone & 0xFFFFFFFF00000000ull) | spare);
-    old = gbcast64(old, 15);
-    if (old == kNextNone) return 1;
+    const uint64_t prev = atomicExch((unsigned long long*)slab_ptr(V, spare), (unsigned long long)mine);
+    if (prev != kEmptyWord && prev != mine) return 3;  // a pool slab is fresh or our own spare
+    // the link word keeps its meta half (the bucket count of a primary slab)
+    const uint64_t old = cas64(sp + 15, link, (link & 0xFFFFFFFF00000000ull) | spare);
+    if (old == link) return 1;
     s = (uint32_t)old;  // lost the race: continue in the winner's slab, keep the spare
     floor = 0;
+    nd = kKeysPerSlab;
+    load_slab(V, s, sl);
   }
 }
 
-// Delete key from u's table.  Returns 1 deleted, 0 absent; *w_out gets the weight.
+// Delete key from u's table (one lane).  Returns 1 deleted, 0 absent; *w_out gets the weight.
 __device__ int delete_key(const DView& V, uint32_t u, uint32_t key, uint32_t* w_out) {
-  const uint2 de = V.dir[u];
-  uint32_t s = de.x + bucket_of(key, de.y, V.hash_a, V.hash_b);
-  const int gl = glane();
+  Slab sl;
+  int nd;
+  uint32_t s = lane_head(V, u, key, sl, nd);
   while (true) {
-    uint64_t* sp = slab_ptr(V, s);
-    const uint64_t x = ld_word<true>(sp + gl);
-    const uint32_t k = (uint32_t)x;
-    const uint32_t hit = gballot(gl < kKeysPerSlab && k == key);
-    if (hit) {
-      const int e = __builtin_ctz(hit);
-      uint64_t old = 0;
-      if (gl == e) old = cas64(sp + e, x, kTombWord);
-      const uint64_t seen = gbcast64(x, e);
-      old = gbcast64(old, e);
-      *w_out = (uint32_t)(seen >> 32);
-      return old == seen ? 1 : 0;
+    int hit, empty;
+    uint64_t hitw;
+    scan_slab(sl, nd, key, 0, hit, hitw, empty);
+    if (hit >= 0) {
+      *w_out = (uint32_t)(hitw >> 32);
+      return cas64(slab_ptr(V, s) + hit, hitw, kTombWord) == hitw ? 1 : 0;
     }
-    if (gballot(gl < kKeysPerSlab && k == kEmptyKey)) return 0;
-    s = gbcast(k, 15);
+    if (empty >= 0) return 0;
+    s = (uint32_t)sl.w[15];
     if (s == kInvalid) return 0;
+    load_slab(V, s, sl);
+    nd = kKeysPerSlab;
   }
 }
 
@@ -128,124 +124,111 @@ __device__ inline bool bad_arc(uint32_t s, uint32_t d, uint32_t nv) {
   return s >= nv || d >= nv || s == d;  // nv <= 2^30, so reserved ids are >= nv
 }
 
-__global__ void __launch_bounds__(kBlock) k_insert(DView F, DView R, DView U, uint32_t views,
-                                                   const uint32_t* __restrict__ src,
-                                                   const uint32_t* __restrict__ dst,
-                                                   const uint32_t* __restrict__ w, uint64_t n,
-                                                   uint32_t nv, uint8_t* status, Log log,
-                                                   uint32_t* overflow) {
-  const uint64_t op = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kGroup;
+// Forward view of an insert batch, one lane per arc.  Writes the status and the log.
+__global__ void __launch_bounds__(kBlock) k_insert_fwd(DView F, const uint32_t* __restrict__ src,
+                                                       const uint32_t* __restrict__ dst,
+                                                       const uint32_t* __restrict__ w, uint64_t n,
+                                                       uint32_t nv, uint8_t* status, Log log,
+                                                       uint32_t* overflow) {
+  const uint64_t op = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
   if (op >= n) return;
   const uint32_t s = src[op], d = dst[op];
   const uint32_t wt = w ? w[op] : 1u;
-  int st;
-  uint8_t uf = 0;
-  const bool lead = glane() == 0;
-  if (bad_arc(s, d, nv)) {
-    st = 2;
-  } else {
-    st = insert_key(F, s, d, wt);
-    if (st == 1) {
-      if (lead) atomicAdd(F.deg + s, 1u);
-      if (views & MK_VIEW_REV) {
-        const int r = insert_key(R, d, s, wt);
-        if (r == 1 && lead) atomicAdd(R.deg + d, 1u);
-        if (r == 3 && lead) atomicOr(overflow, 2u);
-      }
-      if (views & MK_VIEW_UND) {
-        const uint32_t a = min(s, d), b = max(s, d);
-        const int r1 = insert_key(U, a, b, 1u);  // the canonical direction decides who logs
-        const int r2 = insert_key(U, b, a, 1u);
-        uf = r1 == 1;
-        if (lead) {
-          if (r1 == 1) atomicAdd(U.deg + a, 1u);
-          if (r2 == 1) atomicAdd(U.deg + b, 1u);
-          if (r1 == 3 || r2 == 3) atomicOr(overflow, 4u);
-        }
-      }
-    } else if (st == 3) {
-      if (lead) atomicOr(overflow, 1u);
-    }
-  }
-  if (lead) {
-    if (status) status[op] = (uint8_t)st;
-    if (log.s) {
-      log.s[op] = s;
-      log.d[op] = d;
-      log.w[op] = wt;
-      log.st[op] = (uint8_t)st;
-      log.uf[op] = uf;
-    }
-  }
+  int st = 2;
+  if (!bad_arc(s, d, nv)) st = insert_key(F, s, d, wt);
+  if (st == 1) atomicAdd(F.deg + s, 1u);
+  if (st == 3) atomicOr(overflow, 1u);
+  if (status) status[op] = (uint8_t)st;
+  log.s[op] = s;
+  log.d[op] = d;
+  log.w[op] = wt;
+  log.st[op] = (uint8_t)st;
+  log.uf[op] = 0;
 }
 
-__global__ void __launch_bounds__(kBlock) k_delete(DView F, DView R, uint32_t views,
-                                                   const uint32_t* __restrict__ src,
-                                                   const uint32_t* __restrict__ dst, uint64_t n,
-                                                   uint32_t nv, uint8_t* status, Log log) {
-  const uint64_t op = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kGroup;
+// The other views of an insert batch: three lanes per applied arc (reverse view, and
+// both directions of the undirected view).  The canonical undirected direction (small
+// id -> large id) decides which op reports the undirected edge as new.
+__global__ void __launch_bounds__(kBlock) k_insert_aux(DView R, DView U, uint32_t views, Log log,
+                                                       uint64_t n, uint32_t* overflow) {
+  const uint64_t gid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  const uint64_t op = gid / 3;
+  const int task = (int)(gid % 3);
   if (op >= n) return;
-  const uint32_t s = src[op], d = dst[op];
-  int st;
-  uint32_t wt = 0;
-  const bool lead = glane() == 0;
-  if (bad_arc(s, d, nv)) {
-    st = 2;
-  } else {
-    st = delete_key(F, s, d, &wt);
-    if (st == 1) {
-      if (lead) atomicSub(F.deg + s, 1u);
-      if (views & MK_VIEW_REV) {
-        uint32_t w2;
-        if (delete_key(R, d, s, &w2) == 1 && lead) atomicSub(R.deg + d, 1u);
-      }
-    }
-  }
-  if (lead) {
-    if (status) status[op] = (uint8_t)st;
-    if (log.s) {
-      log.s[op] = s;
-      log.d[op] = d;
-      log.w[op] = wt;
-      log.st[op] = (uint8_t)st;
-      log.uf[op] = 0;
-    }
-  }
-}
-
-// Second pass of a delete batch on the undirected view: {u,v} goes only if the reverse
-// arc is absent once the whole batch has been applied to the forward view.
-__global__ void __launch_bounds__(kBlock) k_delete_und(DView F, DView U, uint64_t n, Log log) {
-  const uint64_t op = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kGroup;
-  if (op >= n) return;
+  if (task == 0 && !(views & MK_VIEW_REV)) return;
+  if (task != 0 && !(views & MK_VIEW_UND)) return;
   if (log.st[op] != 1) return;
   const uint32_t s = log.s[op], d = log.d[op];
-  if (probe<false>(F, d, s) != kEmptyWord) return;
-  const uint32_t a = min(s, d), b = max(s, d);
-  uint32_t w;
-  const int r1 = delete_key(U, a, b, &w);
-  const int r2 = delete_key(U, b, a, &w);
-  if (glane() == 0) {
-    if (r1 == 1) atomicSub(U.deg + a, 1u);
-    if (r2 == 1) atomicSub(U.deg + b, 1u);
-    log.uf[op] = r1 == 1;
+  int r;
+  if (task == 0) {
+    r = insert_key(R, d, s, log.w[op]);
+    if (r == 1) atomicAdd(R.deg + d, 1u);
+  } else {
+    const uint32_t a = task == 1 ? min(s, d) : max(s, d);
+    const uint32_t b = task == 1 ? max(s, d) : min(s, d);
+    r = insert_key(U, a, b, 1u);
+    if (r == 1) atomicAdd(U.deg + a, 1u);
+    if (task == 1) log.uf[op] = r == 1;
   }
+  if (r == 3) atomicOr(overflow, task == 0 ? 2u : 4u);
+}
+
+__global__ void __launch_bounds__(kBlock) k_delete_fwd(DView F, const uint32_t* __restrict__ src,
+                                                       const uint32_t* __restrict__ dst, uint64_t n,
+                                                       uint32_t nv, uint8_t* status, Log log) {
+  const uint64_t op = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (op >= n) return;
+  const uint32_t s = src[op], d = dst[op];
+  int st = 2;
+  uint32_t wt = 0;
+  if (!bad_arc(s, d, nv)) st = delete_key(F, s, d, &wt);
+  if (st == 1) atomicSub(F.deg + s, 1u);
+  if (status) status[op] = (uint8_t)st;
+  log.s[op] = s;
+  log.d[op] = d;
+  log.w[op] = wt;
+  log.st[op] = (uint8_t)st;
+  log.uf[op] = 0;
+}
+
+// The other views of a delete batch, three lanes per deleted arc: the reverse view, and
+// the two directions of the undirected view, where {u,v} goes only if the reverse arc is
+// absent once the whole batch has been applied to the forward view.
+__global__ void __launch_bounds__(kBlock) k_delete_aux(DView F, DView R, DView U, uint32_t views,
+                                                       Log log, uint64_t n) {
+  const uint64_t gid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  const uint64_t op = gid / 3;
+  const int task = (int)(gid % 3);
+  if (op >= n) return;
+  if (task == 0 && !(views & MK_VIEW_REV)) return;
+  if (task != 0 && !(views & MK_VIEW_UND)) return;
+  if (log.st[op] != 1) return;
+  const uint32_t s = log.s[op], d = log.d[op];
+  uint32_t w;
+  if (task == 0) {
+    if (delete_key(R, d, s, &w) == 1) atomicSub(R.deg + d, 1u);
+    return;
+  }
+  if (lane_probe(F, d, s) != kEmptyWord) return;
+  const uint32_t a = task == 1 ? min(s, d) : max(s, d);
+  const uint32_t b = task == 1 ? max(s, d) : min(s, d);
+  const int r = delete_key(U, a, b, &w);
+  if (r == 1) atomicSub(U.deg + a, 1u);
+  if (task == 1) log.uf[op] = r == 1;
 }
 
 __global__ void __launch_bounds__(kBlock) k_query(DView F, const uint32_t* __restrict__ src,
                                                   const uint32_t* __restrict__ dst, uint64_t n,
                                                   uint32_t nv, uint8_t* __restrict__ found,
                                                   uint32_t* __restrict__ wout) {
-  const uint64_t op = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kGroup;
+  const uint64_t op = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
   if (op >= n) return;
   const uint32_t s = src[op], d = dst[op];
   uint64_t x = kEmptyWord;
-  if (!bad_arc(s, d, nv)) x = probe<false>(F, s, d);
-  if (glane() == 0) {
-    const bool f = x != kEmptyWord;
-    found[op] = f;
-    if (wout) wout[op] = f ? (uint32_t)(x >> 32) : 0u;
-  }
+  if (!bad_arc(s, d, nv)) x = lane_probe(F, s, d);
+  const bool f = x != kEmptyWord;
+  found[op] = f;
+  if (wout) wout[op] = f ? (uint32_t)(x >> 32) : 0u;
 }
 
 // ============================================================ device: build
@@ -276,21 +259,31 @@ __global__ void k_count_deg(const uint32_t* __restrict__ src, const uint32_t* __
   }
 }
 
-// bucket_count[v] = max(1, ceil(deg0(v) / (load_factor * 15))), 1 when hashing is off.
-__global__ void k_plan(const uint32_t* cnt, uint32_t nv, float keys_per_bucket, uint32_t* nb) {
+// bucket_count[v] = max(1, ceil(deg0(v) / (load_factor * 15))), 1 when hashing is off;
+// extra[v] = bucket_count[v] - 1 head slabs beyond the primary one.
+__global__ void k_plan(const uint32_t* cnt, uint32_t nv, float keys_per_bucket, uint32_t* nb,
+                       uint32_t* extra) {
   for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
     uint32_t b = 1;
     if (keys_per_bucket > 0.f) b = max(1u, (uint32_t)ceilf((float)cnt[v] / keys_per_bucket));
     nb[v] = b;
+    extra[v] = b - 1;
   }
 }
 
-__global__ void k_pack_dir(const uint32_t* base, const uint32_t* nb, uint32_t nv, uint2* dir,
-                           unsigned long long* total) {
+// Primary slab v: word 15 = <INVALID next, nb>; with several buckets, word 14 holds the
+// index of the extra head slabs.
+__global__ void k_init_primary(uint64_t* slab, const uint32_t* nb, const uint32_t* xrel, uint32_t nv) {
   for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
-    dir[v] = make_uint2(base[v], nb[v]);
-    if (v == nv - 1) *total = (unsigned long long)base[v] + nb[v];
+    uint64_t* p = slab + (uint64_t)v * kGroup;
+    p[15] = primary_link(nb[v], kInvalid);
+    if (nb[v] > 1) p[14] = 0xFFFFFFFF00000000ull | (uint64_t)(nv + xrel[v]);
   }
+}
+
+__global__ void k_extra_total(const uint32_t* nb, const uint32_t* xrel, uint32_t nv,
+                              unsigned long long* total) {
+  if (threadIdx.x == 0) *total = (unsigned long long)xrel[nv - 1] + nb[nv - 1] - 1;
 }
 
 // ============================================================ device: export / stats / check
@@ -300,9 +293,9 @@ __global__ void __launch_bounds__(kBlock) k_export(DView F, uint32_t nv, uint32_
   const uint64_t g0 = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kGroup;
   const uint64_t ng = (uint64_t)gridDim.x * kGroupsPerBlock;
   for (uint64_t v = g0; v < nv; v += ng) {
-    for_each_slab<false>(F, (uint32_t)v, [&](uint64_t x) {
+    for_each_slab(F, (uint32_t)v, [&](uint64_t x, bool data) {
       const uint32_t k = (uint32_t)x;
-      const bool p = glane() < kKeysPerSlab && valid_key(k);
+      const bool p = data && valid_key(k);
       const uint64_t m = __ballot(p);
       if (m == 0) return;
       const int leader = __builtin_ctzll(m);
@@ -327,56 +320,77 @@ __global__ void k_sum_u32(const uint32_t* a, uint32_t n, unsigned long long* out
   if (lane64() == 0 && acc) atomicAdd(out, acc);
 }
 
+// Audit one chain (bucket b of vertex v, head slab s with nd data words).  Returns the
+// violations seen by this lane and adds the live keys to *live.
+__device__ uint32_t check_chain(const DView& V, uint32_t v, uint32_t nb, uint32_t b, uint32_t s, int nd,
+                                uint32_t slab_end, uint32_t* live) {
+  const int gl = glane();
+  uint32_t errs = 0, hops = 0;
+  bool seen_empty = false;
+  const uint32_t head = s;
+  const int head_nd = nd;
+  while (s != kInvalid) {
+    if (++hops > (1u << 22)) return errs + 1;  // a cycle
+    const uint64_t x = slab_ptr(V, s)[gl];
+    const uint32_t k = (uint32_t)x;
+    const bool data = gl < nd;
+    const bool isv = data && valid_key(k);
+    // prefix rule: no filled lane after an EMPTY lane in chain order
+    const uint32_t em = gballot(data && k == kEmptyKey);
+    const uint32_t filled = gballot(data && k != kEmptyKey);
+    if (gl == 0 && seen_empty && filled) errs++;
+    if (em) {
+      if (gl == 0 && (filled >> __builtin_ctz(em))) errs++;
+      seen_empty = true;
+    }
+    if (data && !isv && x != kEmptyWord && x != kTombWord) errs++;
+    if (isv && (nb > 1 ? bucket_of(k, nb, V.hash_a, V.hash_b) : 0u) != b) errs++;
+    if (isv) {  // duplicates: count this lane's key over the whole chain
+      uint32_t occ = 0, t = head, h2 = 0;
+      int tnd = head_nd;
+      while (t != kInvalid && ++h2 < (1u << 22)) {
+        const uint64_t* tp = slab_ptr(V, t);
+        for (int j = 0; j < tnd; ++j) occ += (uint32_t)tp[j] == k;
+        t = (uint32_t)tp[15];
+        if (t != kInvalid && (t < V.pool_base || t >= slab_end)) break;
+        tnd = kKeysPerSlab;
+      }
+      if (occ != 1) errs++;
+    }
+    *live += __popc(gballot(isv));
+    const uint32_t nx = gbcast(k, 15);
+    if (nx != kInvalid && (nx < V.pool_base || nx >= slab_end)) return errs + (gl == 0);
+    if (em && nx != kInvalid && gl == 0) errs++;  // an EMPTY lane is only in the tail
+    s = nx;
+    nd = kKeysPerSlab;
+  }
+  return errs;
+}
+
 // One group per vertex: audit every chain of the vertex's table.
-__global__ void __launch_bounds__(kBlock) k_check(DView V, uint32_t nv, uint32_t pool_used,
-                                                  unsigned long long* bad) {
+__global__ void __launch_bounds__(kBlock) k_check(DView V, uint32_t nv, uint32_t n_head,
+                                                  uint32_t pool_used, unsigned long long* bad) {
   const uint64_t g0 = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kGroup;
   const uint64_t ng = (uint64_t)gridDim.x * kGroupsPerBlock;
   const int gl = glane();
+  const uint32_t slab_end = V.pool_base + pool_used;
   for (uint64_t vv = g0; vv < nv; vv += ng) {
     const uint32_t v = (uint32_t)vv;
-    const uint2 de = V.dir[v];
-    uint32_t live = 0, errs = 0;
-    for (uint32_t b = 0; b < de.y; ++b) {
-      bool seen_empty = false;
-      uint32_t s = de.x + b, hops = 0;
-      while (s != kInvalid) {
-        if (++hops > (1u << 24)) { errs++; break; }  // a cycle
-        const uint64_t x = slab_ptr(V, s)[gl];
-        const uint32_t k = (uint32_t)x;
-        const bool data = gl < kKeysPerSlab;
-        const bool isv = data && valid_key(k);
-        // prefix rule: no filled lane after an EMPTY lane in chain order
-        const uint32_t em = gballot(data && k == kEmptyKey);
-        const uint32_t filled = gballot(data && k != kEmptyKey);
-        if (seen_empty && filled) errs++;
-        if (em) {
-          const uint32_t first_empty = __builtin_ctz(em);
-          if (filled >> first_empty) errs++;
-          seen_empty = true;
-        }
-        if (data && !isv && k != kEmptyKey && x != kTombWord) errs += gl == 0 ? 1 : 0;
-        if (isv && bucket_of(k, de.y, V.hash_a, V.hash_b) != b) errs++;
-        // duplicates: count this lane's key over the whole chain
-        if (isv) {
-          uint32_t occ = 0;
-          uint32_t t = de.x + b, hops2 = 0;
-          while (t != kInvalid && ++hops2 < (1u << 24)) {
-            const uint64_t* tp = slab_ptr(V, t);
-            for (int j = 0; j < kKeysPerSlab; ++j) occ += (uint32_t)tp[j] == k;
-            t = (uint32_t)tp[15];
-            if (t != kInvalid && (t < V.pool_base || t >= V.pool_base + pool_used)) break;
-          }
-          if (occ != 1) errs++;
-        }
-        live += __popc(gballot(isv));
-        const uint32_t nx = gbcast(k, 15);
-        if (nx != kInvalid && (nx < V.pool_base || nx >= V.pool_base + pool_used)) {
-          if (gl == 0) errs++;
-          break;
-        }
-        if (em && nx != kInvalid && gl == 0) errs++;  // an EMPTY lane is only in the tail
-        s = nx;
+    const uint64_t* pp = slab_ptr(V, v);
+    const uint32_t nb = (uint32_t)(pp[15] >> 32);
+    uint32_t errs = 0, live = 0;
+    if (nb != V.nbk[v] || nb == 0) {
+      errs = 1;
+    } else {
+      uint32_t xb = 0;
+      if (nb > 1) {
+        xb = (uint32_t)pp[14];
+        if ((pp[14] >> 32) != 0xFFFFFFFFu || xb < nv || xb + nb - 1 > n_head) errs = 1;
+      }
+      if (!errs) {
+        errs += check_chain(V, v, nb, 0, v, nb > 1 ? kKeysPerSlab - 1 : kKeysPerSlab, slab_end, &live);
+        for (uint32_t b = 1; b < nb; ++b)
+          errs += check_chain(V, v, nb, b, xb + b - 1, kKeysPerSlab, slab_end, &live);
       }
     }
     for (int o = 8; o > 0; o >>= 1) errs += __shfl_xor(errs, o, kGroup);
@@ -387,22 +401,24 @@ __global__ void __launch_bounds__(kBlock) k_check(DView V, uint32_t nv, uint32_t
   }
 }
 
-
 // Byte model: slabs one probe walks (op 0: until found / first EMPTY / end; op 1: to the
-// end of the chain unless the key is found first).
+// end of the chain unless the key is found first).  A second head access counts as a slab.
 __device__ inline uint32_t walk_cost(const DView& V, uint32_t u, uint32_t key, int op) {
-  const uint2 de = V.dir[u];
-  uint32_t s = de.x + bucket_of(key, de.y, V.hash_a, V.hash_b);
-  const int gl = glane();
-  uint32_t slabs = 0;
+  Slab sl;
+  int nd;
+  uint32_t extra;
+  lane_head(V, u, key, sl, nd, &extra);
+  uint32_t slabs = 1 + extra;
   while (true) {
-    const uint64_t x = slab_ptr(V, s)[gl];
-    const uint32_t k = (uint32_t)x;
-    ++slabs;
-    if (gballot(gl < kKeysPerSlab && k == key)) return slabs;
-    if (gballot(gl < kKeysPerSlab && k == kEmptyKey)) return slabs;
-    s = gbcast(k, 15);
+    int hit, empty;
+    uint64_t hitw;
+    scan_slab(sl, nd, key, 0, hit, hitw, empty);
+    if (hit >= 0 || empty >= 0) return slabs;
+    const uint32_t s = (uint32_t)sl.w[15];
     if (s == kInvalid) return slabs;
+    load_slab(V, s, sl);
+    nd = kKeysPerSlab;
+    ++slabs;
   }
 }
 
@@ -410,15 +426,19 @@ __global__ void __launch_bounds__(kBlock) k_probe_cost(DView V, int op, int view
                                                        const uint32_t* __restrict__ src,
                                                        const uint32_t* __restrict__ dst, uint64_t n,
                                                        uint32_t nv, unsigned long long* acc) {
-  const uint64_t i = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kGroup;
-  if (i >= n) return;
-  const uint32_t s = src[i], d = dst[i];
-  if (bad_arc(s, d, nv)) return;
-  uint32_t c;
-  if (view == 0) c = walk_cost(V, s, d, op);
-  else if (view == 1) c = walk_cost(V, d, s, op);
-  else c = walk_cost(V, s, d, op) + walk_cost(V, d, s, op);
-  if (glane() == 0) atomicAdd(acc, (unsigned long long)c);
+  const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  uint32_t c = 0;
+  if (i < n) {
+    const uint32_t s = src[i], d = dst[i];
+    if (!bad_arc(s, d, nv)) {
+      if (view == 0) c = walk_cost(V, s, d, op);
+      else if (view == 1) c = walk_cost(V, d, s, op);
+      else c = walk_cost(V, s, d, op) + walk_cost(V, d, s, op);
+    }
+  }
+  unsigned long long t = c;
+  for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+  if (lane64() == 0 && t) atomicAdd(acc, t);
 }
 
 inline uint32_t grid_stride_blocks(uint64_t n, uint32_t cap = 8192) {
@@ -475,16 +495,16 @@ bool layout(const mk_config* c, uint64_t m, char* base, mk_graph* g, size_t* tot
     const uint64_t hb = head_bound(c, arcs), pc = pool_default(c, arcs);
     if (hb + pc >= 0xFFFFFFF0ull) return false;  // slab indices are u32
     uint64_t* slab = cv.take<uint64_t>((hb + pc) * kGroup);
-    uint2* dir = cv.take<uint2>(N);
+    uint32_t* nbk = cv.take<uint32_t>(N);
     uint32_t* deg = cv.take<uint32_t>(N);
     uint32_t* pctr = cv.take<uint32_t>(64);
     if (g) {
       ViewHost& vh = g->view[v];
       vh.on = true;
-      vh.dir = dir;
+      vh.nbk = nbk;
       vh.head_reserved = hb;
       vh.pool_cap = pc;
-      vh.d.dir = dir;
+      vh.d.nbk = nbk;
       vh.d.slab = slab;
       vh.d.deg = deg;
       vh.d.pool_ctr = pctr;
@@ -616,6 +636,15 @@ Log log_at(const mk_graph* g, uint64_t off) {
 
 DView dv(const mk_graph* g, int v) { return g->view[v].on ? g->view[v].d : g->view[VF].d; }
 
+void launch_insert(mk_graph* g, const uint32_t* s, const uint32_t* d, const uint32_t* w, uint64_t n,
+                   uint8_t* status, const Log& lg, hipStream_t stream) {
+  hipLaunchKernelGGL(k_insert_fwd, dim3(grid_for_lanes(n)), dim3(kBlock), 0, stream, dv(g, VF), s, d, w,
+                     n, g->n, status, lg, &g->ctr->pad0[0]);
+  if (g->view[VR].on || g->view[VU].on)
+    hipLaunchKernelGGL(k_insert_aux, dim3(grid_for_lanes(3 * n)), dim3(kBlock), 0, stream, dv(g, VR),
+                       dv(g, VU), g->cfg.views, lg, n, &g->ctr->pad0[0]);
+}
+
 }  // namespace
 
 // ============================================================ C-ABI
@@ -669,13 +698,20 @@ mk_status mk_graph_create(const mk_config* cfg, void* d_arena, size_t arena_byte
   for (int v = 0; v < 3; ++v) {
     ViewHost& vh = g->view[v];
     if (!vh.on) continue;
-    hipLaunchKernelGGL(k_plan, dim3(nb_blocks), dim3(kBlock), 0, stream, vh.d.deg, N, kpb, g->fq[0]);
+    hipLaunchKernelGGL(k_plan, dim3(nb_blocks), dim3(kBlock), 0, stream, vh.d.deg, N, kpb, vh.nbk,
+                       g->fq[0]);
     size_t tb = g->scan_tmp_bytes;
-    if (rocprim::exclusive_scan(g->scan_tmp, tb, g->fq[0], g->fq[1], 0u, (size_t)N,
+    if (rocprim::exclusive_scan(g->scan_tmp, tb, g->fq[0], g->fq[1 + v], 0u, (size_t)N,
                                 rocprim::plus<uint32_t>(), stream) != hipSuccess)
       return fail(MK_ERR_HIP);
-    hipLaunchKernelGGL(k_pack_dir, dim3(nb_blocks), dim3(kBlock), 0, stream, g->fq[1], g->fq[0], N,
-                       vh.dir, &g->ctr->u64tmp[v]);
+  }
+  // extra head slabs per view: read back the scan totals to place the pools
+  for (int v = 0; v < 3; ++v) {
+    ViewHost& vh = g->view[v];
+    if (!vh.on) continue;
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, stream, (uint32_t*)&g->ctr->u64tmp[v], 2, 0u);
+    hipLaunchKernelGGL(k_extra_total, dim3(1), dim3(64), 0, stream, vh.nbk, g->fq[1 + v], N,
+                       &g->ctr->u64tmp[v]);
   }
   if (hipMemcpyAsync(g->h_pin, g->ctr->u64tmp, 3 * sizeof(uint64_t), hipMemcpyDeviceToHost,
                      stream) != hipSuccess ||
@@ -684,19 +720,21 @@ mk_status mk_graph_create(const mk_config* cfg, void* d_arena, size_t arena_byte
   for (int v = 0; v < 3; ++v) {
     ViewHost& vh = g->view[v];
     if (!vh.on) continue;
-    vh.n_head = g->h_pin[v];
+    vh.n_head = (uint64_t)N + g->h_pin[v];
     if (vh.n_head > vh.head_reserved) return fail(MK_ERR_CAPACITY);
     vh.d.pool_base = (uint32_t)vh.n_head;
     hipLaunchKernelGGL(k_fill_slabs, dim3(grid_stride_blocks((vh.n_head + vh.pool_cap) * kGroup)),
                        dim3(kBlock), 0, stream, vh.d.slab, (vh.n_head + vh.pool_cap) * kGroup);
+    hipLaunchKernelGGL(k_init_primary, dim3(nb_blocks), dim3(kBlock), 0, stream, vh.d.slab, vh.nbk,
+                       g->fq[1 + v], N);
     hipLaunchKernelGGL(k_fill_u32, dim3(nb_blocks), dim3(kBlock), 0, stream, vh.d.deg, N, 0u);
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, stream, vh.d.pool_ctr, 64, 0u);
   }
   hipLaunchKernelGGL(k_fill_u32, dim3(nb_blocks), dim3(kBlock), 0, stream, g->mark, N, 0u);
-  if (m) {
-    hipLaunchKernelGGL(k_insert, dim3(grid_for_groups(m)), dim3(kBlock), 0, stream, dv(g, VF),
-                       dv(g, VR), dv(g, VU), g->cfg.views, d_src, d_dst, d_w, m, N, nullptr, Log{},
-                       &g->ctr->pad0[0]);
+  // bulk insert, in chunks that fit the change log (used here as scratch)
+  for (uint64_t off = 0; off < m; off += g->log_cap) {
+    const uint64_t k = std::min<uint64_t>(g->log_cap, m - off);
+    launch_insert(g, d_src + off, d_dst + off, d_w ? d_w + off : nullptr, k, nullptr, g->log, stream);
   }
   if (hipGetLastError() != hipSuccess) return fail(MK_ERR_HIP);
   if (refresh_pool(g, stream) != MK_OK) return fail(MK_ERR_HIP);
@@ -720,9 +758,7 @@ mk_status mk_insert_edges(mk_graph* g, const uint32_t* d_src, const uint32_t* d_
   mk_status st = ensure_pool(g, n, stream);
   if (st != MK_OK) return st;
   const uint64_t off = reserve_log(g, n);
-  hipLaunchKernelGGL(k_insert, dim3(grid_for_groups(n)), dim3(kBlock), 0, stream, dv(g, VF),
-                     dv(g, VR), dv(g, VU), g->cfg.views, d_src, d_dst, d_w, n, g->n, d_status,
-                     log_at(g, off), &g->ctr->pad0[0]);
+  launch_insert(g, d_src, d_dst, d_w, n, d_status, log_at(g, off), stream);
   MK_LAUNCH(g, "k_insert");
   for (int v = 0; v < 3; ++v)
     if (g->view[v].on) g->view[v].pool_used_est += v == VU ? 2 * n : n;
@@ -740,13 +776,13 @@ mk_status mk_delete_edges(mk_graph* g, const uint32_t* d_src, const uint32_t* d_
   if (n > g->log_cap) return MK_ERR_CAPACITY;
   const uint64_t off = reserve_log(g, n);
   const Log lg = log_at(g, off);
-  hipLaunchKernelGGL(k_delete, dim3(grid_for_groups(n)), dim3(kBlock), 0, stream, dv(g, VF),
-                     dv(g, VR), g->cfg.views, d_src, d_dst, n, g->n, d_status, lg);
-  MK_LAUNCH(g, "k_delete");
-  if (g->view[VU].on) {
-    hipLaunchKernelGGL(k_delete_und, dim3(grid_for_groups(n)), dim3(kBlock), 0, stream, dv(g, VF),
-                       dv(g, VU), n, lg);
-    MK_LAUNCH(g, "k_delete_und");
+  hipLaunchKernelGGL(k_delete_fwd, dim3(grid_for_lanes(n)), dim3(kBlock), 0, stream, dv(g, VF),
+                     d_src, d_dst, n, g->n, d_status, lg);
+  MK_LAUNCH(g, "k_delete_fwd");
+  if (g->view[VR].on || g->view[VU].on) {
+    hipLaunchKernelGGL(k_delete_aux, dim3(grid_for_lanes(3 * n)), dim3(kBlock), 0, stream, dv(g, VF),
+                       dv(g, VR), dv(g, VU), g->cfg.views, lg, n);
+    MK_LAUNCH(g, "k_delete_aux");
   }
   g->batches.push_back(BatchRec{kDeleteBatch, off, n, g->next_seq++});
   g->log_tail = off + n;
@@ -759,7 +795,7 @@ mk_status mk_query_edges(mk_graph* g, const uint32_t* d_src, const uint32_t* d_d
   if (!g) return MK_ERR_INVALID_ARG;
   if (n == 0) return MK_OK;
   if (!d_src || !d_dst || !d_found) return MK_ERR_INVALID_ARG;
-  hipLaunchKernelGGL(k_query, dim3(grid_for_groups(n)), dim3(kBlock), 0, stream, dv(g, VF), d_src,
+  hipLaunchKernelGGL(k_query, dim3(grid_for_lanes(n)), dim3(kBlock), 0, stream, dv(g, VF), d_src,
                      d_dst, n, g->n, d_found, d_w);
   MK_LAUNCH(g, "k_query");
   return MK_OK;
@@ -816,7 +852,7 @@ mk_status mk_graph_check(mk_graph* g, uint64_t* h_bad, hipStream_t stream) {
   for (int v = 0; v < 3; ++v) {
     if (!g->view[v].on) continue;
     hipLaunchKernelGGL(k_check, dim3(grid_for_groups(std::min<uint64_t>(g->n, 1u << 20))),
-                       dim3(kBlock), 0, stream, g->view[v].d, g->n,
+                       dim3(kBlock), 0, stream, g->view[v].d, g->n, (uint32_t)g->view[v].n_head,
                        (uint32_t)g->view[v].pool_used_est, bad);
     MK_LAUNCH(g, "k_check");
   }
@@ -835,7 +871,7 @@ mk_status mk_probe_cost(mk_graph* g, int op, int view, const uint32_t* d_src, co
   if (!d_src || !d_dst) return MK_ERR_INVALID_ARG;
   unsigned long long* acc = &g->ctr->u64tmp[1];
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, stream, (uint32_t*)acc, 2, 0u);
-  hipLaunchKernelGGL(k_probe_cost, dim3(grid_for_groups(n)), dim3(kBlock), 0, stream, g->view[view].d,
+  hipLaunchKernelGGL(k_probe_cost, dim3(grid_for_lanes(n)), dim3(kBlock), 0, stream, g->view[view].d,
                      op, view, d_src, d_dst, n, g->n, acc);
   MK_LAUNCH(g, "k_probe_cost");
   MK_HIP(g, hipMemcpyAsync(g->h_pin, acc, 8, hipMemcpyDeviceToHost, stream));

@@ -28,9 +28,9 @@ struct Log {
 struct ViewHost {
   bool on = false;
   DView d{};
-  uint2* dir = nullptr;
+  uint32_t* nbk = nullptr;     // bucket count per vertex
   uint64_t head_reserved = 0;  // head slabs the arena reserves (upper bound)
-  uint64_t n_head = 0;         // head slabs in use
+  uint64_t n_head = 0;         // head slabs in use (N primary + extra)
   uint64_t pool_cap = 0;       // chained slabs
   uint64_t pool_used_est = 0;  // host-side upper bound of the pool counter
 };
@@ -113,6 +113,7 @@ mk_status hip_fail(mk_graph* g, hipError_t e, const char* what);
     if (_e != hipSuccess) return mk::hip_fail(g, _e, what);  \
   } while (0)
 
+inline uint32_t grid_for_lanes(uint64_t lanes) { return (uint32_t)((lanes + kBlock - 1) / kBlock); }
 inline uint32_t grid_for_groups(uint64_t groups) {
   return (uint32_t)((groups + kGroupsPerBlock - 1) / kGroupsPerBlock);
 }

@@ -32,12 +32,12 @@ __device__ inline uint64_t tree_node(uint64_t dist, uint32_t parent) {
   return (dist << 32) | parent;
 }
 
-__device__ inline void push_vertex(const uint2* dir, uint32_t* Lq, uint32_t* Lc, uint32_t* Hq,
+__device__ inline void push_vertex(const uint32_t* nbk, uint32_t* Lq, uint32_t* Lc, uint32_t* Hq,
                                    uint32_t* Hc, uint32_t* mark, uint32_t stamp, bool p, uint32_t v) {
   bool take = false;
   if (p) take = atomicExch(mark + v, stamp) != stamp;
   bool heavy = false;
-  if (take) heavy = dir[v].y > kHeavyBuckets;
+  if (take) heavy = nbk[v] > kHeavyBuckets;
   wave_push(Lq, Lc, take && !heavy, v);
   wave_push(Hq, Hc, take && heavy, v);
 }
@@ -54,15 +54,15 @@ struct Queues {
 // Relax every out-arc of u held in one slab word per lane.
 template <bool kUnit>
 __device__ inline void relax_word(const DView& F, uint64_t* D, uint32_t u, uint64_t du, uint64_t x,
-                                  const Queues& q, uint32_t* mark, uint32_t stamp) {
+                                  bool data, const Queues& q, uint32_t* mark, uint32_t stamp) {
   const uint32_t v = (uint32_t)x;
   bool improve = false;
-  if (glane() < kKeysPerSlab && valid_key(v)) {
+  if (data && valid_key(v)) {
     const uint64_t w = kUnit ? 1ull : (x >> 32);
     const uint64_t cand = tree_node(du + w, u);
     if (cand < D[v]) improve = amin64(D + v, cand) > cand;
   }
-  push_vertex(F.dir, q.Lnext, q.cnt + q.inext, q.Hnext, q.cnt + 3 + q.inext, mark, stamp, improve, v);
+  push_vertex(F.nbk, q.Lnext, q.cnt + q.inext, q.Hnext, q.cnt + 3 + q.inext, mark, stamp, improve, v);
 }
 
 template <bool kUnit>
@@ -79,14 +79,14 @@ __global__ void __launch_bounds__(kBlock) k_expand(DView F, uint64_t* D, Queues 
   for (uint32_t i = g0; i < nl; i += ng) {
     const uint32_t u = q.Lcur[i];
     const uint64_t du = ld_u64_coherent(D + u) >> 32;
-    for_each_slab<false>(F, u, [&](uint64_t x) { relax_word<kUnit>(F, D, u, du, x, q, mark, stamp); });
+    for_each_slab(F, u, [&](uint64_t x, bool data) { relax_word<kUnit>(F, D, u, du, x, data, q, mark, stamp); });
   }
   const uint32_t gib = threadIdx.x / kGroup;
   for (uint32_t j = blockIdx.x; j < nh; j += gridDim.x) {
     const uint32_t u = q.Hcur[j];
     const uint64_t du = ld_u64_coherent(D + u) >> 32;
-    for_each_slab_strided<false>(F, F.dir[u], gib, kGroupsPerBlock, [&](uint64_t x) {
-      relax_word<kUnit>(F, D, u, du, x, q, mark, stamp);
+    for_each_slab_strided(F, u, gib, kGroupsPerBlock, [&](uint64_t x, bool data) {
+      relax_word<kUnit>(F, D, u, du, x, data, q, mark, stamp);
     });
   }
 }
@@ -106,7 +106,7 @@ __global__ void k_seed_source(DView F, uint32_t src, uint32_t* Lq, uint32_t* Hq,
                               uint32_t* mark, uint32_t stamp) {
   if (threadIdx.x != 0) return;
   mark[src] = stamp;
-  if (F.dir[src].y > kHeavyBuckets) {
+  if (F.nbk[src] > kHeavyBuckets) {
     Hq[0] = src;
     cnt[3] = 1;
   } else {
@@ -136,7 +136,7 @@ __global__ void k_relax_batch(DView F, uint64_t* D, Log lg, uint64_t n, uint32_t
         if (cand < D[v]) improve = amin64(D + v, cand) > cand;
       }
     }
-    push_vertex(F.dir, Lq, cnt, Hq, cnt + 3, mark, stamp, improve, v);
+    push_vertex(F.nbk, Lq, cnt, Hq, cnt + 3, mark, stamp, improve, v);
   }
 }
 
@@ -158,23 +158,23 @@ __global__ void k_invalidate(DView F, uint64_t* D, Log lg, uint64_t n, uint32_t*
       if (dv != kTreeNone && (uint32_t)dv == u) hit = cas64(D + v, dv, kTreeNone) == dv;
     }
     wave_push(inval, inval_cnt, hit, v);
-    push_vertex(F.dir, Lq, cnt, Hq, cnt + 3, mark, stamp, hit, v);
+    push_vertex(F.nbk, Lq, cnt, Hq, cnt + 3, mark, stamp, hit, v);
   }
 }
 
 // Delete prologue, step 2: invalidate the subtree below each invalidated vertex x (its
 // tree children are the out-neighbours y whose parent is x).
 __device__ inline void inval_word(const DView& F, uint64_t* D, uint32_t x_parent, uint64_t w,
-                                  const Queues& q, uint32_t* inval, uint32_t* inval_cnt,
+                                  bool data, const Queues& q, uint32_t* inval, uint32_t* inval_cnt,
                                   uint32_t* mark, uint32_t stamp) {
   const uint32_t y = (uint32_t)w;
   bool hit = false;
-  if (glane() < kKeysPerSlab && valid_key(y)) {
+  if (data && valid_key(y)) {
     const uint64_t dy = ld_u64_coherent(D + y);
     if (dy != kTreeNone && (uint32_t)dy == x_parent) hit = cas64(D + y, dy, kTreeNone) == dy;
   }
   wave_push(inval, inval_cnt, hit, y);
-  push_vertex(F.dir, q.Lnext, q.cnt + q.inext, q.Hnext, q.cnt + 3 + q.inext, mark, stamp, hit, y);
+  push_vertex(F.nbk, q.Lnext, q.cnt + q.inext, q.Hnext, q.cnt + 3 + q.inext, mark, stamp, hit, y);
 }
 
 __global__ void __launch_bounds__(kBlock) k_propagate(DView F, uint64_t* D, Queues q, uint32_t* inval,
@@ -190,13 +190,15 @@ __global__ void __launch_bounds__(kBlock) k_propagate(DView F, uint64_t* D, Queu
   const uint32_t ng = gridDim.x * kGroupsPerBlock;
   for (uint32_t i = g0; i < nl; i += ng) {
     const uint32_t x = q.Lcur[i];
-    for_each_slab<false>(F, x, [&](uint64_t w) { inval_word(F, D, x, w, q, inval, inval_cnt, mark, stamp); });
+    for_each_slab(F, x, [&](uint64_t w, bool data) {
+      inval_word(F, D, x, w, data, q, inval, inval_cnt, mark, stamp);
+    });
   }
   const uint32_t gib = threadIdx.x / kGroup;
   for (uint32_t j = blockIdx.x; j < nh; j += gridDim.x) {
     const uint32_t x = q.Hcur[j];
-    for_each_slab_strided<false>(F, F.dir[x], gib, kGroupsPerBlock, [&](uint64_t w) {
-      inval_word(F, D, x, w, q, inval, inval_cnt, mark, stamp);
+    for_each_slab_strided(F, x, gib, kGroupsPerBlock, [&](uint64_t w, bool data) {
+      inval_word(F, D, x, w, data, q, inval, inval_cnt, mark, stamp);
     });
   }
 }
@@ -214,9 +216,9 @@ __global__ void __launch_bounds__(kBlock) k_dec_pull(DView F, DView R, uint64_t*
   for (uint32_t i = g0; i < n; i += ng) {
     const uint32_t y = inval[i];
     uint64_t best = kTreeNone;
-    for_each_slab<false>(R, y, [&](uint64_t x) {
+    for_each_slab(R, y, [&](uint64_t x, bool data) {
       const uint32_t u = (uint32_t)x;
-      if (glane() < kKeysPerSlab && valid_key(u)) {
+      if (data && valid_key(u)) {
         const uint64_t du = ld_u64_coherent(D + u);
         if (du != kTreeNone) {
           const uint64_t cand = tree_node((du >> 32) + (kUnit ? 1ull : (x >> 32)), u);
@@ -227,7 +229,7 @@ __global__ void __launch_bounds__(kBlock) k_dec_pull(DView F, DView R, uint64_t*
     best = gmin_u64(best);
     bool improve = false;
     if (glane() == 0 && best != kTreeNone) improve = amin64(D + y, best) > best;
-    push_vertex(F.dir, Lq, cnt, Hq, cnt + 3, mark, stamp, improve, y);
+    push_vertex(F.nbk, Lq, cnt, Hq, cnt + 3, mark, stamp, improve, y);
   }
 }
 
