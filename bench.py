@@ -31,6 +31,38 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def kernel_source_hash() -> str:
+    """Hash of the HIP sources and the C-ABI header (identifies the kernels profiled)."""
+    import glob
+    import hashlib
+
+    here = os.path.dirname(os.path.abspath(__file__))
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(here, "paper_2305_17813_amd", "csrc", "*")))
+    for f in files + [os.path.join(here, "include", "meerkat_mi355x.h")]:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(kernels):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or
+    None when the kernels changed since the counters were taken."""
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", "rmat_s22_step_hbm_counters.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    try:
+        return sum(rec["kernels"][k]["traffic_bytes"] for k in kernels)
+    except KeyError:
+        return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -193,22 +225,24 @@ def main():
     q_ms = med(times["query"])
     del_ms = med(times["delete"])
     roof = {
-        "kernel": "k_insert (fwd+rev+und views)",
+        "kernel": "insert call = k_insert_fwd + k_insert_aux (fwd, rev, und views)",
         "bound": "hbm",
         "achieved": i_bytes / (ins_ms / 1e3) / 1e9,
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
-        "traffic": None,
+        "traffic": counter_traffic(["k_insert_fwd", "k_insert_aux"]),
         "bytes_per_launch": i_bytes,
         "launch_ms": ins_ms,
     }
     roof["frac"] = roof["achieved"] / roof["peak"]
     rooflines = {
         "k_query": {"achieved": q_bytes / (q_ms / 1e3) / 1e9, "bytes_per_launch": q_bytes, "launch_ms": q_ms,
-                    "slabs_per_op": slabs["q_fwd"] / Q},
-        "k_delete+k_delete_und": {"achieved": d_bytes / (del_ms / 1e3) / 1e9, "bytes_per_launch": d_bytes,
-                                  "launch_ms": del_ms},
-        "k_insert": {"achieved": roof["achieved"], "bytes_per_launch": i_bytes, "launch_ms": ins_ms,
+                    "slabs_per_op": slabs["q_fwd"] / Q, "traffic": counter_traffic(["k_query"])},
+        "k_delete_fwd+k_delete_aux": {"achieved": d_bytes / (del_ms / 1e3) / 1e9, "bytes_per_launch": d_bytes,
+                                      "launch_ms": del_ms,
+                                      "traffic": counter_traffic(["k_delete_fwd", "k_delete_aux"])},
+        "k_insert_fwd+k_insert_aux": {"achieved": roof["achieved"], "bytes_per_launch": i_bytes, "launch_ms": ins_ms,
+                                      "traffic": roof["traffic"],
                      "slabs_per_op": {k: slabs[k] / B for k in ("i_fwd", "i_rev", "i_und")}},
     }
     for r in rooflines.values():
@@ -244,6 +278,7 @@ def main():
         "pagerank_iters": pr_iters,
         "build_s": build_s,
         "roofline": roof,
+        "kernel_source_hash": kernel_source_hash(),
         "rooflines": rooflines,
     }
 
