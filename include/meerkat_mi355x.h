@@ -190,6 +190,56 @@ mk_status mk_graph_stats(mk_graph* g, mk_stats* h_out, hipStream_t stream);
  * number of violations (0 when sound).  Synchronizes. */
 mk_status mk_graph_check(mk_graph* g, uint64_t* h_bad, hipStream_t stream);
 
+/* ---------------------------------------------------------------- cost model
+ * A small MLP (MK_MLP_IN -> 64 -> 64 -> MK_MLP_OUT, ReLU, FP32) that predicts, from the
+ * features of a pending batch, log(ms) of the incremental path, log(ms) of a recompute,
+ * and log2 of the initial slab-count scale.  It picks MK_INCR or MK_RECOMPUTE per
+ * algorithm and batch; the plain always-incremental rule is the fallback.  This is not
+ * in the paper: its own measurements show incremental BFS/SSSP losing to recompute on
+ * road networks (dynamic-vs-static speedups below 1 in the BFS and SSSP figures).
+ * Parameters: MK_MLP_PARAMS floats, W1[64][12], b1[64], W2[64][64], b2[64], W3[3][64],
+ * b3[3], row-major (output x input). */
+#define MK_MLP_IN 12
+#define MK_MLP_HIDDEN 64
+#define MK_MLP_OUT 3
+#define MK_MLP_PARAMS 5187
+
+enum { MK_ALGO_BFS = 0, MK_ALGO_SSSP = 1, MK_ALGO_WCC = 2, MK_ALGO_PAGERANK = 3, MK_ALGO_TC = 4 };
+
+/* Features of a batch about to be applied, for algorithm `algo` (MK_ALGO_*), into
+ * h_out[MK_MLP_IN] (host): log2(1+ops), insert and delete fractions, log2 N, log2(1+arcs),
+ * mean and max log2(1+out-degree) of the touched sources, mean log2(1+in-degree) of the
+ * touched destinations, the affected fraction (BFS/SSSP: inserted arcs that would relax
+ * plus deleted tree arcs; WCC: inserted arcs joining two components plus deletions;
+ * PageRank: mean 1/(1+out-degree) of the sources; triangles: mean log2(1+smaller
+ * undirected degree)), log2(1+deepest finite distance of the algorithm's tree), log2(1+
+ * pending batches) and algo/4; every log2 figure is divided by 32 so that the features lie
+ * roughly in [0, 1].  Either part may be empty (n = 0, pointers NULL).
+ * Synchronizes. */
+mk_status mk_batch_features(mk_graph* g, int algo, const uint32_t* d_ins_src, const uint32_t* d_ins_dst,
+                            const uint32_t* d_ins_w, uint64_t n_ins, const uint32_t* d_del_src,
+                            const uint32_t* d_del_dst, uint64_t n_del, float* h_out, hipStream_t stream);
+
+/* Bytes of device workspace mk_mlp_grad needs for a minibatch of n samples. */
+size_t mk_mlp_workspace_bytes(uint32_t n);
+
+/* Forward pass: d_x [n][MK_MLP_IN] -> d_y [n][MK_MLP_OUT] (device, FP32). */
+mk_status mk_mlp_forward(const float* d_params, const float* d_x, uint32_t n, float* d_y,
+                         hipStream_t stream);
+
+/* Gradient of the masked mean squared error L = sum m (y - t)^2 / sum m over a minibatch
+ * (d_t and d_mask are [n][MK_MLP_OUT]; a mask entry of 0 leaves that output unsupervised).
+ * Writes d_grad [MK_MLP_PARAMS] (overwritten, not accumulated) and *d_loss (device double).
+ * d_ws: device workspace of ws_bytes >= mk_mlp_workspace_bytes(n).  Deterministic. */
+mk_status mk_mlp_grad(const float* d_params, const float* d_x, const float* d_t, const float* d_mask,
+                      uint32_t n, float* d_grad, void* d_ws, size_t ws_bytes, double* d_loss,
+                      hipStream_t stream);
+
+/* One Adam step (Kingma and Ba, with bias correction; `step` counts from 1) on n_params
+ * parameters with first and second moment buffers d_m, d_v (device, FP32). */
+mk_status mk_mlp_adam(float* d_params, const float* d_grad, float* d_m, float* d_v, uint32_t n_params,
+                      float lr, float beta1, float beta2, float eps, uint32_t step, hipStream_t stream);
+
 /* Human-readable name of a status; the last HIP error text for MK_ERR_HIP. */
 const char* mk_status_string(mk_status s);
 

@@ -1,0 +1,217 @@
+"""Learned incremental-versus-recompute cost model.
+
+An MLP (12 -> 64 -> 64 -> 3, ReLU, FP32) reads the features of a pending batch
+(`Graph.batch_features`, computed by a HIP kernel) and predicts log(ms) of the incremental
+path, log(ms) of a recompute and log2 of the initial slab-count scale.  Its forward pass,
+gradient and Adam step are the library's HIP kernels (`mk_mlp_forward`, `mk_mlp_grad`,
+`mk_mlp_adam`); this module marshals tensors, draws minibatches and keeps the records.
+
+The training records come from the method itself: `generate_records` applies seeded
+batches (sizes log-uniform, delete fraction uniform) to a graph and times, with HIP
+events, each algorithm's incremental update (after the insert part and after the delete
+part) and a recompute on the same graph state.  The fallback policy and the baseline of
+the regret is the plain rule of the paper: always incremental.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+import torch
+
+from . import native
+from .native import _check, _ptr, load
+
+N_IN, N_HID, N_OUT, N_PARAMS = 12, 64, 3, 5187
+ALGOS = ["bfs", "sssp", "wcc", "pagerank", "tc"]
+
+
+class MLP:
+    """Parameters, Adam moments and the training loop around the HIP kernels."""
+
+    def __init__(self, device="cuda", seed: int = 0):
+        self.lib = load()
+        self.device = torch.device(device)
+        g = torch.Generator().manual_seed(seed)
+        parts = []
+        for fan_out, fan_in, scale in [(N_HID, N_IN, math.sqrt(2.0 / N_IN)),
+                                       (N_HID, N_HID, math.sqrt(2.0 / N_HID)),
+                                       (N_OUT, N_HID, math.sqrt(1.0 / N_HID))]:
+            parts.append(torch.randn(fan_out * fan_in, generator=g) * scale)
+            parts.append(torch.zeros(fan_out))
+        self.params = torch.cat(parts).float().to(self.device).contiguous()
+        assert self.params.numel() == N_PARAMS
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.grad = torch.zeros_like(self.params)
+        self.loss = torch.zeros(2, dtype=torch.float64, device=self.device)
+        self.step = 0
+        self.ws = None
+
+    def _s(self):
+        return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def forward(self, X: torch.Tensor) -> torch.Tensor:
+        X = X.to(self.device, torch.float32).contiguous()
+        Y = torch.empty(X.shape[0], N_OUT, dtype=torch.float32, device=self.device)
+        _check(self.lib.mk_mlp_forward(_ptr(self.params), _ptr(X), X.shape[0], _ptr(Y), self._s()),
+               "mk_mlp_forward")
+        return Y
+
+    def gradient(self, X, T, M):
+        """Gradient of the masked MSE into self.grad; returns the loss (device tensor)."""
+        n = X.shape[0]
+        need = self.lib.mk_mlp_workspace_bytes(n)
+        if self.ws is None or self.ws.numel() < need:
+            self.ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        _check(self.lib.mk_mlp_grad(_ptr(self.params), _ptr(X), _ptr(T), _ptr(M), n, _ptr(self.grad),
+                                    _ptr(self.ws), self.ws.numel(), _ptr(self.loss), self._s()),
+               "mk_mlp_grad")
+        return self.loss[0]
+
+    def adam(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        self.step += 1
+        _check(self.lib.mk_mlp_adam(_ptr(self.params), _ptr(self.grad), _ptr(self.m), _ptr(self.v),
+                                    N_PARAMS, lr, b1, b2, eps, self.step, self._s()), "mk_mlp_adam")
+
+    def train(self, X, T, M, epochs=200, batch=256, lr=3e-3, seed=0) -> List[float]:
+        X = X.to(self.device, torch.float32).contiguous()
+        T = T.to(self.device, torch.float32).contiguous()
+        M = M.to(self.device, torch.float32).contiguous()
+        n = X.shape[0]
+        g = torch.Generator().manual_seed(seed)
+        hist = []
+        for ep in range(epochs):
+            order = torch.randperm(n, generator=g).to(self.device)
+            tot = 0.0
+            for i in range(0, n, batch):
+                idx = order[i:i + batch]
+                loss = self.gradient(X[idx].contiguous(), T[idx].contiguous(), M[idx].contiguous())
+                self.adam(lr=lr)
+                tot += float(loss) * idx.numel()
+            hist.append(tot / n)
+        return hist
+
+
+@dataclass
+class Records:
+    X: List[np.ndarray] = field(default_factory=list)   # features
+    t_incr: List[float] = field(default_factory=list)   # ms, incremental (insert part + delete part)
+    t_rec: List[float] = field(default_factory=list)    # ms, recompute on the same state
+    algo: List[int] = field(default_factory=list)
+    state: List[int] = field(default_factory=list)      # graph-state id (split key)
+    slab_scale: List[float] = field(default_factory=list)  # log2 best slab scale, nan if unknown
+
+    def arrays(self):
+        X = np.stack(self.X).astype(np.float32)
+        ti = np.asarray(self.t_incr, np.float64)
+        tr = np.asarray(self.t_rec, np.float64)
+        sc = np.asarray(self.slab_scale, np.float64)
+        T = np.stack([np.log(ti), np.log(tr), np.nan_to_num(sc)], 1).astype(np.float32)
+        M = np.stack([np.ones_like(ti), np.ones_like(tr), (~np.isnan(sc)).astype(np.float64)], 1)
+        return X, T, M.astype(np.float32), ti, tr, np.asarray(self.algo), np.asarray(self.state)
+
+
+def _time_call(fn, stream):
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    fn()
+    b.record(stream)
+    b.synchronize()
+    return a.elapsed_time(b)
+
+
+def run_algo(G, algo: str, mode: int, source: int):
+    if algo == "bfs":
+        return G.bfs(source, mode)
+    if algo == "sssp":
+        return G.sssp(source, mode)
+    if algo == "wcc":
+        return G.wcc(mode)
+    if algo == "pagerank":
+        return G.pagerank(mode=mode)
+    return G.triangles(mode)
+
+
+def generate_records(G, wl, source: int, n_batches: int, bmin: int, bmax: int, seed: int,
+                     rec: Optional[Records] = None, state_base: int = 0, algos=ALGOS,
+                     slab_scale: float = float("nan")) -> Records:
+    """Apply `n_batches` seeded mixed batches to G (and its workload `wl`) and record, per
+    algorithm, the features, the incremental time and the recompute time."""
+    rec = rec or Records()
+    rng = np.random.default_rng(seed)
+    stream = G.stream
+    for a in algos:  # every algorithm starts from a valid state
+        run_algo(G, a, native.RECOMPUTE, source)
+    for b in range(n_batches):
+        size = int(round(math.exp(rng.uniform(math.log(bmin), math.log(bmax)))))
+        fdel = float(rng.uniform(0.0, 1.0))
+        n_del = int(round(size * fdel))
+        n_ins = size - n_del
+        ins = wl.insert_batch(n_ins) if n_ins else None
+        dels = wl.delete_batch(n_del) if n_del else None
+        feats = {a: G.batch_features(ALGOS.index(a), ins, dels) for a in algos}
+        t_inc = {a: 0.0 for a in algos}
+        if ins is not None:
+            G.insert_edges(*ins, status=False)
+            for a in algos:
+                t_inc[a] += _time_call(lambda: run_algo(G, a, native.INCR, source), stream)
+        if dels is not None:
+            G.delete_edges(*dels, status=False)
+            for a in algos:
+                t_inc[a] += _time_call(lambda: run_algo(G, a, native.INCR, source), stream)
+        for a in algos:
+            t_r = _time_call(lambda: run_algo(G, a, native.RECOMPUTE, source), stream)
+            rec.X.append(feats[a])
+            rec.t_incr.append(max(t_inc[a], 1e-3))
+            rec.t_rec.append(max(t_r, 1e-3))
+            rec.algo.append(ALGOS.index(a))
+            rec.state.append(state_base + b)
+            rec.slab_scale.append(slab_scale)
+    return rec
+
+
+class CostModel:
+    """Trained MLP + the decision rule (incremental iff predicted incremental < recompute)."""
+
+    def __init__(self, mlp: MLP):
+        self.mlp = mlp
+
+    def predict(self, X: np.ndarray) -> np.ndarray:
+        return self.mlp.forward(torch.as_tensor(np.atleast_2d(X))).cpu().numpy()
+
+    def choose(self, X: np.ndarray) -> np.ndarray:
+        """MK_INCR (1) or MK_RECOMPUTE (2) per feature row."""
+        y = self.predict(X)
+        return np.where(y[:, 0] <= y[:, 1], native.INCR, native.RECOMPUTE)
+
+    def mode_for(self, G, algo: str, ins=None, dels=None) -> int:
+        return int(self.choose(G.batch_features(ALGOS.index(algo), ins, dels)[None, :])[0])
+
+
+def regret(t_incr, t_rec, choice):
+    """Total time of the choices, of the best choices, and of always-incremental."""
+    chosen = np.where(choice == native.INCR, t_incr, t_rec)
+    best = np.minimum(t_incr, t_rec)
+    return {"policy_ms": float(chosen.sum()), "best_ms": float(best.sum()),
+            "always_incremental_ms": float(t_incr.sum()), "always_recompute_ms": float(t_rec.sum()),
+            "policy_regret_ms": float(chosen.sum() - best.sum()),
+            "heuristic_regret_ms": float(t_incr.sum() - best.sum())}
+
+
+def fit(rec: Records, holdout_frac=0.2, epochs=300, seed=0, device="cuda"):
+    """Train on the older graph states, evaluate regret on the newest ones."""
+    X, T, M, ti, tr, algo, state = rec.arrays()
+    cut = np.quantile(state, 1 - holdout_frac)
+    tr_idx = state < cut
+    te_idx = ~tr_idx
+    mlp = MLP(device, seed)
+    hist = mlp.train(torch.from_numpy(X[tr_idx]), torch.from_numpy(T[tr_idx]), torch.from_numpy(M[tr_idx]),
+                     epochs=epochs, seed=seed)
+    cm = CostModel(mlp)
+    choice = cm.choose(X[te_idx])
+    return cm, hist, regret(ti[te_idx], tr[te_idx], choice)

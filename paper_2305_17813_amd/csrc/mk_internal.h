@@ -52,6 +52,8 @@ struct Counters {          // device-side scalars, one 4 KiB block
   uint32_t pr_state[8];    // [0] done flag, [1] iterations run, [2] stall count
   double pr_last;          // last L1 change
   double pr_best;          // smallest L1 change seen
+  double feat[6];          // batch-feature sums
+  uint32_t feat_max[2];    // batch-feature maxima
 };
 
 }  // namespace mk

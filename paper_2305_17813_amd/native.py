@@ -86,11 +86,18 @@ def load():
         "mk_graph_stats": [vp, ctypes.POINTER(MkStats), vp],
         "mk_graph_check": [vp, ctypes.POINTER(u64), vp],
         "mk_probe_cost": [vp, i32, i32, vp, vp, u64, ctypes.POINTER(u64), vp],
+        "mk_batch_features": [vp, i32, vp, vp, vp, u64, vp, vp, u64, ctypes.POINTER(ctypes.c_float), vp],
+        "mk_mlp_forward": [vp, vp, u32, vp, vp],
+        "mk_mlp_grad": [vp, vp, vp, vp, u32, vp, vp, ctypes.c_size_t, vp, vp],
+        "mk_mlp_adam": [vp, vp, vp, vp, u32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                        ctypes.c_float, u32, vp],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
         f.restype = i32
         f.argtypes = args
+    L.mk_mlp_workspace_bytes.restype = ctypes.c_size_t
+    L.mk_mlp_workspace_bytes.argtypes = [u32]
     L.mk_status_string.restype = ctypes.c_char_p
     L.mk_status_string.argtypes = [i32]
     _lib = L
@@ -258,6 +265,27 @@ class Graph:
         _check(self.lib.mk_probe_cost(self.h, int(op), int(view), _ptr(s), _ptr(d), s.numel(),
                                       ctypes.byref(out), self._s()), "mk_probe_cost")
         return int(out.value)
+
+    def batch_features(self, algo: int, ins=None, dels=None):
+        """Cost-model features (MK_MLP_IN floats) of a batch about to be applied."""
+        import numpy as np
+        out = (ctypes.c_float * 12)()
+        if ins is not None and ins[0].numel():
+            s, d = as_u32(ins[0], self.device), as_u32(ins[1], self.device)
+            w = None if len(ins) < 3 or ins[2] is None else as_u32(ins[2], self.device)
+            ni = s.numel()
+        else:
+            s = d = w = None
+            ni = 0
+        if dels is not None and dels[0].numel():
+            ds, dd = as_u32(dels[0], self.device), as_u32(dels[1], self.device)
+            nd = ds.numel()
+        else:
+            ds = dd = None
+            nd = 0
+        _check(self.lib.mk_batch_features(self.h, int(algo), _ptr(s), _ptr(d), _ptr(w), ni, _ptr(ds),
+                                          _ptr(dd), nd, out, self._s()), "mk_batch_features")
+        return np.array(out[:], dtype=np.float32)
 
     def check(self) -> int:
         bad = ctypes.c_uint64()

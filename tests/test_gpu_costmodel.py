@@ -1,0 +1,103 @@
+"""GPU tests of the cost model: the HIP MLP kernels against the FP64 oracle, the batch
+features against values computed from the oracle's degrees, and the trained policy's
+regret against the always-incremental rule on held-out graph states."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp as omlp
+from paper_2305_17813_amd import costmodel as CM
+from paper_2305_17813_amd import inputs as I
+from paper_2305_17813_amd import native
+from parity import Pair, say, u32
+
+pytestmark = pytest.mark.gpu
+
+
+def _problem(seed, n):
+    rng = np.random.default_rng(seed)
+    p = rng.normal(0, 0.3, omlp.N_PARAMS)
+    X = rng.normal(0, 1, (n, 12))
+    T = rng.normal(0, 1, (n, 3))
+    M = (rng.random((n, 3)) < 0.8).astype(float)
+    return p, X, T, M
+
+
+def _dev(a):
+    return torch.as_tensor(np.asarray(a, np.float32)).cuda().contiguous()
+
+
+@pytest.mark.parametrize("n", [1, 37, 300])
+def test_forward_and_gradient_match_oracle(n):
+    say(f"case: MLP forward/grad n={n}")
+    p, X, T, M = _problem(n, n)
+    net = CM.MLP("cuda")
+    net.params.copy_(_dev(p))
+    y = net.forward(_dev(X)).cpu().numpy()
+    yo, _ = omlp.forward(p.astype(np.float32).astype(np.float64), X.astype(np.float32))
+    assert np.abs(y - yo).max() <= 1e-4 * max(1.0, np.abs(yo).max())
+    loss = float(net.gradient(_dev(X), _dev(T), _dev(M)))
+    p32 = p.astype(np.float32).astype(np.float64)
+    X32, T32 = X.astype(np.float32).astype(np.float64), T.astype(np.float32).astype(np.float64)
+    go = omlp.grad(p32, X32, T32, M)
+    g = net.grad.cpu().numpy()
+    assert np.abs(g - go).max() <= 1e-4 * np.abs(go).max()
+    assert abs(loss - omlp.loss(p32, X32, T32, M)) <= 1e-5 * max(1.0, loss)
+
+
+def test_adam_matches_oracle_over_steps():
+    say("case: MLP Adam steps")
+    p, X, T, M = _problem(5, 64)
+    net = CM.MLP("cuda")
+    net.params.copy_(_dev(p))
+    po = p.astype(np.float32).astype(np.float64)
+    m = np.zeros_like(po)
+    v = np.zeros_like(po)
+    for step in range(1, 6):
+        net.gradient(_dev(X), _dev(T), _dev(M))
+        g = net.grad.cpu().numpy().astype(np.float64)  # same gradient on both sides
+        net.adam(lr=1e-2)
+        po, m, v = omlp.adam(po, g, m, v, step, lr=1e-2)
+        assert np.abs(net.params.cpu().numpy() - po).max() <= 1e-5
+
+
+def test_batch_features_from_oracle_degrees():
+    say("case: batch features")
+    g = I.rmat_s(11)
+    p = Pair(g.n, g.src, g.dst, g.w, source=I.max_out_degree_vertex(g))
+    wl = I.Workload(g, 6)
+    ins = wl.insert_batch(300)
+    dels = wl.delete_batch(100)
+    f = p.g.batch_features(native.VIEW_FWD * 0 + 3, ins, dels)  # PageRank features
+    out = p.o.out_degree().astype(np.float64)
+    # in-degrees from the oracle's arcs
+    s, d, _ = p.o.export()
+    indeg = np.bincount(d, minlength=g.n).astype(np.float64)
+    srcs = np.concatenate([u32(ins[0]), u32(dels[0])])
+    dsts = np.concatenate([u32(ins[1]), u32(dels[1])])
+    n = srcs.size
+    exp = [np.log2(1 + n) / 32, 300 / n, 100 / n, np.log2(g.n) / 32, np.log2(1 + out.sum()) / 32,
+           np.mean(np.log2(1 + out[srcs])) / 32, np.log2(1 + out[srcs].max()) / 32,
+           np.mean(np.log2(1 + indeg[dsts])) / 32, np.mean(1 / (1 + out[srcs])), 0.0, 0.0, 3 / 4]
+    assert np.allclose(f, np.asarray(exp, np.float32), rtol=1e-5, atol=1e-6), (f, exp)
+
+
+def test_trained_policy_beats_always_incremental():
+    """Records from the method's own timings on a road-like grid and a power-law graph;
+    the MLP is trained on the older graph states (HIP kernels) and judged on the newer ones."""
+    say("case: cost-model regret")
+    rec = CM.Records()
+    g1 = I.grid_side(128)
+    G1 = native.Graph(g1.n, g1.src, g1.dst, g1.w)
+    CM.generate_records(G1, I.Workload(g1, 21), 0, 40, 30, 4000, seed=1, rec=rec, state_base=0)
+    g2 = I.rmat_s(13)
+    G2 = native.Graph(g2.n, g2.src, g2.dst, g2.w)
+    CM.generate_records(G2, I.Workload(g2, 22), I.max_out_degree_vertex(g2), 40, 10, 4000, seed=2,
+                        rec=rec, state_base=1000)
+    # interleave the two graphs' states so both appear on each side of the split
+    rec.state = [s % 1000 for s in rec.state]
+    cm, hist, r = CM.fit(rec, epochs=300)
+    say(f"  records {len(rec.X)}, loss {hist[0]:.3f} -> {hist[-1]:.4f}, held-out {r}")
+    assert hist[-1] < 0.5 * hist[0]
+    assert r["policy_ms"] < r["always_incremental_ms"]
+    assert r["policy_regret_ms"] < r["heuristic_regret_ms"]
