@@ -144,6 +144,19 @@ mk_status mk_incr_bfs(mk_graph* g, uint32_t source, uint32_t* d_level, uint32_t*
 mk_status mk_incr_sssp(mk_graph* g, uint32_t source, uint32_t* d_dist, uint32_t* d_parent,
                        mk_mode mode, hipStream_t stream);
 
+/* One-off traversal from `source` (BFS levels when weighted == 0, SSSP distances
+ * otherwise; same kernels and tie-break as mk_incr_bfs / mk_incr_sssp, computed from
+ * scratch) that keeps all its state in the caller's workspace, so it changes nothing in
+ * the graph and may overlap other reads of the graph on other streams (the serving loop
+ * runs concurrent requests this way).  Updates must not run concurrently with it.
+ *   d_ws/ws_bytes : device workspace of at least mk_traversal_workspace_bytes(g) bytes.
+ *   slot          : 0..15; concurrent calls must use distinct slots (each slot owns a few
+ *                   pinned host words for size read-backs).
+ *   d_dist, d_parent (nullable) : N uint32 (device).  Synchronizes `stream`. */
+size_t mk_traversal_workspace_bytes(const mk_graph* g);
+mk_status mk_traverse_from(mk_graph* g, uint32_t source, int weighted, void* d_ws, size_t ws_bytes,
+                           uint32_t slot, uint32_t* d_dist, uint32_t* d_parent, hipStream_t stream);
+
 /* Weakly connected components (section 4.4: union-find with full path compression).
  * Inserted arcs are united incrementally; any pending deletion forces a recompute.
  *   d_label : N uint32 (device): the smallest vertex id of the component. */

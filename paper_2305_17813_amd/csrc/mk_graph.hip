@@ -745,6 +745,8 @@ mk_status mk_graph_create(const mk_config* cfg, void* d_arena, size_t arena_byte
 mk_status mk_graph_destroy(mk_graph* g) {
   if (!g) return MK_OK;
   if (g->h_pin) (void)hipHostFree(g->h_pin);
+  for (auto* p : g->slot_pin)
+    if (p) (void)hipHostFree(p);
   delete g;
   return MK_OK;
 }

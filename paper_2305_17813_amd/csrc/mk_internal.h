@@ -10,6 +10,7 @@
 namespace mk {
 
 enum { VF = 0, VR = 1, VU = 2 };
+constexpr uint32_t kSlots = 16;  // concurrent one-off traversals (distinct streams)
 enum BatchKind { kInsertBatch = 0, kDeleteBatch = 1 };
 
 // One applied update batch, remembered for the incremental algorithms.  Its ops live in
@@ -98,6 +99,7 @@ struct mk_graph {
   size_t scan_tmp_bytes = 0;
 
   uint64_t* h_pin = nullptr;  // pinned host words for read-backs
+  uint64_t* slot_pin[mk::kSlots] = {};  // pinned words of one-off traversals, per slot
   uint64_t batches_applied = 0;
   std::string last_err;
 };

@@ -233,6 +233,10 @@ __global__ void __launch_bounds__(kBlock) k_dec_pull(DView F, DView R, uint64_t*
   }
 }
 
+__global__ void k_fill_mark(uint32_t* mark, uint32_t nv) {
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) mark[v] = 0;
+}
+
 __global__ void k_split(const uint64_t* D, uint32_t nv, uint32_t* dist, uint32_t* parent) {
   for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
     const uint64_t x = D[v];
@@ -245,14 +249,40 @@ inline uint32_t blocks_for(uint64_t n, uint32_t cap = 4096) {
   return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((n + kBlock - 1) / kBlock, cap));
 }
 
-Queues queues(mk_graph* g, uint64_t it) {
+// Where a traversal keeps its state: the graph's own arrays for the maintained BFS/SSSP,
+// or a caller workspace for a one-off traversal that other reads may overlap.
+struct TravCtx {
+  uint64_t* D;
+  uint32_t* fq[4];
+  uint32_t* mark;
+  uint32_t* inval;
+  uint32_t* cnt;        // rotating frontier sizes [8]
+  uint32_t* inval_cnt;  // invalidated-list size
+  uint32_t* stamp;      // host-side stamp counter
+  uint64_t* h_pin;      // pinned host words for size read-backs
+};
+
+TravCtx graph_ctx(mk_graph* g, uint64_t* D) {
+  TravCtx c;
+  c.D = D;
+  for (int i = 0; i < 4; ++i) c.fq[i] = g->fq[i];
+  c.mark = g->mark;
+  c.inval = g->inval;
+  c.cnt = g->ctr->frontier;
+  c.inval_cnt = &g->ctr->inval;
+  c.stamp = &g->stamp;
+  c.h_pin = g->h_pin;
+  return c;
+}
+
+Queues queues(const TravCtx& c, uint64_t it) {
   Queues q;
   const int a = (int)(it & 1);
-  q.Lcur = g->fq[a];
-  q.Lnext = g->fq[a ^ 1];
-  q.Hcur = g->fq[2 + a];
-  q.Hnext = g->fq[2 + (a ^ 1)];
-  q.cnt = g->ctr->frontier;
+  q.Lcur = c.fq[a];
+  q.Lnext = c.fq[a ^ 1];
+  q.Hcur = c.fq[2 + a];
+  q.Hnext = c.fq[2 + (a ^ 1)];
+  q.cnt = c.cnt;
   q.icur = (int)(it % 3);
   q.inext = (int)((it + 1) % 3);
   q.iclear = (int)((it + 2) % 3);
@@ -262,23 +292,41 @@ Queues queues(mk_graph* g, uint64_t it) {
 // Run frontier iterations (expand or propagate) until the frontier is empty.  Iteration
 // `it` reads slot it%3; the frontier of iteration 0 sits in fq[0] / fq[2] and slot 0.
 template <class Launch>
-mk_status run_frontier(mk_graph* g, hipStream_t stream, Launch&& launch, uint64_t* iters_out) {
+mk_status run_frontier(mk_graph* g, const TravCtx& c, hipStream_t stream, Launch&& launch) {
   uint64_t it = 0;
   while (true) {
     for (int k = 0; k < kSyncEvery; ++k, ++it) {
-      launch(queues(g, it), ++g->stamp);
+      launch(queues(c, it), ++*c.stamp);
       MK_LAUNCH(g, "frontier kernel");
     }
     const int slot = (int)(it % 3);
-    MK_HIP(g, hipMemcpyAsync(g->h_pin, g->ctr->frontier, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost,
-                             stream));
+    MK_HIP(g, hipMemcpyAsync(c.h_pin, c.cnt, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
     MK_HIP(g, hipStreamSynchronize(stream));
-    const uint32_t* c = reinterpret_cast<const uint32_t*>(g->h_pin);
-    if (c[slot] == 0 && c[3 + slot] == 0) break;
+    const uint32_t* h = reinterpret_cast<const uint32_t*>(c.h_pin);
+    if (h[slot] == 0 && h[3 + slot] == 0) break;
   }
-  if (iters_out) *iters_out = it;
-  // leave the frontier of "iteration 0" empty for the next user
   return MK_OK;
+}
+
+template <bool kUnit>
+mk_status run_expand(mk_graph* g, const TravCtx& c, hipStream_t stream) {
+  const DView F = g->view[VF].d;
+  return run_frontier(g, c, stream, [&](Queues q, uint32_t stamp) {
+    hipLaunchKernelGGL(k_expand<kUnit>, dim3(kExpandBlocks), dim3(kBlock), 0, stream, F, c.D, q, c.mark,
+                       stamp);
+  });
+}
+
+template <bool kUnit>
+mk_status static_from(mk_graph* g, const TravCtx& c, uint32_t source, hipStream_t stream) {
+  const DView F = g->view[VF].d;
+  const uint32_t stamp0 = ++*c.stamp;
+  hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, stream, c.cnt, c.inval_cnt);
+  hipLaunchKernelGGL(k_trav_init, dim3(blocks_for(g->n)), dim3(kBlock), 0, stream, c.D, g->n, source);
+  hipLaunchKernelGGL(k_seed_source, dim3(1), dim3(64), 0, stream, F, source, c.fq[0], c.fq[2], c.cnt,
+                     c.mark, stamp0);
+  MK_LAUNCH(g, "traversal init");
+  return run_expand<kUnit>(g, c, stream);
 }
 
 template <bool kUnit>
@@ -287,59 +335,44 @@ mk_status traverse(mk_graph* g, AlgoState& st, uint64_t* D, uint32_t source, uin
   if (source >= g->n || !d_out) return MK_ERR_INVALID_ARG;
   const DView F = g->view[VF].d;
   const uint32_t N = g->n;
+  const TravCtx c = graph_ctx(g, D);
   Pending p = pending_for(g, st);
   const bool can_dec = g->view[VR].on;
-  bool full = mode == MK_RECOMPUTE || !st.valid || st.source != source || p.lost || p.kinds == 3 ||
-              (p.kinds == 2 && !can_dec);
-  uint32_t* Lq0 = g->fq[0];
-  uint32_t* Hq0 = g->fq[2];
-  uint32_t* cnt = g->ctr->frontier;
-  const uint32_t stamp0 = ++g->stamp;
-  bool run = true;
-  hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, stream, cnt, &g->ctr->inval);
+  const bool full = mode == MK_RECOMPUTE || !st.valid || st.source != source || p.lost ||
+                    p.kinds == 3 || (p.kinds == 2 && !can_dec);
   if (full) {
-    hipLaunchKernelGGL(k_trav_init, dim3(blocks_for(N)), dim3(kBlock), 0, stream, D, N, source);
-    hipLaunchKernelGGL(k_seed_source, dim3(1), dim3(64), 0, stream, F, source, Lq0, Hq0, cnt,
-                       g->mark, stamp0);
-  } else if (p.list.empty()) {
-    run = false;
-  } else if (p.kinds == 1) {
-    for (const BatchRec* b : p.list) {
-      Log lg = g->log;
-      lg.s += b->off; lg.d += b->off; lg.w += b->off; lg.st += b->off; lg.uf += b->off;
-      hipLaunchKernelGGL(k_relax_batch<kUnit>, dim3(blocks_for(b->n)), dim3(kBlock), 0, stream, F,
-                         D, lg, b->n, Lq0, Hq0, cnt, g->mark, stamp0);
-    }
-  } else {  // deletions only
-    for (const BatchRec* b : p.list) {
-      Log lg = g->log;
-      lg.s += b->off; lg.d += b->off; lg.w += b->off; lg.st += b->off; lg.uf += b->off;
-      hipLaunchKernelGGL(k_invalidate, dim3(blocks_for(b->n)), dim3(kBlock), 0, stream, F, D, lg,
-                         b->n, Lq0, Hq0, cnt, g->inval, &g->ctr->inval, g->mark, stamp0);
-    }
-    MK_LAUNCH(g, "k_invalidate");
-    mk_status s = run_frontier(
-        g, stream,
-        [&](Queues q, uint32_t stamp) {
-          hipLaunchKernelGGL(k_propagate, dim3(kExpandBlocks), dim3(kBlock), 0, stream, F, D, q,
-                             g->inval, &g->ctr->inval, g->mark, stamp);
-        },
-        nullptr);
+    mk_status s = static_from<kUnit>(g, c, source, stream);
     if (s != MK_OK) return s;
-    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, stream, cnt, nullptr);
-    const uint32_t stamp1 = ++g->stamp;
-    hipLaunchKernelGGL(k_dec_pull<kUnit>, dim3(kExpandBlocks), dim3(kBlock), 0, stream, F,
-                       g->view[VR].d, D, g->inval, &g->ctr->inval, Lq0, Hq0, cnt, g->mark, stamp1);
-  }
-  MK_LAUNCH(g, "traversal prologue");
-  if (run) {
-    mk_status s = run_frontier(
-        g, stream,
-        [&](Queues q, uint32_t stamp) {
-          hipLaunchKernelGGL(k_expand<kUnit>, dim3(kExpandBlocks), dim3(kBlock), 0, stream, F, D, q,
-                             g->mark, stamp);
-        },
-        nullptr);
+  } else if (!p.list.empty()) {
+    const uint32_t stamp0 = ++g->stamp;
+    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, stream, c.cnt, c.inval_cnt);
+    if (p.kinds == 1) {
+      for (const BatchRec* b : p.list) {
+        Log lg = g->log;
+        lg.s += b->off; lg.d += b->off; lg.w += b->off; lg.st += b->off; lg.uf += b->off;
+        hipLaunchKernelGGL(k_relax_batch<kUnit>, dim3(blocks_for(b->n)), dim3(kBlock), 0, stream, F, D,
+                           lg, b->n, c.fq[0], c.fq[2], c.cnt, c.mark, stamp0);
+      }
+    } else {  // deletions only
+      for (const BatchRec* b : p.list) {
+        Log lg = g->log;
+        lg.s += b->off; lg.d += b->off; lg.w += b->off; lg.st += b->off; lg.uf += b->off;
+        hipLaunchKernelGGL(k_invalidate, dim3(blocks_for(b->n)), dim3(kBlock), 0, stream, F, D, lg, b->n,
+                           c.fq[0], c.fq[2], c.cnt, c.inval, c.inval_cnt, c.mark, stamp0);
+      }
+      MK_LAUNCH(g, "k_invalidate");
+      mk_status s = run_frontier(g, c, stream, [&](Queues q, uint32_t stamp) {
+        hipLaunchKernelGGL(k_propagate, dim3(kExpandBlocks), dim3(kBlock), 0, stream, F, D, q, c.inval,
+                           c.inval_cnt, c.mark, stamp);
+      });
+      if (s != MK_OK) return s;
+      hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, stream, c.cnt, nullptr);
+      const uint32_t stamp1 = ++g->stamp;
+      hipLaunchKernelGGL(k_dec_pull<kUnit>, dim3(kExpandBlocks), dim3(kBlock), 0, stream, F,
+                         g->view[VR].d, D, c.inval, c.inval_cnt, c.fq[0], c.fq[2], c.cnt, c.mark, stamp1);
+    }
+    MK_LAUNCH(g, "traversal prologue");
+    mk_status s = run_expand<kUnit>(g, c, stream);
     if (s != MK_OK) return s;
   }
   hipLaunchKernelGGL(k_split, dim3(blocks_for(N)), dim3(kBlock), 0, stream, D, N, d_out, d_parent);
@@ -348,6 +381,11 @@ mk_status traverse(mk_graph* g, AlgoState& st, uint64_t* D, uint32_t source, uin
   st.source = source;
   mark_seen(g, st);
   return MK_OK;
+}
+
+size_t ws_bytes_for(uint32_t n) {
+  // D (8 B), four queues, stamps and the invalidated list (4 B each), counters
+  return (size_t)n * (8 + 6 * 4) + 512 + 8 * 256;
 }
 
 }  // namespace
@@ -364,6 +402,41 @@ mk_status mk_incr_sssp(mk_graph* g, uint32_t source, uint32_t* d_dist, uint32_t*
                        mk_mode mode, hipStream_t stream) {
   if (!g) return MK_ERR_INVALID_ARG;
   return traverse<false>(g, g->sssp, g->sssp_D, source, d_dist, d_parent, mode, stream);
+}
+
+size_t mk_traversal_workspace_bytes(const mk_graph* g) { return g ? ws_bytes_for(g->n) : 0; }
+
+mk_status mk_traverse_from(mk_graph* g, uint32_t source, int weighted, void* d_ws, size_t ws_bytes,
+                           uint32_t slot, uint32_t* d_dist, uint32_t* d_parent, hipStream_t stream) {
+  if (!g || !d_ws || !d_dist || source >= g->n || slot >= kSlots) return MK_ERR_INVALID_ARG;
+  if (ws_bytes < ws_bytes_for(g->n)) return MK_ERR_CAPACITY;
+  if (!g->slot_pin[slot]) {
+    if (hipHostMalloc((void**)&g->slot_pin[slot], 64 * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess)
+      return MK_ERR_HIP;
+  }
+  const uint32_t N = g->n;
+  char* p = reinterpret_cast<char*>(((uintptr_t)d_ws + 255) & ~uintptr_t(255));
+  auto take = [&](size_t bytes) {
+    char* r = p;
+    p += (bytes + 255) & ~size_t(255);
+    return r;
+  };
+  TravCtx c;
+  c.D = reinterpret_cast<uint64_t*>(take((size_t)N * 8));
+  for (int i = 0; i < 4; ++i) c.fq[i] = reinterpret_cast<uint32_t*>(take((size_t)N * 4));
+  c.mark = reinterpret_cast<uint32_t*>(take((size_t)N * 4));
+  c.inval = reinterpret_cast<uint32_t*>(take((size_t)N * 4));
+  c.cnt = reinterpret_cast<uint32_t*>(take(64));
+  c.inval_cnt = c.cnt + 8;
+  uint32_t stamp = 0;
+  c.stamp = &stamp;
+  c.h_pin = g->slot_pin[slot];
+  hipLaunchKernelGGL(k_fill_mark, dim3(blocks_for(N)), dim3(kBlock), 0, stream, c.mark, N);
+  mk_status s = weighted ? static_from<false>(g, c, source, stream) : static_from<true>(g, c, source, stream);
+  if (s != MK_OK) return s;
+  hipLaunchKernelGGL(k_split, dim3(blocks_for(N)), dim3(kBlock), 0, stream, c.D, N, d_dist, d_parent);
+  MK_LAUNCH(g, "k_split");
+  return MK_OK;
 }
 
 }  // extern "C"

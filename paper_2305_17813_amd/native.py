@@ -88,6 +88,7 @@ def load():
         "mk_probe_cost": [vp, i32, i32, vp, vp, u64, ctypes.POINTER(u64), vp],
         "mk_batch_features": [vp, i32, vp, vp, vp, u64, vp, vp, u64, ctypes.POINTER(ctypes.c_float), vp],
         "mk_mlp_forward": [vp, vp, u32, vp, vp],
+        "mk_traverse_from": [vp, u32, i32, vp, ctypes.c_size_t, u32, vp, vp, vp],
         "mk_mlp_grad": [vp, vp, vp, vp, u32, vp, vp, ctypes.c_size_t, vp, vp],
         "mk_mlp_adam": [vp, vp, vp, vp, u32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                         ctypes.c_float, u32, vp],
@@ -96,6 +97,8 @@ def load():
         f = getattr(L, name)
         f.restype = i32
         f.argtypes = args
+    L.mk_traversal_workspace_bytes.restype = ctypes.c_size_t
+    L.mk_traversal_workspace_bytes.argtypes = [vp]
     L.mk_mlp_workspace_bytes.restype = ctypes.c_size_t
     L.mk_mlp_workspace_bytes.argtypes = [u32]
     L.mk_status_string.restype = ctypes.c_char_p
@@ -169,8 +172,8 @@ class Graph:
         self.h = h
         self.arena_bytes = nbytes
 
-    def _s(self):
-        return ctypes.c_void_p(self.stream.cuda_stream)
+    def _s(self, stream=None):
+        return ctypes.c_void_p((stream or self.stream).cuda_stream)
 
     def close(self):
         if getattr(self, "h", None):
@@ -184,60 +187,79 @@ class Graph:
             pass
 
     # ------------------------------------------------------------ updates / queries
-    def insert_edges(self, src, dst, w=None, status: bool = True):
+    def insert_edges(self, src, dst, w=None, status: bool = True, stream=None):
         s, d = as_u32(src, self.device), as_u32(dst, self.device)
         ww = None if w is None else as_u32(w, self.device)
         out = torch.empty(s.numel(), dtype=torch.uint8, device=self.device) if status else None
         _check(self.lib.mk_insert_edges(self.h, _ptr(s), _ptr(d), _ptr(ww), s.numel(), _ptr(out),
-                                        self._s()), "mk_insert_edges")
+                                        self._s(stream)), "mk_insert_edges")
         return out
 
-    def delete_edges(self, src, dst, status: bool = True):
+    def delete_edges(self, src, dst, status: bool = True, stream=None):
         s, d = as_u32(src, self.device), as_u32(dst, self.device)
         out = torch.empty(s.numel(), dtype=torch.uint8, device=self.device) if status else None
-        _check(self.lib.mk_delete_edges(self.h, _ptr(s), _ptr(d), s.numel(), _ptr(out), self._s()),
-               "mk_delete_edges")
+        _check(self.lib.mk_delete_edges(self.h, _ptr(s), _ptr(d), s.numel(), _ptr(out),
+                                        self._s(stream)), "mk_delete_edges")
         return out
 
-    def query_edges(self, src, dst, weights: bool = True):
+    def query_edges(self, src, dst, weights: bool = True, stream=None, out=None):
+        """Membership (and weights) of arcs; `out` = (found u8, weight i32) preallocated."""
         s, d = as_u32(src, self.device), as_u32(dst, self.device)
-        found = torch.empty(s.numel(), dtype=torch.uint8, device=self.device)
-        w = torch.empty(s.numel(), dtype=torch.int32, device=self.device) if weights else None
+        if out is None:
+            found = torch.empty(s.numel(), dtype=torch.uint8, device=self.device)
+            w = torch.empty(s.numel(), dtype=torch.int32, device=self.device) if weights else None
+        else:
+            found, w = out
         _check(self.lib.mk_query_edges(self.h, _ptr(s), _ptr(d), s.numel(), _ptr(found), _ptr(w),
-                                       self._s()), "mk_query_edges")
+                                       self._s(stream)), "mk_query_edges")
         return found, w
 
+    def traversal_workspace(self) -> torch.Tensor:
+        return torch.empty(self.lib.mk_traversal_workspace_bytes(self.h), dtype=torch.uint8,
+                           device=self.device)
+
+    def traverse_from(self, source: int, weighted: bool, ws: torch.Tensor, slot: int = 0,
+                      stream=None, parents: bool = True):
+        """One-off BFS (weighted=False) or SSSP from `source` in the workspace `ws`; leaves
+        the graph untouched, so it may overlap other reads on other streams."""
+        di = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        pa = torch.empty(self.n, dtype=torch.int32, device=self.device) if parents else None
+        _check(self.lib.mk_traverse_from(self.h, int(source), int(bool(weighted)), _ptr(ws), ws.numel(),
+                                         int(slot), _ptr(di), _ptr(pa), self._s(stream)),
+               "mk_traverse_from")
+        return di, pa
+
     # ------------------------------------------------------------ algorithms
-    def bfs(self, source: int, mode: int = AUTO, parents: bool = True):
+    def bfs(self, source: int, mode: int = AUTO, parents: bool = True, stream=None):
         lv = torch.empty(self.n, dtype=torch.int32, device=self.device)
         pa = torch.empty(self.n, dtype=torch.int32, device=self.device) if parents else None
-        _check(self.lib.mk_incr_bfs(self.h, int(source), _ptr(lv), _ptr(pa), mode, self._s()),
+        _check(self.lib.mk_incr_bfs(self.h, int(source), _ptr(lv), _ptr(pa), mode, self._s(stream)),
                "mk_incr_bfs")
         return lv, pa
 
-    def sssp(self, source: int, mode: int = AUTO, parents: bool = True):
+    def sssp(self, source: int, mode: int = AUTO, parents: bool = True, stream=None):
         di = torch.empty(self.n, dtype=torch.int32, device=self.device)
         pa = torch.empty(self.n, dtype=torch.int32, device=self.device) if parents else None
-        _check(self.lib.mk_incr_sssp(self.h, int(source), _ptr(di), _ptr(pa), mode, self._s()),
+        _check(self.lib.mk_incr_sssp(self.h, int(source), _ptr(di), _ptr(pa), mode, self._s(stream)),
                "mk_incr_sssp")
         return di, pa
 
-    def wcc(self, mode: int = AUTO):
+    def wcc(self, mode: int = AUTO, stream=None):
         lab = torch.empty(self.n, dtype=torch.int32, device=self.device)
-        _check(self.lib.mk_incr_wcc(self.h, _ptr(lab), mode, self._s()), "mk_incr_wcc")
+        _check(self.lib.mk_incr_wcc(self.h, _ptr(lab), mode, self._s(stream)), "mk_incr_wcc")
         return lab
 
     def pagerank(self, damping: float = 0.85, tol: float = 1e-9, max_iter: int = 500,
-                 mode: int = AUTO):
+                 mode: int = AUTO, stream=None):
         r = torch.empty(self.n, dtype=torch.float32, device=self.device)
         it = torch.zeros(1, dtype=torch.int32, device=self.device)
         _check(self.lib.mk_incr_pagerank(self.h, float(damping), float(tol), int(max_iter), _ptr(r),
-                                         _ptr(it), mode, self._s()), "mk_incr_pagerank")
+                                         _ptr(it), mode, self._s(stream)), "mk_incr_pagerank")
         return r, it
 
-    def triangles(self, mode: int = AUTO):
+    def triangles(self, mode: int = AUTO, stream=None):
         c = torch.zeros(1, dtype=torch.int64, device=self.device)
-        _check(self.lib.mk_count_triangles(self.h, _ptr(c), mode, self._s()), "mk_count_triangles")
+        _check(self.lib.mk_count_triangles(self.h, _ptr(c), mode, self._s(stream)), "mk_count_triangles")
         return c
 
     # ------------------------------------------------------------ inspection
