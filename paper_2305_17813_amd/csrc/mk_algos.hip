@@ -18,6 +18,7 @@ using namespace mk;
 namespace {
 
 constexpr uint32_t kWalkBlocks = 4096;
+constexpr uint32_t kPrChunk = 4;  // buckets per heavy-vertex work item
 constexpr int kPrSyncEvery = 4;
 
 inline uint32_t blocks_for(uint64_t n, uint32_t cap = 4096) {
@@ -81,8 +82,25 @@ __global__ void __launch_bounds__(kBlock) k_wcc_all(DView F, uint32_t* P, uint32
     const uint32_t v = (uint32_t)x;
     if (data && valid_key(v)) uf_union(P, u, v);
   };
+  // single-bucket vertices: one lane each
+  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < nv; u += gridDim.x * blockDim.x) {
+    if (F.nbk[u] != 1 || F.deg[u] == 0) continue;
+    Slab sl;
+    uint32_t t = u;
+    while (true) {
+      load_slab(F, t, sl);
+#pragma unroll
+      for (int j = 0; j < kKeysPerSlab; ++j) {
+        const uint32_t v = (uint32_t)sl.w[j];
+        if (valid_key(v)) uf_union(P, u, v);
+      }
+      t = (uint32_t)sl.w[15];
+      if (t == kInvalid) break;
+    }
+  }
   for (uint32_t u = g0; u < nv; u += ng) {
-    if (F.nbk[u] > kHeavyBuckets || F.deg[u] == 0) continue;
+    const uint32_t nb = F.nbk[u];
+    if (nb == 1 || nb > kHeavyBuckets || F.deg[u] == 0) continue;
     for_each_slab(F, u, [&](uint64_t x, bool data) { body(u, x, data); });
   }
   const uint32_t nh = *nheavy, gib = threadIdx.x / kGroup;
@@ -152,49 +170,106 @@ __global__ void __launch_bounds__(kBlock) k_pr_gather(DView R, const float* __re
                                                       float* __restrict__ y, uint32_t nv, float damping,
                                                       const double* dang, double* delta,
                                                       const uint32_t* heavy, const uint32_t* nheavy,
-                                                      const uint32_t* state) {
+                                                      const uint32_t* hcnt, const uint32_t* hoff,
+                                                      double* hacc, const uint32_t* state) {
   __shared__ double lds[kBlock / 64];
-  __shared__ double part[kGroupsPerBlock];
   if (state[0]) return;
   const double base = (1.0 - (double)damping) / nv + (double)damping * (*dang) / nv;
   double local = 0;
+  // single-bucket vertices (most of a power-law graph): one lane per vertex, so a wave keeps
+  // 64 slab reads and their gathers in flight
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
+    if (R.nbk[v] != 1) continue;
+    double s = 0;
+    if (R.deg[v] != 0) {  // vertices without in-arcs need no slab read
+      Slab sl;
+      uint32_t t = v;
+      while (true) {
+        load_slab(R, t, sl);
+#pragma unroll
+        for (int j = 0; j < kKeysPerSlab; ++j) {
+          const uint32_t u = (uint32_t)sl.w[j];
+          if (valid_key(u)) s += (double)c[u];
+        }
+        t = (uint32_t)sl.w[15];
+        if (t == kInvalid) break;
+      }
+    }
+    const float nvl = (float)(base + (double)damping * s);
+    y[v] = nvl;
+    local += fabs((double)nvl - (double)x[v]);
+  }
+  // vertices with 2 .. kHeavyBuckets buckets: one 16-lane group per vertex
   const uint32_t g0 = (blockIdx.x * kBlock + threadIdx.x) / kGroup;
   const uint32_t ng = gridDim.x * kGroupsPerBlock;
   for (uint32_t v = g0; v < nv; v += ng) {
-    if (R.nbk[v] > kHeavyBuckets) continue;
+    const uint32_t nb = R.nbk[v];
+    if (nb == 1 || nb > kHeavyBuckets) continue;
     double s = 0;
-    if (R.deg[v] != 0) {  // vertices without in-arcs need no slab read
-      for_each_slab(R, v, [&](uint64_t w, bool data) {
-        const uint32_t u = (uint32_t)w;
-        if (data && valid_key(u)) s += (double)c[u];
-      });
-      s = gsum(s);
-    }
+    for_each_slab(R, v, [&](uint64_t w, bool data) {
+      const uint32_t u = (uint32_t)w;
+      if (data && valid_key(u)) s += (double)c[u];
+    });
+    s = gsum(s);
     if (glane() == 0) {
       const float nvl = (float)(base + (double)damping * s);
       y[v] = nvl;
       local += fabs((double)nvl - (double)x[v]);
     }
   }
-  const uint32_t nh = *nheavy, gib = threadIdx.x / kGroup;
-  for (uint32_t j = blockIdx.x; j < nh; j += gridDim.x) {
-    const uint32_t v = heavy[j];
-    double s = 0;
-    for_each_slab_strided(R, v, gib, kGroupsPerBlock, [&](uint64_t w, bool data) {
-      const uint32_t u = (uint32_t)w;
-      if (data && valid_key(u)) s += (double)c[u];
-    });
-    s = gsum(s);
-    __syncthreads();
-    if (glane() == 0) part[gib] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double t = 0;
-      for (int i = 0; i < kGroupsPerBlock; ++i) t += part[i];
-      const float nvl = (float)(base + (double)damping * t);
-      y[v] = nvl;
-      local += fabs((double)nvl - (double)x[v]);
+  // heavy vertices: work items of kPrChunk buckets spread over every group; partial sums
+  // go to hacc[j] and k_pr_heavy_final turns them into ranks
+  const uint32_t nh = *nheavy;
+  if (nh) {
+    const uint32_t items = hoff[nh - 1] + hcnt[nh - 1];
+    for (uint32_t it = g0; it < items; it += ng) {
+      uint32_t lo = 0, hi = nh;  // last j with hoff[j] <= it
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (hoff[mid] <= it) lo = mid;
+        else hi = mid;
+      }
+      const uint32_t v = heavy[lo];
+      const uint32_t b0 = (it - hoff[lo]) * kPrChunk;
+      double s = 0;
+      for_each_bucket_range(R, v, b0, b0 + kPrChunk, [&](uint64_t w, bool data) {
+        const uint32_t u = (uint32_t)w;
+        if (data && valid_key(u)) s += (double)c[u];
+      });
+      s = gsum(s);
+      if (glane() == 0 && s != 0.0) atomicAdd(hacc + lo, s);
     }
+  }
+  const double s = block_sum(local, lds);
+  if (threadIdx.x == 0 && s != 0.0) atomicAdd(delta, s);
+}
+
+// Work items per heavy vertex: ceil(buckets / kPrChunk).
+__global__ void k_heavy_items(const uint32_t* nbk, const uint32_t* heavy, const uint32_t* nheavy,
+                              uint32_t* cnt, double* acc) {
+  const uint32_t nh = *nheavy;
+  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < nh; j += gridDim.x * blockDim.x) {
+    cnt[j] = (nbk[heavy[j]] + kPrChunk - 1) / kPrChunk;
+    acc[j] = 0.0;
+  }
+}
+
+// Ranks of the heavy vertices from their partial sums (and their share of the L1 change).
+__global__ void __launch_bounds__(kBlock) k_pr_heavy_final(const uint32_t* heavy, const uint32_t* nheavy,
+                                                           double* acc, const float* x, float* y,
+                                                           uint32_t nv, float damping, const double* dang,
+                                                           double* delta, const uint32_t* state) {
+  __shared__ double lds[kBlock / 64];
+  if (state[0]) return;
+  const double base = (1.0 - (double)damping) / nv + (double)damping * (*dang) / nv;
+  const uint32_t nh = *nheavy;
+  double local = 0;
+  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < nh; j += gridDim.x * blockDim.x) {
+    const uint32_t v = heavy[j];
+    const float nvl = (float)(base + (double)damping * acc[j]);
+    y[v] = nvl;
+    acc[j] = 0.0;
+    local += fabs((double)nvl - (double)x[v]);
   }
   const double s = block_sum(local, lds);
   if (threadIdx.x == 0 && s != 0.0) atomicAdd(delta, s);
@@ -446,6 +521,19 @@ mk_status mk_incr_pagerank(mk_graph* g, float damping, double tol_l1, uint32_t m
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, nh, 1u);
   hipLaunchKernelGGL(k_collect_heavy, dim3(blocks_for(N)), dim3(kBlock), 0, stream, g->view[VR].nbk,
                      N, g->heavy_rev, nh);
+  // heavy-vertex work items: counts, exclusive offsets, FP64 partial sums (scratch: the
+  // traversal queues, which PageRank does not use)
+  uint32_t* hcnt = g->fq[0];
+  uint32_t* hoff = g->fq[1];
+  double* hacc = g->pr_hacc;
+  hipLaunchKernelGGL(k_heavy_items, dim3(blocks_for(N)), dim3(kBlock), 0, stream, g->view[VR].nbk,
+                     g->heavy_rev, nh, hcnt, hacc);
+  {
+    size_t tb = g->scan_tmp_bytes;
+    if (rocprim::exclusive_scan(g->scan_tmp, tb, hcnt, hoff, 0u, (size_t)N, rocprim::plus<uint32_t>(),
+                                stream) != hipSuccess)
+      return MK_ERR_HIP;
+  }
   hipLaunchKernelGGL(k_pr_start, dim3(1), dim3(64), 0, stream, g->ctr);
   MK_LAUNCH(g, "pagerank setup");
   float* buf[2] = {g->pr_x, g->pr_y};
@@ -459,7 +547,11 @@ mk_status mk_incr_pagerank(mk_graph* g, float damping, double tol_l1, uint32_t m
                          g->view[VF].d.deg, g->pr_c, N, &g->ctr->pr_acc[2 * slot], g->ctr->pr_state);
       hipLaunchKernelGGL(k_pr_gather, dim3(kWalkBlocks), dim3(kBlock), 0, stream, g->view[VR].d,
                          g->pr_c, x, y, N, damping, &g->ctr->pr_acc[2 * slot],
-                         &g->ctr->pr_acc[2 * slot + 1], g->heavy_rev, nh, g->ctr->pr_state);
+                         &g->ctr->pr_acc[2 * slot + 1], g->heavy_rev, nh, hcnt, hoff, hacc,
+                         g->ctr->pr_state);
+      hipLaunchKernelGGL(k_pr_heavy_final, dim3(blocks_for(N, 512)), dim3(kBlock), 0, stream, g->heavy_rev,
+                         nh, hacc, x, y, N, damping, &g->ctr->pr_acc[2 * slot],
+                         &g->ctr->pr_acc[2 * slot + 1], g->ctr->pr_state);
       hipLaunchKernelGGL(k_pr_check, dim3(1), dim3(64), 0, stream, g->ctr, slot, tol_l1, max_iter);
       MK_LAUNCH(g, "pagerank iteration");
     }

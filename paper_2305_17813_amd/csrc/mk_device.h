@@ -207,6 +207,24 @@ __device__ inline void for_each_slab_strided(const DView& V, uint32_t v, uint32_
   }
 }
 
+// Walk buckets [b0, min(b1, nb)) of vertex v (a work item of a heavy vertex).
+template <class F>
+__device__ inline void for_each_bucket_range(const DView& V, uint32_t v, uint32_t b0, uint32_t b1, F&& f) {
+  const int gl = glane();
+  const uint64_t x = ld_word(slab_ptr(V, v) + gl);
+  const uint32_t nb = (uint32_t)(gbcast64(x, 15) >> 32);
+  const uint32_t xb = nb > 1 ? gbcast((uint32_t)x, 14) : 0u;
+  if (b1 > nb) b1 = nb;
+  for (uint32_t b = b0; b < b1; ++b) {
+    if (b == 0) {
+      walk_chain(V, v, x, nb > 1 ? kKeysPerSlab - 1 : kKeysPerSlab, f);
+    } else {
+      const uint32_t s = xb + b - 1;
+      walk_chain(V, s, ld_word(slab_ptr(V, s) + gl), kKeysPerSlab, f);
+    }
+  }
+}
+
 // Group-cooperative membership probe (SearchEdge): walk only the hashed chain of `u`.
 // Returns the data word when found, or kEmptyWord when absent.
 __device__ inline uint64_t probe(const DView& V, uint32_t u, uint32_t key) {

@@ -519,7 +519,7 @@ bool layout(const mk_config* c, uint64_t m, char* base, mk_graph* g, size_t* tot
   lg.st = cv.take<uint8_t>(L);
   lg.uf = cv.take<uint8_t>(L);
   Counters* ctr = cv.take<Counters>(1);
-  uint32_t* fq[4];
+  uint32_t* fq[6];
   for (auto& q : fq) q = cv.take<uint32_t>(N);
   uint32_t* mark = cv.take<uint32_t>(N);
   uint32_t* inval = cv.take<uint32_t>(N);
@@ -530,6 +530,7 @@ bool layout(const mk_config* c, uint64_t m, char* base, mk_graph* g, size_t* tot
   float* py = cv.take<float>(N);
   float* pc = cv.take<float>(N);
   uint32_t* hv = cv.take<uint32_t>(N);
+  double* hacc = cv.take<double>(N);
   uint64_t* tk0 = nullptr;
   uint64_t* tk1 = nullptr;
   size_t sort_bytes = 0, scan_bytes = 0;
@@ -549,7 +550,7 @@ bool layout(const mk_config* c, uint64_t m, char* base, mk_graph* g, size_t* tot
     g->log = lg;
     g->log_cap = L;
     g->ctr = ctr;
-    for (int i = 0; i < 4; ++i) g->fq[i] = fq[i];
+    for (int i = 0; i < 6; ++i) g->fq[i] = fq[i];
     g->mark = mark;
     g->inval = inval;
     g->bfs_D = bfsD;
@@ -559,6 +560,7 @@ bool layout(const mk_config* c, uint64_t m, char* base, mk_graph* g, size_t* tot
     g->pr_y = py;
     g->pr_c = pc;
     g->heavy_rev = hv;
+    g->pr_hacc = hacc;
     g->tc_keys[0] = tk0;
     g->tc_keys[1] = tk1;
     g->sort_tmp = sort_tmp;

@@ -43,7 +43,7 @@ struct AlgoState {
 };
 
 struct Counters {          // device-side scalars, one 4 KiB block
-  uint32_t frontier[8];    // rotating frontier sizes (light and heavy queues)
+  uint32_t frontier[12];   // rotating frontier sizes (light, heavy and giant queues)
   uint32_t inval;          // invalidated-vertex list size
   uint32_t pad0[7];
   unsigned long long tc_s[3];  // S1, S2, S3 of the triangle batch identity
@@ -75,7 +75,7 @@ struct mk_graph {
 
   // traversal scratch
   mk::Counters* ctr = nullptr;
-  uint32_t* fq[4] = {nullptr, nullptr, nullptr, nullptr};  // light cur/next, heavy cur/next
+  uint32_t* fq[6] = {};      // light, heavy and giant frontier queues (two of each)
   uint32_t* mark = nullptr;
   uint32_t* inval = nullptr;
   uint32_t stamp = 0;
@@ -88,7 +88,8 @@ struct mk_graph {
   float* pr_x = nullptr;      // current ranks
   float* pr_y = nullptr;      // next ranks
   float* pr_c = nullptr;      // contribution per vertex
-  uint32_t* heavy_rev = nullptr;  // rev-view vertices walked by a block
+  uint32_t* heavy_rev = nullptr;  // rev-view vertices split into bucket work items
+  double* pr_hacc = nullptr;      // FP64 partial sums of the heavy vertices
   uint32_t n_heavy_rev = 0;
   bool heavy_rev_ok = false;
 

@@ -32,23 +32,32 @@ __device__ inline uint64_t tree_node(uint64_t dist, uint32_t parent) {
   return (dist << 32) | parent;
 }
 
-__device__ inline void push_vertex(const uint32_t* nbk, uint32_t* Lq, uint32_t* Lc, uint32_t* Hq,
-                                   uint32_t* Hc, uint32_t* mark, uint32_t stamp, bool p, uint32_t v) {
+constexpr uint32_t kGiantBuckets = 512;  // vertices with more buckets are split over 256 groups
+constexpr uint32_t kGiantSplit = 256;
+
+// Where pushed vertices go: light (<= kHeavyBuckets buckets), heavy (<= kGiantBuckets)
+// and giant queues with their size counters.
+struct PushQ {
+  uint32_t* q[3];
+  uint32_t* c[3];
+};
+
+__device__ inline void push_vertex(const uint32_t* nbk, const PushQ& Q, uint32_t* mark, uint32_t stamp,
+                                   bool p, uint32_t v) {
   bool take = false;
   if (p) take = atomicExch(mark + v, stamp) != stamp;
-  bool heavy = false;
-  if (take) heavy = nbk[v] > kHeavyBuckets;
-  wave_push(Lq, Lc, take && !heavy, v);
-  wave_push(Hq, Hc, take && heavy, v);
+  uint32_t nb = 0;
+  if (take) nb = nbk[v];
+  wave_push(Q.q[0], Q.c[0], take && nb <= kHeavyBuckets, v);
+  wave_push(Q.q[1], Q.c[1], take && nb > kHeavyBuckets && nb <= kGiantBuckets, v);
+  wave_push(Q.q[2], Q.c[2], take && nb > kGiantBuckets, v);
 }
 
 struct Queues {
-  const uint32_t* Lcur;
-  const uint32_t* Hcur;
-  uint32_t* Lnext;
-  uint32_t* Hnext;
-  uint32_t* cnt;  // [0..2] light sizes, [3..5] heavy sizes (rotating)
-  int icur, inext, iclear;
+  const uint32_t* cur[3];  // light, heavy, giant
+  PushQ next;
+  uint32_t* cnt;  // [3k .. 3k+2]: rotating sizes of queue k
+  int icur, iclear;
 };
 
 // Relax every out-arc of u held in one slab word per lane.
@@ -62,30 +71,51 @@ __device__ inline void relax_word(const DView& F, uint64_t* D, uint32_t u, uint6
     const uint64_t cand = tree_node(du + w, u);
     if (cand < D[v]) improve = amin64(D + v, cand) > cand;
   }
-  push_vertex(F.nbk, q.Lnext, q.cnt + q.inext, q.Hnext, q.cnt + 3 + q.inext, mark, stamp, improve, v);
+  push_vertex(F.nbk, q.next, mark, stamp, improve, v);
 }
 
 template <bool kUnit>
 __global__ void __launch_bounds__(kBlock) k_expand(DView F, uint64_t* D, Queues q, uint32_t* mark,
                                                    uint32_t stamp) {
-  const uint32_t nl = q.cnt[q.icur], nh = q.cnt[3 + q.icur];
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    q.cnt[q.iclear] = 0;
-    q.cnt[3 + q.iclear] = 0;
+  const uint32_t nl = q.cnt[q.icur], nh = q.cnt[3 + q.icur], ngi = q.cnt[6 + q.icur];
+  if (blockIdx.x == 0 && threadIdx.x < 3) q.cnt[3 * threadIdx.x + q.iclear] = 0;
+  if (nl == 0 && nh == 0 && ngi == 0) return;
+  // single-bucket frontier vertices: one lane each (64 slab reads in flight per wave)
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nl; i += gridDim.x * blockDim.x) {
+    const uint32_t u = q.cur[0][i];
+    if (F.nbk[u] != 1) continue;
+    const uint64_t du = ld_u64_coherent(D + u) >> 32;
+    Slab sl;
+    uint32_t t = u;
+    while (true) {
+      load_slab(F, t, sl);
+#pragma unroll
+      for (int j = 0; j < kKeysPerSlab; ++j) relax_word<kUnit>(F, D, u, du, sl.w[j], true, q, mark, stamp);
+      t = (uint32_t)sl.w[15];
+      if (t == kInvalid) break;
+    }
   }
-  if (nl == 0 && nh == 0) return;
+  // other light vertices: one 16-lane group each
   const uint32_t g0 = (blockIdx.x * kBlock + threadIdx.x) / kGroup;
   const uint32_t ng = gridDim.x * kGroupsPerBlock;
   for (uint32_t i = g0; i < nl; i += ng) {
-    const uint32_t u = q.Lcur[i];
+    const uint32_t u = q.cur[0][i];
+    if (F.nbk[u] == 1) continue;
     const uint64_t du = ld_u64_coherent(D + u) >> 32;
     for_each_slab(F, u, [&](uint64_t x, bool data) { relax_word<kUnit>(F, D, u, du, x, data, q, mark, stamp); });
   }
   const uint32_t gib = threadIdx.x / kGroup;
   for (uint32_t j = blockIdx.x; j < nh; j += gridDim.x) {
-    const uint32_t u = q.Hcur[j];
+    const uint32_t u = q.cur[1][j];
     const uint64_t du = ld_u64_coherent(D + u) >> 32;
     for_each_slab_strided(F, u, gib, kGroupsPerBlock, [&](uint64_t x, bool data) {
+      relax_word<kUnit>(F, D, u, du, x, data, q, mark, stamp);
+    });
+  }
+  for (uint32_t it = g0; it < ngi * kGiantSplit; it += ng) {  // giant: kGiantSplit groups each
+    const uint32_t u = q.cur[2][it / kGiantSplit];
+    const uint64_t du = ld_u64_coherent(D + u) >> 32;
+    for_each_slab_strided(F, u, it % kGiantSplit, kGiantSplit, [&](uint64_t x, bool data) {
       relax_word<kUnit>(F, D, u, du, x, data, q, mark, stamp);
     });
   }
@@ -98,27 +128,23 @@ __global__ void k_trav_init(uint64_t* D, uint32_t nv, uint32_t src) {
 
 // Reset the rotating counters so that slot 0 is the current frontier.
 __global__ void k_queue_reset(uint32_t* cnt, uint32_t* inval_cnt) {
-  if (threadIdx.x < 6) cnt[threadIdx.x] = 0;
+  if (threadIdx.x < 9) cnt[threadIdx.x] = 0;
   if (threadIdx.x == 0 && inval_cnt) *inval_cnt = 0;
 }
 
-__global__ void k_seed_source(DView F, uint32_t src, uint32_t* Lq, uint32_t* Hq, uint32_t* cnt,
-                              uint32_t* mark, uint32_t stamp) {
+__global__ void k_seed_source(DView F, uint32_t src, PushQ Q, uint32_t* mark, uint32_t stamp) {
   if (threadIdx.x != 0) return;
   mark[src] = stamp;
-  if (F.nbk[src] > kHeavyBuckets) {
-    Hq[0] = src;
-    cnt[3] = 1;
-  } else {
-    Lq[0] = src;
-    cnt[0] = 1;
-  }
+  const uint32_t nb = F.nbk[src];
+  const int k = nb <= kHeavyBuckets ? 0 : (nb <= kGiantBuckets ? 1 : 2);
+  Q.q[k][0] = src;
+  *Q.c[k] = 1;
 }
 
 // Insert prologue: relax each effective inserted arc.
 template <bool kUnit>
-__global__ void k_relax_batch(DView F, uint64_t* D, Log lg, uint64_t n, uint32_t* Lq, uint32_t* Hq,
-                              uint32_t* cnt, uint32_t* mark, uint32_t stamp) {
+__global__ void k_relax_batch(DView F, uint64_t* D, Log lg, uint64_t n, PushQ Q, uint32_t* mark,
+                              uint32_t stamp) {
   // whole waves step together so that the wave-wide push sees every lane
   const uint64_t lane = threadIdx.x & 63;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -136,14 +162,13 @@ __global__ void k_relax_batch(DView F, uint64_t* D, Log lg, uint64_t n, uint32_t
         if (cand < D[v]) improve = amin64(D + v, cand) > cand;
       }
     }
-    push_vertex(F.nbk, Lq, cnt, Hq, cnt + 3, mark, stamp, improve, v);
+    push_vertex(F.nbk, Q, mark, stamp, improve, v);
   }
 }
 
 // Delete prologue, step 1: a deleted arc (u, v) of the dependence tree invalidates v.
-__global__ void k_invalidate(DView F, uint64_t* D, Log lg, uint64_t n, uint32_t* Lq, uint32_t* Hq,
-                             uint32_t* cnt, uint32_t* inval, uint32_t* inval_cnt, uint32_t* mark,
-                             uint32_t stamp) {
+__global__ void k_invalidate(DView F, uint64_t* D, Log lg, uint64_t n, PushQ Q, uint32_t* inval,
+                             uint32_t* inval_cnt, uint32_t* mark, uint32_t stamp) {
   const uint64_t lane = threadIdx.x & 63;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x - lane; base < n;
@@ -158,7 +183,7 @@ __global__ void k_invalidate(DView F, uint64_t* D, Log lg, uint64_t n, uint32_t*
       if (dv != kTreeNone && (uint32_t)dv == u) hit = cas64(D + v, dv, kTreeNone) == dv;
     }
     wave_push(inval, inval_cnt, hit, v);
-    push_vertex(F.nbk, Lq, cnt, Hq, cnt + 3, mark, stamp, hit, v);
+    push_vertex(F.nbk, Q, mark, stamp, hit, v);
   }
 }
 
@@ -174,30 +199,33 @@ __device__ inline void inval_word(const DView& F, uint64_t* D, uint32_t x_parent
     if (dy != kTreeNone && (uint32_t)dy == x_parent) hit = cas64(D + y, dy, kTreeNone) == dy;
   }
   wave_push(inval, inval_cnt, hit, y);
-  push_vertex(F.nbk, q.Lnext, q.cnt + q.inext, q.Hnext, q.cnt + 3 + q.inext, mark, stamp, hit, y);
+  push_vertex(F.nbk, q.next, mark, stamp, hit, y);
 }
 
 __global__ void __launch_bounds__(kBlock) k_propagate(DView F, uint64_t* D, Queues q, uint32_t* inval,
                                                       uint32_t* inval_cnt, uint32_t* mark,
                                                       uint32_t stamp) {
-  const uint32_t nl = q.cnt[q.icur], nh = q.cnt[3 + q.icur];
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    q.cnt[q.iclear] = 0;
-    q.cnt[3 + q.iclear] = 0;
-  }
-  if (nl == 0 && nh == 0) return;
+  const uint32_t nl = q.cnt[q.icur], nh = q.cnt[3 + q.icur], ngi = q.cnt[6 + q.icur];
+  if (blockIdx.x == 0 && threadIdx.x < 3) q.cnt[3 * threadIdx.x + q.iclear] = 0;
+  if (nl == 0 && nh == 0 && ngi == 0) return;
   const uint32_t g0 = (blockIdx.x * kBlock + threadIdx.x) / kGroup;
   const uint32_t ng = gridDim.x * kGroupsPerBlock;
   for (uint32_t i = g0; i < nl; i += ng) {
-    const uint32_t x = q.Lcur[i];
+    const uint32_t x = q.cur[0][i];
     for_each_slab(F, x, [&](uint64_t w, bool data) {
       inval_word(F, D, x, w, data, q, inval, inval_cnt, mark, stamp);
     });
   }
   const uint32_t gib = threadIdx.x / kGroup;
   for (uint32_t j = blockIdx.x; j < nh; j += gridDim.x) {
-    const uint32_t x = q.Hcur[j];
+    const uint32_t x = q.cur[1][j];
     for_each_slab_strided(F, x, gib, kGroupsPerBlock, [&](uint64_t w, bool data) {
+      inval_word(F, D, x, w, data, q, inval, inval_cnt, mark, stamp);
+    });
+  }
+  for (uint32_t it = g0; it < ngi * kGiantSplit; it += ng) {
+    const uint32_t x = q.cur[2][it / kGiantSplit];
+    for_each_slab_strided(F, x, it % kGiantSplit, kGiantSplit, [&](uint64_t w, bool data) {
       inval_word(F, D, x, w, data, q, inval, inval_cnt, mark, stamp);
     });
   }
@@ -208,8 +236,7 @@ __global__ void __launch_bounds__(kBlock) k_propagate(DView F, uint64_t* D, Queu
 template <bool kUnit>
 __global__ void __launch_bounds__(kBlock) k_dec_pull(DView F, DView R, uint64_t* D,
                                                      const uint32_t* inval, const uint32_t* inval_cnt,
-                                                     uint32_t* Lq, uint32_t* Hq, uint32_t* cnt,
-                                                     uint32_t* mark, uint32_t stamp) {
+                                                     PushQ Q, uint32_t* mark, uint32_t stamp) {
   const uint32_t n = *inval_cnt;
   const uint32_t g0 = (blockIdx.x * kBlock + threadIdx.x) / kGroup;
   const uint32_t ng = gridDim.x * kGroupsPerBlock;
@@ -229,7 +256,7 @@ __global__ void __launch_bounds__(kBlock) k_dec_pull(DView F, DView R, uint64_t*
     best = gmin_u64(best);
     bool improve = false;
     if (glane() == 0 && best != kTreeNone) improve = amin64(D + y, best) > best;
-    push_vertex(F.nbk, Lq, cnt, Hq, cnt + 3, mark, stamp, improve, y);
+    push_vertex(F.nbk, Q, mark, stamp, improve, y);
   }
 }
 
@@ -253,10 +280,10 @@ inline uint32_t blocks_for(uint64_t n, uint32_t cap = 4096) {
 // or a caller workspace for a one-off traversal that other reads may overlap.
 struct TravCtx {
   uint64_t* D;
-  uint32_t* fq[4];
+  uint32_t* fq[6];  // light, heavy and giant queues, two of each
   uint32_t* mark;
   uint32_t* inval;
-  uint32_t* cnt;        // rotating frontier sizes [8]
+  uint32_t* cnt;        // rotating frontier sizes [9]
   uint32_t* inval_cnt;  // invalidated-list size
   uint32_t* stamp;      // host-side stamp counter
   uint64_t* h_pin;      // pinned host words for size read-backs
@@ -265,7 +292,7 @@ struct TravCtx {
 TravCtx graph_ctx(mk_graph* g, uint64_t* D) {
   TravCtx c;
   c.D = D;
-  for (int i = 0; i < 4; ++i) c.fq[i] = g->fq[i];
+  for (int i = 0; i < 6; ++i) c.fq[i] = g->fq[i];
   c.mark = g->mark;
   c.inval = g->inval;
   c.cnt = g->ctr->frontier;
@@ -275,16 +302,27 @@ TravCtx graph_ctx(mk_graph* g, uint64_t* D) {
   return c;
 }
 
+// The queues of iteration 0 (and of every prologue): fq[0], fq[2], fq[4] with slot 0.
+PushQ first_push(const TravCtx& c) {
+  PushQ Q;
+  for (int k = 0; k < 3; ++k) {
+    Q.q[k] = c.fq[2 * k];
+    Q.c[k] = c.cnt + 3 * k;
+  }
+  return Q;
+}
+
 Queues queues(const TravCtx& c, uint64_t it) {
   Queues q;
   const int a = (int)(it & 1);
-  q.Lcur = c.fq[a];
-  q.Lnext = c.fq[a ^ 1];
-  q.Hcur = c.fq[2 + a];
-  q.Hnext = c.fq[2 + (a ^ 1)];
+  const int inext = (int)((it + 1) % 3);
+  for (int k = 0; k < 3; ++k) {
+    q.cur[k] = c.fq[2 * k + a];
+    q.next.q[k] = c.fq[2 * k + (a ^ 1)];
+    q.next.c[k] = c.cnt + 3 * k + inext;
+  }
   q.cnt = c.cnt;
   q.icur = (int)(it % 3);
-  q.inext = (int)((it + 1) % 3);
   q.iclear = (int)((it + 2) % 3);
   return q;
 }
@@ -300,10 +338,10 @@ mk_status run_frontier(mk_graph* g, const TravCtx& c, hipStream_t stream, Launch
       MK_LAUNCH(g, "frontier kernel");
     }
     const int slot = (int)(it % 3);
-    MK_HIP(g, hipMemcpyAsync(c.h_pin, c.cnt, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
+    MK_HIP(g, hipMemcpyAsync(c.h_pin, c.cnt, 9 * sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
     MK_HIP(g, hipStreamSynchronize(stream));
     const uint32_t* h = reinterpret_cast<const uint32_t*>(c.h_pin);
-    if (h[slot] == 0 && h[3 + slot] == 0) break;
+    if (h[slot] == 0 && h[3 + slot] == 0 && h[6 + slot] == 0) break;
   }
   return MK_OK;
 }
@@ -323,8 +361,8 @@ mk_status static_from(mk_graph* g, const TravCtx& c, uint32_t source, hipStream_
   const uint32_t stamp0 = ++*c.stamp;
   hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, stream, c.cnt, c.inval_cnt);
   hipLaunchKernelGGL(k_trav_init, dim3(blocks_for(g->n)), dim3(kBlock), 0, stream, c.D, g->n, source);
-  hipLaunchKernelGGL(k_seed_source, dim3(1), dim3(64), 0, stream, F, source, c.fq[0], c.fq[2], c.cnt,
-                     c.mark, stamp0);
+  hipLaunchKernelGGL(k_seed_source, dim3(1), dim3(64), 0, stream, F, source, first_push(c), c.mark,
+                     stamp0);
   MK_LAUNCH(g, "traversal init");
   return run_expand<kUnit>(g, c, stream);
 }
@@ -351,14 +389,14 @@ mk_status traverse(mk_graph* g, AlgoState& st, uint64_t* D, uint32_t source, uin
         Log lg = g->log;
         lg.s += b->off; lg.d += b->off; lg.w += b->off; lg.st += b->off; lg.uf += b->off;
         hipLaunchKernelGGL(k_relax_batch<kUnit>, dim3(blocks_for(b->n)), dim3(kBlock), 0, stream, F, D,
-                           lg, b->n, c.fq[0], c.fq[2], c.cnt, c.mark, stamp0);
+                           lg, b->n, first_push(c), c.mark, stamp0);
       }
     } else {  // deletions only
       for (const BatchRec* b : p.list) {
         Log lg = g->log;
         lg.s += b->off; lg.d += b->off; lg.w += b->off; lg.st += b->off; lg.uf += b->off;
         hipLaunchKernelGGL(k_invalidate, dim3(blocks_for(b->n)), dim3(kBlock), 0, stream, F, D, lg, b->n,
-                           c.fq[0], c.fq[2], c.cnt, c.inval, c.inval_cnt, c.mark, stamp0);
+                           first_push(c), c.inval, c.inval_cnt, c.mark, stamp0);
       }
       MK_LAUNCH(g, "k_invalidate");
       mk_status s = run_frontier(g, c, stream, [&](Queues q, uint32_t stamp) {
@@ -369,7 +407,7 @@ mk_status traverse(mk_graph* g, AlgoState& st, uint64_t* D, uint32_t source, uin
       hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, stream, c.cnt, nullptr);
       const uint32_t stamp1 = ++g->stamp;
       hipLaunchKernelGGL(k_dec_pull<kUnit>, dim3(kExpandBlocks), dim3(kBlock), 0, stream, F,
-                         g->view[VR].d, D, c.inval, c.inval_cnt, c.fq[0], c.fq[2], c.cnt, c.mark, stamp1);
+                         g->view[VR].d, D, c.inval, c.inval_cnt, first_push(c), c.mark, stamp1);
     }
     MK_LAUNCH(g, "traversal prologue");
     mk_status s = run_expand<kUnit>(g, c, stream);
@@ -384,8 +422,8 @@ mk_status traverse(mk_graph* g, AlgoState& st, uint64_t* D, uint32_t source, uin
 }
 
 size_t ws_bytes_for(uint32_t n) {
-  // D (8 B), four queues, stamps and the invalidated list (4 B each), counters
-  return (size_t)n * (8 + 6 * 4) + 512 + 8 * 256;
+  // D (8 B), six queues, stamps and the invalidated list (4 B each), counters
+  return (size_t)n * (8 + 8 * 4) + 512 + 10 * 256;
 }
 
 }  // namespace
@@ -423,11 +461,11 @@ mk_status mk_traverse_from(mk_graph* g, uint32_t source, int weighted, void* d_w
   };
   TravCtx c;
   c.D = reinterpret_cast<uint64_t*>(take((size_t)N * 8));
-  for (int i = 0; i < 4; ++i) c.fq[i] = reinterpret_cast<uint32_t*>(take((size_t)N * 4));
+  for (int i = 0; i < 6; ++i) c.fq[i] = reinterpret_cast<uint32_t*>(take((size_t)N * 4));
   c.mark = reinterpret_cast<uint32_t*>(take((size_t)N * 4));
   c.inval = reinterpret_cast<uint32_t*>(take((size_t)N * 4));
   c.cnt = reinterpret_cast<uint32_t*>(take(64));
-  c.inval_cnt = c.cnt + 8;
+  c.inval_cnt = c.cnt + 12;
   uint32_t stamp = 0;
   c.stamp = &stamp;
   c.h_pin = g->slot_pin[slot];
