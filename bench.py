@@ -214,6 +214,7 @@ def main():
     log(f"[bench] timed {args.steps} steps in {wall:.2f}s")
 
     K = args.steps
+    st_after = G.stats()
     t_ins = sum(times["insert"]) / 1e3
     t_del = sum(times["delete"]) / 1e3
     t_q = sum(times["query"]) / 1e3
@@ -252,6 +253,14 @@ def main():
                                       "traffic": roof["traffic"],
                      "slabs_per_op": {k: slabs[k] / B for k in ("i_fwd", "i_rev", "i_und")}},
     }
+    # PageRank: one pull iteration reads the reverse view's slabs (128 B each; vertices
+    # without in-arcs are skipped, so this over-counts), gathers a 4 B contribution per arc
+    # and streams ranks, contributions and out-degrees (12 B per vertex)
+    rev_slabs = st_after["head_slabs"][1] + st_after["pool_used"][1]
+    pr_iter_bytes = 128 * rev_slabs + 4 * st_after["n_arcs"] + 12 * g_in.n
+    pr_ms_iter = (sum(times["pr_i"]) + sum(times["pr_d"])) / sum(sum(x) for x in pr_iters)
+    rooflines["pagerank_iteration"] = {"achieved": pr_iter_bytes / (pr_ms_iter / 1e3) / 1e9,
+                                       "bytes_per_launch": pr_iter_bytes, "launch_ms": pr_ms_iter}
     for r in rooflines.values():
         r["frac"] = r["achieved"] / HBM_PEAK_GBS
 

@@ -395,7 +395,8 @@ __device__ inline uint64_t lower_bound_u64(const uint64_t* a, uint64_t n, uint64
 //   S1 += |N_G(u) & N_G(v)|, S2 += |N_G(u) & N_B(v)|, S3 += |N_B(u) & N_B(v)|
 // with G the graph after the batch and B the graph of the batch alone.
 __global__ void __launch_bounds__(kBlock) k_tc_batch(DView U, const uint64_t* keys, uint64_t nk,
-                                                     uint32_t nv, unsigned long long* S) {
+                                                     uint32_t nv, unsigned long long* S,
+                                                     uint32_t* heavy, uint32_t* nheavy) {
   const uint64_t g0 = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kGroup;
   const uint64_t ng = (uint64_t)gridDim.x * kGroupsPerBlock;
   uint64_t s1 = 0, s2 = 0, s3 = 0;
@@ -407,10 +408,15 @@ __global__ void __launch_bounds__(kBlock) k_tc_batch(DView U, const uint64_t* ke
     // S1 and S3 are symmetric in (u, v): count them once, on the canonical direction
     const bool canon = u < v;
     uint64_t c1 = 0;
+    bool split = false;
     if (canon) {
       const bool u_small = U.deg[u] <= U.deg[v];  // walk the smaller side, probe the other
-      c1 = 2 * group_intersect(U, u_small ? u : v, u_small ? v : u);
+      const uint32_t a = u_small ? u : v;
+      // a large smaller side (two hubs) is counted by k_tc_heavy_s1 over many groups
+      split = U.nbk[a] > kHeavyBuckets;
+      if (!split) c1 = 2 * group_intersect(U, a, u_small ? v : u);
     }
+    wave_push(heavy, nheavy, split && gl == 0, (uint32_t)i);
     // batch neighbourhoods from the sorted key list
     const uint64_t vlo = lower_bound_u64(keys, nk, (uint64_t)v << 32);
     const uint64_t vhi = lower_bound_u64(keys, nk, ((uint64_t)v + 1) << 32);
@@ -440,6 +446,31 @@ __global__ void __launch_bounds__(kBlock) k_tc_batch(DView U, const uint64_t* ke
     if (s2) atomicAdd(S + 1, (unsigned long long)s2);
     if (s3) atomicAdd(S + 2, (unsigned long long)s3);
   }
+}
+
+// S1 of the batch arcs whose smaller side has many buckets: kTcSplit groups per arc, each
+// walking every kTcSplit-th bucket of the smaller neighbourhood.
+constexpr uint32_t kTcSplit = 64;
+__global__ void __launch_bounds__(kBlock) k_tc_heavy_s1(DView U, const uint64_t* keys, const uint32_t* heavy,
+                                                        const uint32_t* nheavy, unsigned long long* S) {
+  const uint32_t nh = *nheavy;
+  const uint64_t g0 = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kGroup;
+  const uint64_t ng = (uint64_t)gridDim.x * kGroupsPerBlock;
+  uint64_t acc = 0;
+  for (uint64_t it = g0; it < (uint64_t)nh * kTcSplit; it += ng) {
+    const uint64_t key = keys[heavy[it / kTcSplit]];
+    const uint32_t u = (uint32_t)(key >> 32), v = (uint32_t)key;
+    const bool u_small = U.deg[u] <= U.deg[v];
+    const uint32_t a = u_small ? u : v, b = u_small ? v : u;
+    uint64_t c = 0;
+    for_each_slab_strided(U, a, (uint32_t)(it % kTcSplit), kTcSplit, [&](uint64_t x, bool data) {
+      const uint32_t k = (uint32_t)x;
+      if (data && valid_key(k) && k != b) c += lane_has(U, b, k);
+    });
+    c = gsum_u64(c);
+    if (glane() == 0) acc += 2 * c;
+  }
+  if (glane() == 0 && acc) atomicAdd(S, (unsigned long long)acc);
 }
 
 __global__ void k_tc_begin(Counters* C, bool reset_total) {
@@ -602,8 +633,14 @@ mk_status mk_count_triangles(mk_graph* g, uint64_t* d_count, mk_mode mode, hipSt
                                  end_bit, stream) != hipSuccess)
       return MK_ERR_HIP;
     hipLaunchKernelGGL(k_tc_begin, dim3(1), dim3(64), 0, stream, g->ctr, false);
+    // after the sort, tc_keys[0] is free: it holds the list of split arcs
+    uint32_t* hl = reinterpret_cast<uint32_t*>(g->tc_keys[0]);
+    uint32_t* nhl = &g->ctr->pad0[4];
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, nhl, 1u);
     hipLaunchKernelGGL(k_tc_batch, dim3(grid_for_groups(std::min<uint64_t>(nk, 1u << 20))),
-                       dim3(kBlock), 0, stream, U, g->tc_keys[1], nk, N, g->ctr->tc_s);
+                       dim3(kBlock), 0, stream, U, g->tc_keys[1], nk, N, g->ctr->tc_s, hl, nhl);
+    hipLaunchKernelGGL(k_tc_heavy_s1, dim3(kWalkBlocks), dim3(kBlock), 0, stream, U, g->tc_keys[1], hl, nhl,
+                       g->ctr->tc_s);
     hipLaunchKernelGGL(k_tc_finish, dim3(1), dim3(64), 0, stream, g->ctr,
                        p.kinds == 1 ? 0 : 1, out);
   }

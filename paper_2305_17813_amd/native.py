@@ -249,8 +249,10 @@ class Graph:
         _check(self.lib.mk_incr_wcc(self.h, _ptr(lab), mode, self._s(stream)), "mk_incr_wcc")
         return lab
 
-    def pagerank(self, damping: float = 0.85, tol: float = 1e-9, max_iter: int = 500,
+    def pagerank(self, damping: float = 0.85, tol: float = 5e-8, max_iter: int = 500,
                  mode: int = AUTO, stream=None):
+        """PageRank; the default stop (iteration L1 change <= 5e-8) bounds the distance to the
+        fixed point by d/(1-d) * 5e-8 = 2.8e-7 in L1, inside the 1e-6 budget."""
         r = torch.empty(self.n, dtype=torch.float32, device=self.device)
         it = torch.zeros(1, dtype=torch.int32, device=self.device)
         _check(self.lib.mk_incr_pagerank(self.h, float(damping), float(tol), int(max_iter), _ptr(r),
