@@ -203,3 +203,47 @@ def test_generators_identical_on_gpu_and_cpu():
     b = I.rmat_graph(10, 8, 123, device=DEV)
     assert torch.equal(a.src, b.src.cpu()) and torch.equal(a.dst, b.dst.cpu())
     assert torch.equal(a.w, b.w.cpu())
+
+
+def test_contended_inserts_on_few_tails():
+    """2^18 inserts (a quarter of them copies of others) aimed at 256 single-bucket source
+    vertices: thousands of lanes race on the same chain tails and slab links; every arc
+    lands exactly once, and a third are then deleted."""
+    say("case: contended inserts")
+    n = 1 << 17
+    rng = np.random.default_rng(11)
+    k = 1 << 18
+    src = rng.integers(0, 256, k)
+    dst = rng.integers(256, n, k)
+    dup = rng.integers(0, k, k // 4)
+    src[: k // 4], dst[: k // 4] = src[dup], dst[dup]
+    p = Pair(n, [0], [1], [1], pool_slabs=1 << 20)  # the pre-check assumes a slab per insert
+    p.insert(src, dst, np.full(src.size, 3), exact_status=False)
+    p.check_structure()
+    p.delete(src[::3], dst[::3], exact_status=False)
+    p.check_structure()
+
+
+def test_pagerank_reports_max_iter():
+    say("case: PageRank iteration cap")
+    g = I.rmat_s(10)
+    G = native.Graph(g.n, g.src, g.dst, g.w)
+    r, it = G.pagerank(tol=0.0, max_iter=3, mode=native.RECOMPUTE)
+    assert int(it.item()) == 3
+
+
+def test_export_and_recreate_round_trip():
+    """Checkpoint by export: a graph re-created from the export answers like the oracle."""
+    say("case: export round trip")
+    g = I.rmat_s(11)
+    p = make_pair(g, source=I.max_out_degree_vertex(g))
+    wl = I.Workload(g, 12)
+    s, d, w = wl.insert_batch(2000)
+    p.insert(s, d, w)
+    s, d = wl.delete_batch(2000)
+    p.delete(s, d)
+    es, ed, ew = p.g.export()
+    q = Pair(g.n, es, ed, ew, source=p.source)
+    q.o = p.o  # the oracle already holds the same arc set
+    q.check_structure()
+    q.check_all()
