@@ -65,6 +65,10 @@ typedef struct {
                             the edge-count hint with room for later inserts                  */
   uint64_t log_capacity; /* update ops remembered for incremental algorithms (ring of
                             batches); 0 = max(2^20, edge hint / 8)                           */
+  uint32_t sssp_delta;   /* width of one distance band of the weighted frontier epilogue
+                            (vertices are expanded band by band, nearest first); 0 = derived
+                            from the initial mean weight and mean out-degree                 */
+  uint32_t reserved;     /* must be 0                                                        */
 } mk_config;
 
 typedef struct {

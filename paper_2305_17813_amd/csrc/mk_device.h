@@ -117,6 +117,24 @@ __device__ inline void wave_push(uint32_t* q, uint32_t* ctr, bool p, uint32_t v)
   if (p) q[base + lanes_below(m)] = v;
 }
 
+// Wave-aggregated reservation of `cnt` (0..15) slots per lane: one atomic per wave; the
+// exclusive prefix over the active lanes comes from one ballot per bit of the count, so
+// inactive lanes never contribute.  Returns this lane's first slot.
+__device__ inline uint32_t wave_reserve(uint32_t* ctr, uint32_t cnt) {
+  uint32_t excl = 0, total = 0;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const uint64_t m = __ballot((cnt >> b) & 1u);
+    excl += lanes_below(m) << b;
+    total += (uint32_t)__popcll(m) << b;
+  }
+  if (total == 0) return 0;
+  const int leader = __builtin_ctzll(__ballot(true));
+  uint32_t base = 0;
+  if (lane64() == leader) base = atomicAdd(ctr, total);
+  return __shfl(base, leader) + excl;
+}
+
 // ----------------------------------------------------------------- memory access
 // Slab words are read with relaxed atomic loads of wavefront scope: ordinary cached
 // loads for the hardware, but the compiler may not merge or hoist them across the CASes

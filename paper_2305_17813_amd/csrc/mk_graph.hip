@@ -461,7 +461,7 @@ struct Carver {
 
 bool config_ok(const mk_config* c) {
   return c && c->n_vertices >= 1 && c->n_vertices <= (1u << 30) && c->load_factor >= 0.f &&
-         c->load_factor <= 64.f;
+         c->load_factor <= 64.f && c->reserved == 0;
 }
 
 uint64_t view_arcs(int v, uint64_t m) { return v == VU ? 2 * m : m; }
@@ -523,6 +523,9 @@ bool layout(const mk_config* c, uint64_t m, char* base, mk_graph* g, size_t* tot
   for (auto& q : fq) q = cv.take<uint32_t>(N);
   uint32_t* mark = cv.take<uint32_t>(N);
   uint32_t* inval = cv.take<uint32_t>(N);
+  uint32_t* far0 = cv.take<uint32_t>(N);
+  uint32_t* far1 = cv.take<uint32_t>(N);
+  uint32_t* far_mark = cv.take<uint32_t>(N);
   uint64_t* bfsD = cv.take<uint64_t>(N);
   uint64_t* ssspD = cv.take<uint64_t>(N);
   uint32_t* par = cv.take<uint32_t>(N);
@@ -553,6 +556,9 @@ bool layout(const mk_config* c, uint64_t m, char* base, mk_graph* g, size_t* tot
     for (int i = 0; i < 6; ++i) g->fq[i] = fq[i];
     g->mark = mark;
     g->inval = inval;
+    g->far[0] = far0;
+    g->far[1] = far1;
+    g->far_mark = far_mark;
     g->bfs_D = bfsD;
     g->sssp_D = ssspD;
     g->wcc_parent = par;
@@ -577,6 +583,16 @@ uint64_t hash_const(uint32_t seed, uint64_t salt) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
   return z ^ (z >> 31);
+}
+
+// Default band width of the weighted frontier epilogue: about kBandArcs arcs' worth of
+// mean weight spread over the mean out-degree, so that a band holds enough vertices to
+// fill the device while few of them are improved again after their expansion.
+constexpr double kBandArcs = 32.0;
+uint32_t default_band(uint64_t m, uint32_t n, double mean_w) {
+  const double deg = std::max(1.0, (double)m / std::max<uint32_t>(n, 1));
+  const double b = std::ceil(kBandArcs * std::max(1.0, mean_w) / deg);
+  return (uint32_t)std::min(b, (double)(1u << 30));
 }
 
 mk_status refresh_pool(mk_graph* g, hipStream_t stream) {
@@ -715,10 +731,17 @@ mk_status mk_graph_create(const mk_config* cfg, void* d_arena, size_t arena_byte
     hipLaunchKernelGGL(k_extra_total, dim3(1), dim3(64), 0, stream, vh.nbk, g->fq[1 + v], N,
                        &g->ctr->u64tmp[v]);
   }
-  if (hipMemcpyAsync(g->h_pin, g->ctr->u64tmp, 3 * sizeof(uint64_t), hipMemcpyDeviceToHost,
+  // the initial weight sum sets the default band width of the weighted epilogue
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, stream, (uint32_t*)&g->ctr->u64tmp[3], 2, 0u);
+  if (m && d_w)
+    hipLaunchKernelGGL(k_sum_u32, dim3(grid_stride_blocks(m, 1024)), dim3(kBlock), 0, stream, d_w,
+                       (uint32_t)std::min<uint64_t>(m, 0xFFFFFFFFu), &g->ctr->u64tmp[3]);
+  if (hipMemcpyAsync(g->h_pin, g->ctr->u64tmp, 4 * sizeof(uint64_t), hipMemcpyDeviceToHost,
                      stream) != hipSuccess ||
       hipStreamSynchronize(stream) != hipSuccess)
     return fail(MK_ERR_HIP);
+  g->sssp_delta = cfg->sssp_delta ? cfg->sssp_delta
+                                  : default_band(m, N, m ? (d_w ? (double)g->h_pin[3] / m : 1.0) : 1.0);
   for (int v = 0; v < 3; ++v) {
     ViewHost& vh = g->view[v];
     if (!vh.on) continue;
@@ -733,6 +756,7 @@ mk_status mk_graph_create(const mk_config* cfg, void* d_arena, size_t arena_byte
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, stream, vh.d.pool_ctr, 64, 0u);
   }
   hipLaunchKernelGGL(k_fill_u32, dim3(nb_blocks), dim3(kBlock), 0, stream, g->mark, N, 0u);
+  hipLaunchKernelGGL(k_fill_u32, dim3(nb_blocks), dim3(kBlock), 0, stream, g->far_mark, N, 0u);
   // bulk insert, in chunks that fit the change log (used here as scratch)
   for (uint64_t off = 0; off < m; off += g->log_cap) {
     const uint64_t k = std::min<uint64_t>(g->log_cap, m - off);

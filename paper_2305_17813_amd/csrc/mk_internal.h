@@ -43,7 +43,9 @@ struct AlgoState {
 };
 
 struct Counters {          // device-side scalars, one 4 KiB block
-  uint32_t frontier[12];   // rotating frontier sizes (light, heavy and giant queues)
+  uint32_t frontier[16];   // [0..8] rotating frontier sizes (light, heavy and giant
+                           // queues), [9..10] far-pile sizes, [11..12] band thresholds,
+                           // [13] smallest far distance
   uint32_t inval;          // invalidated-vertex list size
   uint32_t pad0[7];
   unsigned long long tc_s[3];  // S1, S2, S3 of the triangle batch identity
@@ -78,6 +80,9 @@ struct mk_graph {
   uint32_t* fq[6] = {};      // light, heavy and giant frontier queues (two of each)
   uint32_t* mark = nullptr;
   uint32_t* inval = nullptr;
+  uint32_t* far[2] = {};      // far piles of the weighted epilogue
+  uint32_t* far_mark = nullptr;
+  uint32_t sssp_delta = 0;    // band width of the weighted epilogue
   uint32_t stamp = 0;
   uint32_t rot = 0;           // frontier counter rotation
 

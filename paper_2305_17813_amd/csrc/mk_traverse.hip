@@ -16,6 +16,13 @@
 // not edges (a per-iteration stamp keeps each vertex once); subtree invalidation walks
 // the tree top-down through the forward view instead of walking every vertex's parent
 // chain to the source; vertices with many buckets are expanded by a whole block.
+//
+// Weighted epilogue in distance bands (near-far): an improved vertex joins the frontier
+// only if its new distance is below the current band's threshold T, else it waits on a
+// far pile.  When the frontier empties, the pile's smallest pending distance f gives the
+// next threshold f + delta, the pile entries below it form the next frontier and the
+// rest stay.  Any order of relaxations reaches the same unique fixed point; expanding
+// nearer vertices first only avoids re-expanding vertices whose distance drops again.
 #include <algorithm>
 
 #include "mk_internal.h"
@@ -53,6 +60,28 @@ __device__ inline void push_vertex(const uint32_t* nbk, const PushQ& Q, uint32_t
   wave_push(Q.q[2], Q.c[2], take && nb > kGiantBuckets, v);
 }
 
+// Near-far routing of the weighted epilogue.  T == nullptr: every push is near.
+struct Route {
+  const uint32_t* T;   // threshold of the current band
+  uint32_t* far;       // far pile of the current band and its size
+  uint32_t* far_cnt;
+  uint32_t* far_mark;  // band id of the last far push of each vertex
+  uint32_t band;
+};
+
+__device__ inline uint32_t band_limit(const Route& r) { return r.T ? *r.T : 0xFFFFFFFFu; }
+
+// Push v, improved to distance `dist`, into the near queues when dist < T, else onto the
+// far pile (once per band).
+__device__ inline void push_routed(const uint32_t* nbk, const PushQ& Q, const Route& r, uint32_t T,
+                                   uint32_t* mark, uint32_t stamp, bool p, uint32_t v, uint32_t dist) {
+  const bool near = p && dist < T;
+  bool take_far = false;
+  if (p && !near) take_far = atomicExch(r.far_mark + v, r.band) != r.band;
+  wave_push(r.far, r.far_cnt, take_far, v);
+  push_vertex(nbk, Q, mark, stamp, near, v);
+}
+
 struct Queues {
   const uint32_t* cur[3];  // light, heavy, giant
   PushQ next;
@@ -63,23 +92,90 @@ struct Queues {
 // Relax every out-arc of u held in one slab word per lane.
 template <bool kUnit>
 __device__ inline void relax_word(const DView& F, uint64_t* D, uint32_t u, uint64_t du, uint64_t x,
-                                  bool data, const Queues& q, uint32_t* mark, uint32_t stamp) {
+                                  bool data, const Queues& q, const Route& r, uint32_t T,
+                                  uint32_t* mark, uint32_t stamp) {
   const uint32_t v = (uint32_t)x;
   bool improve = false;
+  uint64_t cand = kTreeNone;
   if (data && valid_key(v)) {
     const uint64_t w = kUnit ? 1ull : (x >> 32);
-    const uint64_t cand = tree_node(du + w, u);
+    cand = tree_node(du + w, u);
     if (cand < D[v]) improve = amin64(D + v, cand) > cand;
   }
-  push_vertex(F.nbk, q.next, mark, stamp, improve, v);
+  push_routed(F.nbk, q.next, r, T, mark, stamp, improve, v, (uint32_t)(cand >> 32));
+}
+
+// Append the keys of the slab words selected by `mask` (bit j: word j) of every active lane
+// to q, with one counter atomic per wave.
+__device__ inline void push_words(uint32_t* q, uint32_t* ctr, uint32_t mask, const Slab& sl) {
+  if (__ballot(mask != 0) == 0) return;
+  uint32_t pos = wave_reserve(ctr, (uint32_t)__popc(mask));
+#pragma unroll
+  for (int j = 0; j < kKeysPerSlab; ++j)
+    if (mask >> j & 1) q[pos++] = (uint32_t)sl.w[j];
+}
+
+// Relax the 15 out-arcs of a whole slab held by one lane.  The distance loads, the atomic
+// minima, the frontier marks and the bucket counts are each issued as one independent
+// batch, and the pushes of the wave are appended with one counter atomic per queue.
+template <bool kUnit>
+__device__ inline void relax_slab_lane(const DView& F, uint64_t* D, uint32_t u, uint64_t du, const Slab& sl,
+                                       const Queues& q, const Route& r, uint32_t T, uint32_t* mark,
+                                       uint32_t stamp) {
+  uint64_t cand[kKeysPerSlab], cur[kKeysPerSlab];
+#pragma unroll
+  for (int j = 0; j < kKeysPerSlab; ++j) {
+    const uint32_t v = (uint32_t)sl.w[j];
+    const bool ok = valid_key(v);
+    cand[j] = ok ? tree_node(du + (kUnit ? 1ull : (sl.w[j] >> 32)), u) : kTreeNone;
+    cur[j] = ok ? D[v] : 0ull;
+  }
+#pragma unroll
+  for (int j = 0; j < kKeysPerSlab; ++j)
+    cur[j] = cand[j] < cur[j] ? amin64(D + (uint32_t)sl.w[j], cand[j]) : 0ull;
+  uint32_t near = 0, far = 0;
+#pragma unroll
+  for (int j = 0; j < kKeysPerSlab; ++j) {
+    if (cur[j] > cand[j]) {
+      if ((uint32_t)(cand[j] >> 32) < T) near |= 1u << j;
+      else far |= 1u << j;
+    }
+  }
+  uint32_t tk[kKeysPerSlab];
+#pragma unroll
+  for (int j = 0; j < kKeysPerSlab; ++j) {
+    const uint32_t v = (uint32_t)sl.w[j];
+    tk[j] = 0;
+    if (near >> j & 1) tk[j] = atomicExch(mark + v, stamp);
+    else if (far >> j & 1) tk[j] = atomicExch(r.far_mark + v, r.band);
+  }
+  uint32_t tn = 0, tf = 0;
+#pragma unroll
+  for (int j = 0; j < kKeysPerSlab; ++j) {
+    if ((near >> j & 1) && tk[j] != stamp) tn |= 1u << j;
+    if ((far >> j & 1) && tk[j] != r.band) tf |= 1u << j;
+  }
+#pragma unroll
+  for (int j = 0; j < kKeysPerSlab; ++j) tk[j] = (tn >> j & 1) ? F.nbk[(uint32_t)sl.w[j]] : 1u;
+  uint32_t heavy = 0, giant = 0;
+#pragma unroll
+  for (int j = 0; j < kKeysPerSlab; ++j) {
+    if (tk[j] > kGiantBuckets) giant |= 1u << j;
+    else if (tk[j] > kHeavyBuckets) heavy |= 1u << j;
+  }
+  push_words(q.next.q[0], q.next.c[0], tn & ~(heavy | giant), sl);
+  push_words(q.next.q[1], q.next.c[1], heavy, sl);
+  push_words(q.next.q[2], q.next.c[2], giant, sl);
+  push_words(r.far, r.far_cnt, tf, sl);
 }
 
 template <bool kUnit>
-__global__ void __launch_bounds__(kBlock) k_expand(DView F, uint64_t* D, Queues q, uint32_t* mark,
+__global__ void __launch_bounds__(kBlock) k_expand(DView F, uint64_t* D, Queues q, Route r, uint32_t* mark,
                                                    uint32_t stamp) {
   const uint32_t nl = q.cnt[q.icur], nh = q.cnt[3 + q.icur], ngi = q.cnt[6 + q.icur];
   if (blockIdx.x == 0 && threadIdx.x < 3) q.cnt[3 * threadIdx.x + q.iclear] = 0;
   if (nl == 0 && nh == 0 && ngi == 0) return;
+  const uint32_t T = band_limit(r);
   // single-bucket frontier vertices: one lane each (64 slab reads in flight per wave)
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nl; i += gridDim.x * blockDim.x) {
     const uint32_t u = q.cur[0][i];
@@ -89,8 +185,7 @@ __global__ void __launch_bounds__(kBlock) k_expand(DView F, uint64_t* D, Queues 
     uint32_t t = u;
     while (true) {
       load_slab(F, t, sl);
-#pragma unroll
-      for (int j = 0; j < kKeysPerSlab; ++j) relax_word<kUnit>(F, D, u, du, sl.w[j], true, q, mark, stamp);
+      relax_slab_lane<kUnit>(F, D, u, du, sl, q, r, T, mark, stamp);
       t = (uint32_t)sl.w[15];
       if (t == kInvalid) break;
     }
@@ -102,22 +197,76 @@ __global__ void __launch_bounds__(kBlock) k_expand(DView F, uint64_t* D, Queues 
     const uint32_t u = q.cur[0][i];
     if (F.nbk[u] == 1) continue;
     const uint64_t du = ld_u64_coherent(D + u) >> 32;
-    for_each_slab(F, u, [&](uint64_t x, bool data) { relax_word<kUnit>(F, D, u, du, x, data, q, mark, stamp); });
+    for_each_slab(F, u, [&](uint64_t x, bool data) {
+      relax_word<kUnit>(F, D, u, du, x, data, q, r, T, mark, stamp);
+    });
   }
   const uint32_t gib = threadIdx.x / kGroup;
   for (uint32_t j = blockIdx.x; j < nh; j += gridDim.x) {
     const uint32_t u = q.cur[1][j];
     const uint64_t du = ld_u64_coherent(D + u) >> 32;
     for_each_slab_strided(F, u, gib, kGroupsPerBlock, [&](uint64_t x, bool data) {
-      relax_word<kUnit>(F, D, u, du, x, data, q, mark, stamp);
+      relax_word<kUnit>(F, D, u, du, x, data, q, r, T, mark, stamp);
     });
   }
   for (uint32_t it = g0; it < ngi * kGiantSplit; it += ng) {  // giant: kGiantSplit groups each
     const uint32_t u = q.cur[2][it / kGiantSplit];
     const uint64_t du = ld_u64_coherent(D + u) >> 32;
     for_each_slab_strided(F, u, it % kGiantSplit, kGiantSplit, [&](uint64_t x, bool data) {
-      relax_word<kUnit>(F, D, u, du, x, data, q, mark, stamp);
+      relax_word<kUnit>(F, D, u, du, x, data, q, r, T, mark, stamp);
     });
+  }
+}
+
+// Band step, part 1: reset the pile minimum and the size of the pile about to be filled.
+__global__ void k_band_reset(uint32_t* fmin, uint32_t* next_cnt) {
+  if (threadIdx.x == 0) {
+    *fmin = 0xFFFFFFFFu;
+    *next_cnt = 0;
+  }
+}
+
+// Band step, part 2: the smallest distance on the far pile at or above the old threshold
+// (an entry below it was expanded, at its current distance, in an earlier band).
+__global__ void k_band_min(const uint64_t* D, const uint32_t* far, const uint32_t* far_cnt, const uint32_t* T,
+                           uint32_t* fmin) {
+  const uint32_t n = *far_cnt, told = *T;
+  uint32_t m = 0xFFFFFFFFu;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const uint32_t d = (uint32_t)(ld_u64_coherent(D + far[i]) >> 32);
+    if (d >= told && d < m) m = d;
+  }
+  for (int o = 32; o > 0; o >>= 1) m = min(m, (uint32_t)__shfl_xor((int)m, o));
+  if (lane64() == 0 && m != 0xFFFFFFFFu) atomicMin(fmin, m);
+}
+
+// Band step, part 3: the new threshold is fmin + delta; pile entries in [old T, new T) form
+// the frontier of the next band, later ones move to the other pile under the new band id.
+__global__ void k_band_split(const uint32_t* nbk, const uint64_t* D, const uint32_t* far, const uint32_t* far_cnt,
+                             const uint32_t* T, const uint32_t* fmin, uint32_t delta, uint32_t* T_next,
+                             PushQ Q, uint32_t* far_next, uint32_t* next_cnt, uint32_t* far_mark,
+                             uint32_t band_next) {
+  const uint32_t n = *far_cnt, told = *T, fm = *fmin;
+  const uint32_t tnew = fm == 0xFFFFFFFFu ? told : (fm >= 0xFFFFFFFFu - delta ? 0xFFFFFFFFu : fm + delta);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *T_next = tnew;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t base = blockIdx.x * blockDim.x + threadIdx.x - lane; base < n; base += stride) {
+    const uint32_t i = base + lane;
+    bool near = false, keep = false;
+    uint32_t v = 0, nb = 0;
+    if (i < n) {
+      v = far[i];
+      const uint32_t d = (uint32_t)(ld_u64_coherent(D + v) >> 32);
+      near = d >= told && d < tnew;
+      keep = d >= tnew;
+    }
+    if (keep) far_mark[v] = band_next;
+    wave_push(far_next, next_cnt, keep, v);
+    if (near) nb = nbk[v];
+    wave_push(Q.q[0], Q.c[0], near && nb <= kHeavyBuckets, v);
+    wave_push(Q.q[1], Q.c[1], near && nb > kHeavyBuckets && nb <= kGiantBuckets, v);
+    wave_push(Q.q[2], Q.c[2], near && nb > kGiantBuckets, v);
   }
 }
 
@@ -126,14 +275,22 @@ __global__ void k_trav_init(uint64_t* D, uint32_t nv, uint32_t src) {
     D[v] = v == src ? (uint64_t)src : kTreeNone;
 }
 
-// Reset the rotating counters so that slot 0 is the current frontier.
+// Reset the rotating counters so that slot 0 is the current frontier, empty both far
+// piles and set the first threshold to 0 (every prologue push of a weighted traversal
+// waits on the pile until the first band step).
 __global__ void k_queue_reset(uint32_t* cnt, uint32_t* inval_cnt) {
-  if (threadIdx.x < 9) cnt[threadIdx.x] = 0;
+  if (threadIdx.x < 13) cnt[threadIdx.x] = 0;
   if (threadIdx.x == 0 && inval_cnt) *inval_cnt = 0;
 }
 
-__global__ void k_seed_source(DView F, uint32_t src, PushQ Q, uint32_t* mark, uint32_t stamp) {
+__global__ void k_seed_source(DView F, uint32_t src, PushQ Q, Route r, uint32_t* mark, uint32_t stamp) {
   if (threadIdx.x != 0) return;
+  if (r.T) {  // weighted: the source waits on the far pile for the first band step
+    r.far_mark[src] = r.band;
+    r.far[0] = src;
+    *r.far_cnt = 1;
+    return;
+  }
   mark[src] = stamp;
   const uint32_t nb = F.nbk[src];
   const int k = nb <= kHeavyBuckets ? 0 : (nb <= kGiantBuckets ? 1 : 2);
@@ -143,8 +300,9 @@ __global__ void k_seed_source(DView F, uint32_t src, PushQ Q, uint32_t* mark, ui
 
 // Insert prologue: relax each effective inserted arc.
 template <bool kUnit>
-__global__ void k_relax_batch(DView F, uint64_t* D, Log lg, uint64_t n, PushQ Q, uint32_t* mark,
+__global__ void k_relax_batch(DView F, uint64_t* D, Log lg, uint64_t n, PushQ Q, Route r, uint32_t* mark,
                               uint32_t stamp) {
+  const uint32_t T = band_limit(r);
   // whole waves step together so that the wave-wide push sees every lane
   const uint64_t lane = threadIdx.x & 63;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -153,16 +311,17 @@ __global__ void k_relax_batch(DView F, uint64_t* D, Log lg, uint64_t n, PushQ Q,
     const uint64_t i = base + lane;
     bool improve = false;
     uint32_t v = 0;
+    uint64_t cand = kTreeNone;
     if (i < n && lg.st[i] == 1) {
       const uint32_t u = lg.s[i];
       v = lg.d[i];
       const uint64_t du = ld_u64_coherent(D + u);
       if (du != kTreeNone) {
-        const uint64_t cand = tree_node((du >> 32) + (kUnit ? 1u : lg.w[i]), u);
+        cand = tree_node((du >> 32) + (kUnit ? 1u : lg.w[i]), u);
         if (cand < D[v]) improve = amin64(D + v, cand) > cand;
       }
     }
-    push_vertex(F.nbk, Q, mark, stamp, improve, v);
+    push_routed(F.nbk, Q, r, T, mark, stamp, improve, v, (uint32_t)(cand >> 32));
   }
 }
 
@@ -208,10 +367,51 @@ __global__ void __launch_bounds__(kBlock) k_propagate(DView F, uint64_t* D, Queu
   const uint32_t nl = q.cnt[q.icur], nh = q.cnt[3 + q.icur], ngi = q.cnt[6 + q.icur];
   if (blockIdx.x == 0 && threadIdx.x < 3) q.cnt[3 * threadIdx.x + q.iclear] = 0;
   if (nl == 0 && nh == 0 && ngi == 0) return;
+  // single-bucket vertices: one lane each; the child tests of a slab are issued together
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nl; i += gridDim.x * blockDim.x) {
+    const uint32_t x = q.cur[0][i];
+    if (F.nbk[x] != 1) continue;
+    Slab sl;
+    uint32_t t = x;
+    while (true) {
+      load_slab(F, t, sl);
+      uint64_t dy[kKeysPerSlab];
+#pragma unroll
+      for (int j = 0; j < kKeysPerSlab; ++j) {
+        const uint32_t y = (uint32_t)sl.w[j];
+        dy[j] = valid_key(y) ? ld_u64_coherent(D + y) : kTreeNone;
+      }
+#pragma unroll
+      for (int j = 0; j < kKeysPerSlab; ++j) {
+        const uint32_t y = (uint32_t)sl.w[j];
+        const bool child = dy[j] != kTreeNone && (uint32_t)dy[j] == x;
+        dy[j] = child ? cas64(D + y, dy[j], kTreeNone) ^ dy[j] : 1ull;  // 0: this lane cut y
+      }
+      uint32_t cut = 0;
+#pragma unroll
+      for (int j = 0; j < kKeysPerSlab; ++j)
+        if (dy[j] == 0) cut |= 1u << j;
+      // a cut vertex is new to the invalidated set, so it needs no frontier mark
+      uint32_t heavy = 0, giant = 0;
+#pragma unroll
+      for (int j = 0; j < kKeysPerSlab; ++j) {
+        const uint32_t nb = (cut >> j & 1) ? F.nbk[(uint32_t)sl.w[j]] : 1u;
+        if (nb > kGiantBuckets) giant |= 1u << j;
+        else if (nb > kHeavyBuckets) heavy |= 1u << j;
+      }
+      push_words(inval, inval_cnt, cut, sl);
+      push_words(q.next.q[0], q.next.c[0], cut & ~(heavy | giant), sl);
+      push_words(q.next.q[1], q.next.c[1], heavy, sl);
+      push_words(q.next.q[2], q.next.c[2], giant, sl);
+      t = (uint32_t)sl.w[15];
+      if (t == kInvalid) break;
+    }
+  }
   const uint32_t g0 = (blockIdx.x * kBlock + threadIdx.x) / kGroup;
   const uint32_t ng = gridDim.x * kGroupsPerBlock;
   for (uint32_t i = g0; i < nl; i += ng) {
     const uint32_t x = q.cur[0][i];
+    if (F.nbk[x] == 1) continue;
     for_each_slab(F, x, [&](uint64_t w, bool data) {
       inval_word(F, D, x, w, data, q, inval, inval_cnt, mark, stamp);
     });
@@ -233,30 +433,73 @@ __global__ void __launch_bounds__(kBlock) k_propagate(DView F, uint64_t* D, Queu
 
 // Delete prologue, step 3: each invalidated vertex takes the best candidate offered by
 // its still-valid in-neighbours (reverse view) and, if reached, joins the frontier.
+// Single-bucket vertices are pulled by one lane, up to kHeavyBuckets buckets by a 16-lane
+// group, larger ones by a whole block (each group offers its own best; the atomic
+// minimum keeps the smallest).
+template <bool kUnit>
+__device__ inline uint64_t pull_word(const uint64_t* D, uint64_t x, bool data) {
+  const uint32_t u = (uint32_t)x;
+  if (!data || !valid_key(u)) return kTreeNone;
+  const uint64_t du = ld_u64_coherent(D + u);
+  if (du == kTreeNone) return kTreeNone;
+  return tree_node((du >> 32) + (kUnit ? 1ull : (x >> 32)), u);
+}
+
 template <bool kUnit>
 __global__ void __launch_bounds__(kBlock) k_dec_pull(DView F, DView R, uint64_t* D,
                                                      const uint32_t* inval, const uint32_t* inval_cnt,
-                                                     PushQ Q, uint32_t* mark, uint32_t stamp) {
+                                                     PushQ Q, Route r, uint32_t* mark, uint32_t stamp) {
   const uint32_t n = *inval_cnt;
+  const uint32_t T = band_limit(r);
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const uint32_t y = inval[i];
+    if (R.nbk[y] != 1) continue;
+    uint64_t best = kTreeNone;
+    Slab sl;
+    uint32_t t = y;
+    while (true) {
+      load_slab(R, t, sl);
+      uint64_t c[kKeysPerSlab];
+#pragma unroll
+      for (int j = 0; j < kKeysPerSlab; ++j) c[j] = pull_word<kUnit>(D, sl.w[j], true);
+#pragma unroll
+      for (int j = 0; j < kKeysPerSlab; ++j) best = c[j] < best ? c[j] : best;
+      t = (uint32_t)sl.w[15];
+      if (t == kInvalid) break;
+    }
+    bool improve = false;
+    if (best != kTreeNone) improve = amin64(D + y, best) > best;
+    push_routed(F.nbk, Q, r, T, mark, stamp, improve, y, (uint32_t)(best >> 32));
+  }
   const uint32_t g0 = (blockIdx.x * kBlock + threadIdx.x) / kGroup;
   const uint32_t ng = gridDim.x * kGroupsPerBlock;
   for (uint32_t i = g0; i < n; i += ng) {
     const uint32_t y = inval[i];
+    const uint32_t nb = R.nbk[y];
+    if (nb == 1 || nb > kHeavyBuckets) continue;
     uint64_t best = kTreeNone;
     for_each_slab(R, y, [&](uint64_t x, bool data) {
-      const uint32_t u = (uint32_t)x;
-      if (data && valid_key(u)) {
-        const uint64_t du = ld_u64_coherent(D + u);
-        if (du != kTreeNone) {
-          const uint64_t cand = tree_node((du >> 32) + (kUnit ? 1ull : (x >> 32)), u);
-          best = cand < best ? cand : best;
-        }
-      }
+      const uint64_t c = pull_word<kUnit>(D, x, data);
+      best = c < best ? c : best;
     });
     best = gmin_u64(best);
     bool improve = false;
     if (glane() == 0 && best != kTreeNone) improve = amin64(D + y, best) > best;
-    push_vertex(F.nbk, Q, mark, stamp, improve, y);
+    push_routed(F.nbk, Q, r, T, mark, stamp, improve, y, (uint32_t)(best >> 32));
+  }
+  const uint32_t gib = threadIdx.x / kGroup;
+  for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+    const uint32_t y = inval[i];
+    if (R.nbk[y] <= kHeavyBuckets) continue;
+    uint64_t best = kTreeNone;
+    for_each_slab_strided(R, y, gib, kGroupsPerBlock, [&](uint64_t x, bool data) {
+      const uint64_t c = pull_word<kUnit>(D, x, data);
+      best = c < best ? c : best;
+    });
+    best = gmin_u64(best);
+    bool improve = false;
+    if (glane() == 0 && best != kTreeNone) improve = amin64(D + y, best) > best;
+    push_routed(F.nbk, Q, r, T, mark, stamp, improve, y, (uint32_t)(best >> 32));
   }
 }
 
@@ -283,10 +526,14 @@ struct TravCtx {
   uint32_t* fq[6];  // light, heavy and giant queues, two of each
   uint32_t* mark;
   uint32_t* inval;
-  uint32_t* cnt;        // rotating frontier sizes [9]
+  uint32_t* far[2];     // far piles of the weighted epilogue
+  uint32_t* far_mark;
+  uint32_t* cnt;        // [0..8] rotating frontier sizes, [9..10] pile sizes,
+                        // [11..12] band thresholds, [13] smallest pile distance
   uint32_t* inval_cnt;  // invalidated-list size
-  uint32_t* stamp;      // host-side stamp counter
+  uint32_t* stamp;      // host-side stamp counter (also numbers the bands)
   uint64_t* h_pin;      // pinned host words for size read-backs
+  uint32_t delta;       // band width
 };
 
 TravCtx graph_ctx(mk_graph* g, uint64_t* D) {
@@ -295,11 +542,35 @@ TravCtx graph_ctx(mk_graph* g, uint64_t* D) {
   for (int i = 0; i < 6; ++i) c.fq[i] = g->fq[i];
   c.mark = g->mark;
   c.inval = g->inval;
+  c.far[0] = g->far[0];
+  c.far[1] = g->far[1];
+  c.far_mark = g->far_mark;
   c.cnt = g->ctr->frontier;
   c.inval_cnt = &g->ctr->inval;
   c.stamp = &g->stamp;
   c.h_pin = g->h_pin;
+  c.delta = g->sssp_delta;
   return c;
+}
+
+// Host-side band state of one weighted traversal: which pile and threshold word are current.
+struct Bands {
+  int fb = 0, tb = 0;
+  uint32_t band = 0;
+};
+
+Route route_of(const TravCtx& c, const Bands& b) {
+  return Route{c.cnt + 11 + b.tb, c.far[b.fb], c.cnt + 9 + b.fb, c.far_mark, b.band};
+}
+
+// Band 0 of a weighted traversal (kUnit == false): threshold 0, so every prologue push
+// lands on pile 0.  Unweighted traversals route nothing.
+template <bool kUnit>
+Route first_route(const TravCtx& c, Bands& b) {
+  if (kUnit) return Route{nullptr, nullptr, nullptr, nullptr, 0};
+  b = Bands{};
+  b.band = ++*c.stamp;
+  return route_of(c, b);
 }
 
 // The queues of iteration 0 (and of every prologue): fq[0], fq[2], fq[4] with slot 0.
@@ -327,32 +598,74 @@ Queues queues(const TravCtx& c, uint64_t it) {
   return q;
 }
 
-// Run frontier iterations (expand or propagate) until the frontier is empty.  Iteration
-// `it` reads slot it%3; the frontier of iteration 0 sits in fq[0] / fq[2] and slot 0.
+// Run frontier iterations (expand or propagate) from iteration *it until the frontier is
+// empty.  Iteration `it` reads slot it%3; the frontier of iteration 0 sits in fq[0] /
+// fq[2] / fq[4] and slot 0.  On return *it is the first iteration with an empty frontier
+// and c.h_pin holds the counters read back last.
 template <class Launch>
-mk_status run_frontier(mk_graph* g, const TravCtx& c, hipStream_t stream, Launch&& launch) {
-  uint64_t it = 0;
+mk_status run_frontier(mk_graph* g, const TravCtx& c, hipStream_t stream, Launch&& launch,
+                       uint64_t* it_io = nullptr) {
+  uint64_t it = it_io ? *it_io : 0;
   while (true) {
     for (int k = 0; k < kSyncEvery; ++k, ++it) {
       launch(queues(c, it), ++*c.stamp);
       MK_LAUNCH(g, "frontier kernel");
     }
     const int slot = (int)(it % 3);
-    MK_HIP(g, hipMemcpyAsync(c.h_pin, c.cnt, 9 * sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
+    MK_HIP(g, hipMemcpyAsync(c.h_pin, c.cnt, 14 * sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
     MK_HIP(g, hipStreamSynchronize(stream));
     const uint32_t* h = reinterpret_cast<const uint32_t*>(c.h_pin);
     if (h[slot] == 0 && h[3 + slot] == 0 && h[6 + slot] == 0) break;
   }
+  if (it_io) *it_io = it;
   return MK_OK;
 }
 
+constexpr uint32_t kBandBlocks = 1024;
+
+// Frontier epilogue.  Unweighted: expand until the frontier is empty.  Weighted: band by
+// band; each band step moves the next band of the far pile into the (empty) frontier of
+// the current iteration, then the band is expanded until its frontier is empty.
 template <bool kUnit>
-mk_status run_expand(mk_graph* g, const TravCtx& c, hipStream_t stream) {
+mk_status run_expand(mk_graph* g, const TravCtx& c, hipStream_t stream, Bands& b) {
   const DView F = g->view[VF].d;
-  return run_frontier(g, c, stream, [&](Queues q, uint32_t stamp) {
-    hipLaunchKernelGGL(k_expand<kUnit>, dim3(kExpandBlocks), dim3(kBlock), 0, stream, F, c.D, q, c.mark,
-                       stamp);
-  });
+  if (kUnit) {
+    const Route r{nullptr, nullptr, nullptr, nullptr, 0};
+    return run_frontier(g, c, stream, [&](Queues q, uint32_t stamp) {
+      hipLaunchKernelGGL(k_expand<kUnit>, dim3(kExpandBlocks), dim3(kBlock), 0, stream, F, c.D, q, r,
+                         c.mark, stamp);
+    });
+  }
+  uint32_t* fmin = c.cnt + 13;
+  uint64_t it = 0;
+  while (true) {
+    const int nf = b.fb ^ 1, nt = b.tb ^ 1;
+    const uint32_t band_next = ++*c.stamp;
+    hipLaunchKernelGGL(k_band_reset, dim3(1), dim3(64), 0, stream, fmin, c.cnt + 9 + nf);
+    hipLaunchKernelGGL(k_band_min, dim3(kBandBlocks), dim3(kBlock), 0, stream, c.D, c.far[b.fb],
+                       c.cnt + 9 + b.fb, c.cnt + 11 + b.tb, fmin);
+    PushQ cur;
+    for (int k = 0; k < 3; ++k) {
+      cur.q[k] = c.fq[2 * k + (int)(it & 1)];
+      cur.c[k] = c.cnt + 3 * k + (int)(it % 3);
+    }
+    hipLaunchKernelGGL(k_band_split, dim3(kBandBlocks), dim3(kBlock), 0, stream, F.nbk, c.D, c.far[b.fb],
+                       c.cnt + 9 + b.fb, c.cnt + 11 + b.tb, fmin, c.delta, c.cnt + 11 + nt, cur, c.far[nf],
+                       c.cnt + 9 + nf, c.far_mark, band_next);
+    MK_LAUNCH(g, "band step");
+    b.fb = nf;
+    b.tb = nt;
+    b.band = band_next;
+    const Route r = route_of(c, b);
+    mk_status s = run_frontier(g, c, stream, [&](Queues q, uint32_t stamp) {
+      hipLaunchKernelGGL(k_expand<kUnit>, dim3(kExpandBlocks), dim3(kBlock), 0, stream, F, c.D, q, r,
+                         c.mark, stamp);
+    }, &it);
+    if (s != MK_OK) return s;
+    const uint32_t* h = reinterpret_cast<const uint32_t*>(c.h_pin);
+    if (h[9 + b.fb] == 0) break;  // the frontier and the pile are both empty
+  }
+  return MK_OK;
 }
 
 template <bool kUnit>
@@ -361,10 +674,12 @@ mk_status static_from(mk_graph* g, const TravCtx& c, uint32_t source, hipStream_
   const uint32_t stamp0 = ++*c.stamp;
   hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, stream, c.cnt, c.inval_cnt);
   hipLaunchKernelGGL(k_trav_init, dim3(blocks_for(g->n)), dim3(kBlock), 0, stream, c.D, g->n, source);
-  hipLaunchKernelGGL(k_seed_source, dim3(1), dim3(64), 0, stream, F, source, first_push(c), c.mark,
+  Bands b;
+  const Route r0 = first_route<kUnit>(c, b);
+  hipLaunchKernelGGL(k_seed_source, dim3(1), dim3(64), 0, stream, F, source, first_push(c), r0, c.mark,
                      stamp0);
   MK_LAUNCH(g, "traversal init");
-  return run_expand<kUnit>(g, c, stream);
+  return run_expand<kUnit>(g, c, stream, b);
 }
 
 template <bool kUnit>
@@ -384,12 +699,14 @@ mk_status traverse(mk_graph* g, AlgoState& st, uint64_t* D, uint32_t source, uin
   } else if (!p.list.empty()) {
     const uint32_t stamp0 = ++g->stamp;
     hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, stream, c.cnt, c.inval_cnt);
+    Bands bands;
     if (p.kinds == 1) {
+      const Route r0 = first_route<kUnit>(c, bands);
       for (const BatchRec* b : p.list) {
         Log lg = g->log;
         lg.s += b->off; lg.d += b->off; lg.w += b->off; lg.st += b->off; lg.uf += b->off;
         hipLaunchKernelGGL(k_relax_batch<kUnit>, dim3(blocks_for(b->n)), dim3(kBlock), 0, stream, F, D,
-                           lg, b->n, first_push(c), c.mark, stamp0);
+                           lg, b->n, first_push(c), r0, c.mark, stamp0);
       }
     } else {  // deletions only
       for (const BatchRec* b : p.list) {
@@ -406,11 +723,12 @@ mk_status traverse(mk_graph* g, AlgoState& st, uint64_t* D, uint32_t source, uin
       if (s != MK_OK) return s;
       hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, stream, c.cnt, nullptr);
       const uint32_t stamp1 = ++g->stamp;
+      const Route r0 = first_route<kUnit>(c, bands);
       hipLaunchKernelGGL(k_dec_pull<kUnit>, dim3(kExpandBlocks), dim3(kBlock), 0, stream, F,
-                         g->view[VR].d, D, c.inval, c.inval_cnt, first_push(c), c.mark, stamp1);
+                         g->view[VR].d, D, c.inval, c.inval_cnt, first_push(c), r0, c.mark, stamp1);
     }
     MK_LAUNCH(g, "traversal prologue");
-    mk_status s = run_expand<kUnit>(g, c, stream);
+    mk_status s = run_expand<kUnit>(g, c, stream, bands);
     if (s != MK_OK) return s;
   }
   hipLaunchKernelGGL(k_split, dim3(blocks_for(N)), dim3(kBlock), 0, stream, D, N, d_out, d_parent);
@@ -422,8 +740,9 @@ mk_status traverse(mk_graph* g, AlgoState& st, uint64_t* D, uint32_t source, uin
 }
 
 size_t ws_bytes_for(uint32_t n) {
-  // D (8 B), six queues, stamps and the invalidated list (4 B each), counters
-  return (size_t)n * (8 + 8 * 4) + 512 + 10 * 256;
+  // D (8 B); six queues, stamps, the invalidated list, two far piles and the band marks
+  // (4 B each); counters; 256-byte alignment of each of the 13 regions
+  return (size_t)n * (8 + 11 * 4) + 128 + 14 * 256;
 }
 
 }  // namespace
@@ -464,12 +783,17 @@ mk_status mk_traverse_from(mk_graph* g, uint32_t source, int weighted, void* d_w
   for (int i = 0; i < 6; ++i) c.fq[i] = reinterpret_cast<uint32_t*>(take((size_t)N * 4));
   c.mark = reinterpret_cast<uint32_t*>(take((size_t)N * 4));
   c.inval = reinterpret_cast<uint32_t*>(take((size_t)N * 4));
-  c.cnt = reinterpret_cast<uint32_t*>(take(64));
-  c.inval_cnt = c.cnt + 12;
+  c.far[0] = reinterpret_cast<uint32_t*>(take((size_t)N * 4));
+  c.far[1] = reinterpret_cast<uint32_t*>(take((size_t)N * 4));
+  c.far_mark = reinterpret_cast<uint32_t*>(take((size_t)N * 4));
+  c.cnt = reinterpret_cast<uint32_t*>(take(128));
+  c.inval_cnt = c.cnt + 16;
   uint32_t stamp = 0;
   c.stamp = &stamp;
   c.h_pin = g->slot_pin[slot];
+  c.delta = g->sssp_delta;
   hipLaunchKernelGGL(k_fill_mark, dim3(blocks_for(N)), dim3(kBlock), 0, stream, c.mark, N);
+  hipLaunchKernelGGL(k_fill_mark, dim3(blocks_for(N)), dim3(kBlock), 0, stream, c.far_mark, N);
   mk_status s = weighted ? static_from<false>(g, c, source, stream) : static_from<true>(g, c, source, stream);
   if (s != MK_OK) return s;
   hipLaunchKernelGGL(k_split, dim3(blocks_for(N)), dim3(kBlock), 0, stream, c.D, N, d_dist, d_parent);

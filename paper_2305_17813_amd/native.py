@@ -33,7 +33,8 @@ class MkError(RuntimeError):
 class MkConfig(ctypes.Structure):
     _fields_ = [("n_vertices", ctypes.c_uint32), ("views", ctypes.c_uint32),
                 ("load_factor", ctypes.c_float), ("hash_seed", ctypes.c_uint32),
-                ("pool_slabs", ctypes.c_uint64), ("log_capacity", ctypes.c_uint64)]
+                ("pool_slabs", ctypes.c_uint64), ("log_capacity", ctypes.c_uint64),
+                ("sssp_delta", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class MkStats(ctypes.Structure):
@@ -145,7 +146,8 @@ class Graph:
 
     def __init__(self, n: int, src, dst, w=None, views=VIEW_FWD | VIEW_REV | VIEW_UND,
                  load_factor: float = 0.7, hash_seed: int = 1, pool_slabs: int = 0,
-                 log_capacity: int = 0, device="cuda", stream: Optional[torch.cuda.Stream] = None):
+                 log_capacity: int = 0, device="cuda", stream: Optional[torch.cuda.Stream] = None,
+                 sssp_delta: int = 0):
         self.lib = load()
         self.device = torch.device(device)
         if self.device.index is None:
@@ -158,7 +160,7 @@ class Graph:
         w = None if w is None else as_u32(w, self.device)
         m = int(src.numel())
         self.cfg = MkConfig(self.n, self.views, float(load_factor), int(hash_seed), int(pool_slabs),
-                            int(log_capacity))
+                            int(log_capacity), int(sssp_delta), 0)
         nbytes = self.lib.mk_arena_bytes(ctypes.byref(self.cfg), m)
         if nbytes == 0:
             raise MkError(1, "mk_arena_bytes")

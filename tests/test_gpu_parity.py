@@ -247,3 +247,27 @@ def test_export_and_recreate_round_trip():
     q.o = p.o  # the oracle already holds the same arc set
     q.check_structure()
     q.check_all()
+
+
+@pytest.mark.parametrize("delta", [1, 37, 1 << 30])
+def test_band_width_leaves_sssp_unchanged(delta):
+    """The weighted epilogue's band width only changes the expansion order: distances and
+    parents equal the oracle's for a width of 1 (one distance per band), a middling one
+    and one wider than every distance (a single band), through inserts and deletes."""
+    say(f"case: band width {delta}")
+    for g, src in ((I.grid_side(64), 0), (I.rmat_s(11), None)):
+        src = I.max_out_degree_vertex(g) if src is None else src
+        p = make_pair(g, source=src, sssp_delta=delta)
+        p.check_all(algos=("sssp", "bfs"))
+        wl = I.Workload(g, 9)
+        for b in (50, 600):
+            s, d, w = wl.insert_batch(b)
+            p.insert(s, d, w)
+            p.check_all(algos=("sssp",))
+            s, d = wl.delete_batch(b)
+            p.delete(s, d)
+            p.check_all(algos=("sssp",))
+        dist, par = p.g.traverse_from(src, True, p.g.traversal_workspace())
+        od, op = p.o.sssp(src)
+        assert np.array_equal(u32(dist), np.asarray(od, np.uint32))
+        assert np.array_equal(u32(par), np.asarray(op, np.uint32))
