@@ -83,7 +83,12 @@ __device__ int insert_key(const DView& V, uint32_t u, uint32_t key, uint32_t w) 
     // word to write; writing it with an atomic exchange (performed where the CASes are)
     // and waiting for its result orders it before the link without an L2 write-back.
     if (spare == kInvalid) {
-      const uint32_t got = atomicAdd(V.pool_ctr, 1u);
+      // one bump of the pool counter for every lane of the wave that needs a slab now
+      const uint64_t m = __ballot(true);
+      const int leader = __builtin_ctzll(m);
+      uint32_t base = 0;
+      if (lane64() == leader) base = atomicAdd(V.pool_ctr, (uint32_t)__popcll(m));
+      const uint32_t got = __shfl(base, leader) + lanes_below(m);
       if (got >= V.pool_cap) return 3;
       spare = V.pool_base + got;
     }
@@ -585,13 +590,16 @@ uint64_t hash_const(uint32_t seed, uint64_t salt) {
   return z ^ (z >> 31);
 }
 
-// Default band width of the weighted frontier epilogue: about kBandArcs arcs' worth of
-// mean weight spread over the mean out-degree, so that a band holds enough vertices to
-// fill the device while few of them are improved again after their expansion.
+// Default band width of the weighted frontier epilogue: kBandArcs mean weights spread
+// over the mean out-degree (so that a band of a sparse, long-range graph holds enough
+// vertices to fill the device while few are improved again after their expansion), and
+// at least kBandMin mean weights (so that a dense, low-diameter graph needs few bands).
 constexpr double kBandArcs = 32.0;
+constexpr double kBandMin = 8.0;
 uint32_t default_band(uint64_t m, uint32_t n, double mean_w) {
   const double deg = std::max(1.0, (double)m / std::max<uint32_t>(n, 1));
-  const double b = std::ceil(kBandArcs * std::max(1.0, mean_w) / deg);
+  const double w = std::max(1.0, mean_w);
+  const double b = std::ceil(std::max(kBandArcs * w / deg, kBandMin * w));
   return (uint32_t)std::min(b, (double)(1u << 30));
 }
 

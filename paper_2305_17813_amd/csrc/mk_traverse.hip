@@ -89,22 +89,6 @@ struct Queues {
   int icur, iclear;
 };
 
-// Relax every out-arc of u held in one slab word per lane.
-template <bool kUnit>
-__device__ inline void relax_word(const DView& F, uint64_t* D, uint32_t u, uint64_t du, uint64_t x,
-                                  bool data, const Queues& q, const Route& r, uint32_t T,
-                                  uint32_t* mark, uint32_t stamp) {
-  const uint32_t v = (uint32_t)x;
-  bool improve = false;
-  uint64_t cand = kTreeNone;
-  if (data && valid_key(v)) {
-    const uint64_t w = kUnit ? 1ull : (x >> 32);
-    cand = tree_node(du + w, u);
-    if (cand < D[v]) improve = amin64(D + v, cand) > cand;
-  }
-  push_routed(F.nbk, q.next, r, T, mark, stamp, improve, v, (uint32_t)(cand >> 32));
-}
-
 // Append the keys of the slab words selected by `mask` (bit j: word j) of every active lane
 // to q, with one counter atomic per wave.
 __device__ inline void push_words(uint32_t* q, uint32_t* ctr, uint32_t mask, const Slab& sl) {
@@ -120,13 +104,13 @@ __device__ inline void push_words(uint32_t* q, uint32_t* ctr, uint32_t mask, con
 // batch, and the pushes of the wave are appended with one counter atomic per queue.
 template <bool kUnit>
 __device__ inline void relax_slab_lane(const DView& F, uint64_t* D, uint32_t u, uint64_t du, const Slab& sl,
-                                       const Queues& q, const Route& r, uint32_t T, uint32_t* mark,
+                                       int nd, const Queues& q, const Route& r, uint32_t T, uint32_t* mark,
                                        uint32_t stamp) {
   uint64_t cand[kKeysPerSlab], cur[kKeysPerSlab];
 #pragma unroll
   for (int j = 0; j < kKeysPerSlab; ++j) {
     const uint32_t v = (uint32_t)sl.w[j];
-    const bool ok = valid_key(v);
+    const bool ok = j < nd && valid_key(v);
     cand[j] = ok ? tree_node(du + (kUnit ? 1ull : (sl.w[j] >> 32)), u) : kTreeNone;
     cur[j] = ok ? D[v] : 0ull;
   }
@@ -169,6 +153,36 @@ __device__ inline void relax_slab_lane(const DView& F, uint64_t* D, uint32_t u, 
   push_words(r.far, r.far_cnt, tf, sl);
 }
 
+// Relax every arc in bucket b of u (nb buckets, extra head slabs from xb) with one lane.
+template <bool kUnit>
+__device__ inline void relax_bucket_lane(const DView& F, uint64_t* D, uint32_t u, uint64_t du, uint32_t b,
+                                         uint32_t nb, uint32_t xb, const Queues& q, const Route& r,
+                                         uint32_t T, uint32_t* mark, uint32_t stamp) {
+  uint32_t t = b == 0 ? u : xb + b - 1;
+  int nd = (b == 0 && nb > 1) ? kKeysPerSlab - 1 : kKeysPerSlab;
+  Slab sl;
+  while (true) {
+    load_slab(F, t, sl);
+    relax_slab_lane<kUnit>(F, D, u, du, sl, nd, q, r, T, mark, stamp);
+    t = (uint32_t)sl.w[15];
+    if (t == kInvalid) break;
+    nd = kKeysPerSlab;
+  }
+}
+
+// First extra head slab of a multi-bucket vertex (word 14 of its primary slab).
+__device__ inline uint32_t extra_base(const DView& F, uint32_t u) {
+  return (uint32_t)ld_word(slab_ptr(F, u) + 14);
+}
+
+constexpr uint32_t kGiantLanes = kGiantSplit * kGroup;  // lanes sharing one giant vertex
+
+// Frontier expansion.  Every path gives each lane whole slabs (one bucket chain at a
+// time), so the pushes of a wave cover up to 64 x 15 arcs per counter atomic:
+//   single-bucket vertices: one lane each;
+//   2 .. kHeavyBuckets buckets: one 16-lane group per vertex, a lane per bucket;
+//   heavy: one block per vertex, a lane per bucket;
+//   giant: kGiantLanes lanes per vertex, striding over its buckets.
 template <bool kUnit>
 __global__ void __launch_bounds__(kBlock) k_expand(DView F, uint64_t* D, Queues q, Route r, uint32_t* mark,
                                                    uint32_t stamp) {
@@ -181,40 +195,33 @@ __global__ void __launch_bounds__(kBlock) k_expand(DView F, uint64_t* D, Queues 
     const uint32_t u = q.cur[0][i];
     if (F.nbk[u] != 1) continue;
     const uint64_t du = ld_u64_coherent(D + u) >> 32;
-    Slab sl;
-    uint32_t t = u;
-    while (true) {
-      load_slab(F, t, sl);
-      relax_slab_lane<kUnit>(F, D, u, du, sl, q, r, T, mark, stamp);
-      t = (uint32_t)sl.w[15];
-      if (t == kInvalid) break;
-    }
+    relax_bucket_lane<kUnit>(F, D, u, du, 0, 1, 0, q, r, T, mark, stamp);
   }
-  // other light vertices: one 16-lane group each
   const uint32_t g0 = (blockIdx.x * kBlock + threadIdx.x) / kGroup;
   const uint32_t ng = gridDim.x * kGroupsPerBlock;
   for (uint32_t i = g0; i < nl; i += ng) {
     const uint32_t u = q.cur[0][i];
-    if (F.nbk[u] == 1) continue;
+    const uint32_t nb = F.nbk[u];
+    if (nb == 1 || (uint32_t)glane() >= nb) continue;
     const uint64_t du = ld_u64_coherent(D + u) >> 32;
-    for_each_slab(F, u, [&](uint64_t x, bool data) {
-      relax_word<kUnit>(F, D, u, du, x, data, q, r, T, mark, stamp);
-    });
+    relax_bucket_lane<kUnit>(F, D, u, du, glane(), nb, extra_base(F, u), q, r, T, mark, stamp);
   }
-  const uint32_t gib = threadIdx.x / kGroup;
   for (uint32_t j = blockIdx.x; j < nh; j += gridDim.x) {
     const uint32_t u = q.cur[1][j];
+    const uint32_t nb = F.nbk[u];
     const uint64_t du = ld_u64_coherent(D + u) >> 32;
-    for_each_slab_strided(F, u, gib, kGroupsPerBlock, [&](uint64_t x, bool data) {
-      relax_word<kUnit>(F, D, u, du, x, data, q, r, T, mark, stamp);
-    });
+    const uint32_t xb = extra_base(F, u);
+    for (uint32_t b = threadIdx.x; b < nb; b += kBlock)
+      relax_bucket_lane<kUnit>(F, D, u, du, b, nb, xb, q, r, T, mark, stamp);
   }
-  for (uint32_t it = g0; it < ngi * kGiantSplit; it += ng) {  // giant: kGiantSplit groups each
-    const uint32_t u = q.cur[2][it / kGiantSplit];
+  const uint32_t nthreads = gridDim.x * kBlock;
+  for (uint32_t it = blockIdx.x * kBlock + threadIdx.x; it < ngi * kGiantLanes; it += nthreads) {
+    const uint32_t u = q.cur[2][it / kGiantLanes];
+    const uint32_t nb = F.nbk[u];
     const uint64_t du = ld_u64_coherent(D + u) >> 32;
-    for_each_slab_strided(F, u, it % kGiantSplit, kGiantSplit, [&](uint64_t x, bool data) {
-      relax_word<kUnit>(F, D, u, du, x, data, q, r, T, mark, stamp);
-    });
+    const uint32_t xb = extra_base(F, u);
+    for (uint32_t b = it % kGiantLanes; b < nb; b += kGiantLanes)
+      relax_bucket_lane<kUnit>(F, D, u, du, b, nb, xb, q, r, T, mark, stamp);
   }
 }
 
