@@ -262,32 +262,6 @@ __device__ inline uint64_t probe(const DView& V, uint32_t u, uint32_t key) {
   }
 }
 
-// Single-lane membership test (each lane probes its own key; used where every lane of a
-// group has a different key, as in triangle counting).
-__device__ inline bool lane_has(const DView& V, uint32_t u, uint32_t key) {
-  const uint32_t* p = reinterpret_cast<const uint32_t*>(slab_ptr(V, u));
-  const uint32_t nb = p[31];
-  uint32_t s = u;
-  int nd = kKeysPerSlab;
-  if (nb > 1) {
-    const uint32_t b = bucket_of(key, nb, V.hash_a, V.hash_b);
-    if (b == 0) nd = kKeysPerSlab - 1;
-    else s = p[28] + b - 1;
-  }
-  while (true) {
-    const uint32_t* sp = reinterpret_cast<const uint32_t*>(slab_ptr(V, s));
-    for (int j = 0; j < nd; ++j) {
-      const uint32_t k = sp[2 * j];
-      if (k == key) return true;
-      if (k == kEmptyKey) return false;
-    }
-    s = sp[30];
-    if (s == kInvalid) return false;
-    nd = kKeysPerSlab;
-  }
-}
-
-
 // ----------------------------------------------------------------- one op per lane
 // Batched insert/delete/query ops are independent and latency-bound, so each lane runs
 // its own op and reads the whole slab itself (8 x 16-byte loads): a wave keeps 64 probes
@@ -362,6 +336,13 @@ __device__ inline uint64_t lane_probe(const DView& V, uint32_t u, uint32_t key) 
     load_slab(V, s, sl);
     nd = kKeysPerSlab;
   }
+}
+
+// Single-lane membership test (each lane probes its own key; used where every lane of a
+// group has a different key, as in triangle counting).  Whole slabs are read with 16-byte
+// loads, so a probe waits one round trip per slab.
+__device__ inline bool lane_has(const DView& V, uint32_t u, uint32_t key) {
+  return lane_probe(V, u, key) != kEmptyWord;
 }
 
 }  // namespace mk
