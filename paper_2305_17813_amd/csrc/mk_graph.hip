@@ -198,23 +198,32 @@ __global__ void __launch_bounds__(kBlock) k_delete_fwd(DView F, const uint32_t* 
 
 // The other views of a delete batch, three lanes per deleted arc: the reverse view, and
 // the two directions of the undirected view, where {u,v} goes only if the reverse arc is
-// absent once the whole batch has been applied to the forward view.
+// absent once the whole batch has been applied to the forward view.  The three lanes of
+// an arc sit in one wave (21 arcs per wave, lane 63 idle), so the forward-view probe for
+// the reverse arc is made once and handed to the second undirected lane by a shuffle.
+constexpr uint32_t kOpsPerWave = 21;
 __global__ void __launch_bounds__(kBlock) k_delete_aux(DView F, DView R, DView U, uint32_t views,
                                                        Log log, uint64_t n) {
-  const uint64_t gid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-  const uint64_t op = gid / 3;
-  const int task = (int)(gid % 3);
-  if (op >= n) return;
-  if (task == 0 && !(views & MK_VIEW_REV)) return;
-  if (task != 0 && !(views & MK_VIEW_UND)) return;
-  if (log.st[op] != 1) return;
-  const uint32_t s = log.s[op], d = log.d[op];
-  uint32_t w;
-  if (task == 0) {
-    if (delete_key(R, d, s, &w) == 1) atomicSub(R.deg + d, 1u);
-    return;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const int task = (int)(lane % 3);
+  const uint64_t op = wave * kOpsPerWave + lane / 3;
+  bool live = lane < 3 * kOpsPerWave && op < n;
+  if (live) live = log.st[op] == 1;
+  if (task == 0 && !(views & MK_VIEW_REV)) live = false;
+  if (task != 0 && !(views & MK_VIEW_UND)) live = false;
+  uint32_t s = 0, d = 0, w;
+  if (live) {
+    s = log.s[op];
+    d = log.d[op];
   }
-  if (lane_probe(F, d, s) != kEmptyWord) return;
+  if (live && task == 0 && delete_key(R, d, s, &w) == 1) atomicSub(R.deg + d, 1u);
+  bool absent = false;
+  if (live && task == 1) absent = lane_probe(F, d, s) == kEmptyWord;
+  // every lane is active here: lane 3k+2 takes the answer of lane 3k+1
+  const int from = (int)(lane - task) + 1;
+  absent = __shfl((int)absent, from < 64 ? from : (int)lane) != 0;
+  if (!live || task == 0 || !absent) return;
   const uint32_t a = task == 1 ? min(s, d) : max(s, d);
   const uint32_t b = task == 1 ? max(s, d) : min(s, d);
   const int r = delete_key(U, a, b, &w);
@@ -816,7 +825,8 @@ mk_status mk_delete_edges(mk_graph* g, const uint32_t* d_src, const uint32_t* d_
                      d_src, d_dst, n, g->n, d_status, lg);
   MK_LAUNCH(g, "k_delete_fwd");
   if (g->view[VR].on || g->view[VU].on) {
-    hipLaunchKernelGGL(k_delete_aux, dim3(grid_for_lanes(3 * n)), dim3(kBlock), 0, stream, dv(g, VF),
+    hipLaunchKernelGGL(k_delete_aux, dim3(grid_for_lanes((n + kOpsPerWave - 1) / kOpsPerWave * 64)),
+                       dim3(kBlock), 0, stream, dv(g, VF),
                        dv(g, VR), dv(g, VU), g->cfg.views, lg, n);
     MK_LAUNCH(g, "k_delete_aux");
   }
