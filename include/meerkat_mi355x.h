@@ -189,6 +189,16 @@ mk_status mk_count_triangles(mk_graph* g, uint64_t* d_count, mk_mode mode, hipSt
 mk_status mk_graph_export(mk_graph* g, uint32_t* d_src, uint32_t* d_dst, uint32_t* d_w,
                           uint64_t cap, uint64_t* h_count, hipStream_t stream);
 
+/* Slab reclamation (the paper never reuses a slab: a deleted arc leaves a TOMBSTONE that
+ * later inserts skip, so chains only grow under delete churn).  Every chain holding at least
+ * `min_tombstones` tombstones (0 is taken as 1) is rewritten with its live arcs packed from
+ * its head slab, EMPTY lanes after them, and the chain cut after the last slab it still
+ * needs; the slabs after the cut return to the view's free list, which inserts draw from
+ * before the bump pointer.  The arc set, degrees and all incremental algorithm state are
+ * unchanged.  Must not overlap any other call on the same graph (reads included).
+ *   h_freed : host; receives the number of slabs returned to the free lists. */
+mk_status mk_compact(mk_graph* g, uint32_t min_tombstones, uint64_t* h_freed, hipStream_t stream);
+
 /* Byte model of the batched operations (no change is made): the number of slabs that
  * `op` (0 = query/delete, which stop at the arc or the first EMPTY lane; 1 = insert, which
  * walks the hashed chain to its end) would read for each of the n arcs in `view` (0 fwd

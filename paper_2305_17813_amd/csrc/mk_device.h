@@ -44,7 +44,11 @@ constexpr uint32_t kHeavyBuckets = 16;  // vertices with more buckets are walked
 struct DView {
   uint64_t* slab;       // slab s occupies words [16 s, 16 s + 16); slab v is v's primary
   const uint32_t* nbk;  // bucket count per vertex (a copy of the primary slabs' meta)
-  uint32_t* pool_ctr;   // chained slabs handed out so far
+  uint32_t* pool_ctr;   // [0] chained slabs handed out by the bump pointer so far,
+                        // [1] slabs ever appended to the free list, [2] taken from it,
+                        // [3] spares returned by the running insert kernels
+  uint32_t* free_ids;   // free list: a ring of pool_cap reclaimed slab ids
+  uint32_t* spare_ids;  // slabs taken but never linked by the running insert kernels
   uint32_t pool_base;   // index of the first chained (pool) slab
   uint32_t pool_cap;    // number of pool slabs
   uint32_t* deg;        // live keys per vertex

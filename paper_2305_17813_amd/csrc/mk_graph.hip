@@ -48,12 +48,11 @@ namespace {
 // 3 pool empty.  Progress never depends on a load being fresh: every failed CAS returns
 // the word's true value and `floor` (words of this slab known to be filled) only grows, so
 // a slab is retried at most 15 times.
-__device__ int insert_key(const DView& V, uint32_t u, uint32_t key, uint32_t w) {
+__device__ int insert_key_core(const DView& V, uint32_t u, uint32_t key, uint32_t w, uint32_t& spare) {
   Slab sl;
   int nd;
   uint32_t s = lane_head(V, u, key, sl, nd);
   const uint64_t mine = ((uint64_t)w << 32) | key;
-  uint32_t spare = kInvalid;
   int floor = 0;
   while (true) {
     uint64_t* sp = slab_ptr(V, s);
@@ -83,24 +82,68 @@ __device__ int insert_key(const DView& V, uint32_t u, uint32_t key, uint32_t w) 
     // word to write; writing it with an atomic exchange (performed where the CASes are)
     // and waiting for its result orders it before the link without an L2 write-back.
     if (spare == kInvalid) {
-      // one bump of the pool counter for every lane of the wave that needs a slab now
-      const uint64_t m = __ballot(true);
-      const int leader = __builtin_ctzll(m);
+      // the bump pointer first (one counter atomic for the lanes of the wave that need a
+      // slab now), reclaimed slabs once it is exhausted; both hand out EMPTY slabs
+      uint64_t m = __ballot(true);
+      int leader = __builtin_ctzll(m);
       uint32_t base = 0;
       if (lane64() == leader) base = atomicAdd(V.pool_ctr, (uint32_t)__popcll(m));
       const uint32_t got = __shfl(base, leader) + lanes_below(m);
-      if (got >= V.pool_cap) return 3;
-      spare = V.pool_base + got;
+      if (got < V.pool_cap) {
+        spare = V.pool_base + got;
+      } else {
+        m = __ballot(true);
+        leader = __builtin_ctzll(m);
+        if (lane64() == leader) base = atomicAdd(V.pool_ctr + 2, (uint32_t)__popcll(m));
+        const uint32_t idx = __shfl(base, leader) + lanes_below(m);
+        if ((int32_t)(V.pool_ctr[1] - idx) <= 0) return 3;
+        spare = V.free_ids[idx % V.pool_cap];
+      }
     }
     const uint64_t prev = atomicExch((unsigned long long*)slab_ptr(V, spare), (unsigned long long)mine);
     if (prev != kEmptyWord && prev != mine) return 3;  // a pool slab is fresh or our own spare
     // the link word keeps its meta half (the bucket count of a primary slab)
     const uint64_t old = cas64(sp + 15, link, (link & 0xFFFFFFFF00000000ull) | spare);
-    if (old == link) return 1;
+    if (old == link) {
+      spare = kInvalid;  // linked: now part of the chain
+      return 1;
+    }
     s = (uint32_t)old;  // lost the race: continue in the winner's slab, keep the spare
     floor = 0;
     nd = kKeysPerSlab;
     load_slab(V, s, sl);
+  }
+}
+
+// insert_key_core, then a slab that was taken but never linked (its lane lost every link
+// race and placed the key elsewhere) is cleared and listed for return to the free list
+// once the kernel has finished.
+__device__ int insert_key(const DView& V, uint32_t u, uint32_t key, uint32_t w) {
+  uint32_t spare = kInvalid;
+  const int r = insert_key_core(V, u, key, w, spare);
+  if (spare != kInvalid) {
+    slab_ptr(V, spare)[0] = kEmptyWord;
+    V.spare_ids[atomicAdd(V.pool_ctr + 3, 1u)] = spare;
+  }
+  return r;
+}
+
+// After the insert kernels: their unused spares join the free list (one block per view;
+// the take counter, which inserts may have run past the end of the list, is clamped first).
+__global__ void k_spare_merge(DView F, DView R, DView U, uint32_t views) {
+  if (!(views & (1u << blockIdx.x))) return;
+  const DView& V = blockIdx.x == 0 ? F : (blockIdx.x == 1 ? R : U);
+  uint32_t* c = V.pool_ctr;
+  const uint32_t n = c[3];
+  if (n == 0) return;
+  const uint32_t end = c[1];
+  const uint32_t take = (int32_t)(end - c[2]) < 0 ? end : c[2];
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) V.free_ids[(end + i) % V.pool_cap] = V.spare_ids[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    c[2] = take;
+    c[1] = end + n;
+    c[3] = 0;
   }
 }
 
@@ -417,6 +460,91 @@ __global__ void __launch_bounds__(kBlock) k_check(DView V, uint32_t nv, uint32_t
 
 // Byte model: slabs one probe walks (op 0: until found / first EMPTY / end; op 1: to the
 // end of the chain unless the key is found first).  A second head access counts as a slab.
+// ------------------------------------------------------------ slab reclamation
+// Take back free-list entries that inserts asked for but did not get (the take counter
+// may run past the append counter).
+__global__ void k_free_fix(uint32_t* ctr) {
+  if (threadIdx.x == 0 && (int32_t)(ctr[1] - ctr[2]) < 0) ctr[2] = ctr[1];
+}
+
+// Rewrite every chain holding at least min_tomb tombstones with its live words packed from
+// its head slab in chain order, EMPTY after them, and the chain cut after the last slab it
+// still needs; the slabs after the cut are refilled with EMPTY words and appended to the
+// free list.  One 16-lane group per chain (head slab h: primary slabs [0, N), extra head
+// slabs after them).  Packing only moves a word to an earlier position of its own chain,
+// so the write position never passes the slab being read.
+__global__ void __launch_bounds__(kBlock) k_compact(DView V, uint64_t n_head, uint32_t nv, uint32_t min_tomb,
+                                                    unsigned long long* freed) {
+  const uint64_t g0 = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kGroup;
+  const uint64_t ng = (uint64_t)gridDim.x * kGroupsPerBlock;
+  const int gl = glane();
+  const uint32_t below = (1u << gl) - 1u;
+  unsigned long long total = 0;
+  for (uint64_t h = g0; h < n_head; h += ng) {
+    const uint32_t head = (uint32_t)h;
+    const uint64_t x = ld_word(slab_ptr(V, head) + gl);
+    const int nd0 = (head < nv && (uint32_t)(gbcast64(x, 15) >> 32) > 1) ? kKeysPerSlab - 1 : kKeysPerSlab;
+    uint32_t tomb = 0;
+    {
+      uint64_t y = x;
+      int nd = nd0;
+      while (true) {
+        tomb += __popc(gballot(gl < nd && y == kTombWord));
+        const uint32_t nx = gbcast((uint32_t)y, 15);
+        if (nx == kInvalid) break;
+        y = ld_word(slab_ptr(V, nx) + gl);
+        nd = kKeysPerSlab;
+      }
+    }
+    if (tomb < min_tomb || tomb == 0) continue;
+    uint32_t ws = head;  // slab being written, its capacity and fill
+    int wcap = nd0, wpos = 0;
+    uint64_t y = x;
+    int rnd = nd0;
+    while (true) {
+      const uint32_t next = gbcast((uint32_t)y, 15);
+      const bool live = gl < rnd && valid_key((uint32_t)y);
+      const uint32_t m = gballot(live);
+      const int r = __popc(m & below), cnt = __popc(m);
+      const int n1 = min(cnt, wcap - wpos);
+      if (live && r < n1) slab_ptr(V, ws)[wpos + r] = y;
+      wpos += n1;
+      if (cnt > n1) {  // spill into the next slab of the chain (not past the one being read)
+        ws = (uint32_t)ld_word(slab_ptr(V, ws) + 15);
+        wcap = kKeysPerSlab;
+        if (live && r >= n1) slab_ptr(V, ws)[r - n1] = y;
+        wpos = cnt - n1;
+      }
+      if (next == kInvalid) break;
+      y = ld_word(slab_ptr(V, next) + gl);
+      rnd = kKeysPerSlab;
+    }
+    // end the chain at ws and hand the rest to the free list (each lane rewrites only the
+    // word it read itself; the link comes from lane 15)
+    const uint64_t xw = ld_word(slab_ptr(V, ws) + gl);
+    const uint64_t wl = gbcast64(xw, 15);
+    const uint32_t rest = (uint32_t)wl;
+    if (gl >= wpos && gl < wcap) slab_ptr(V, ws)[gl] = kEmptyWord;
+    if (gl == 15) slab_ptr(V, ws)[15] = (wl & 0xFFFFFFFF00000000ull) | kInvalid;
+    uint32_t k = 0;
+    for (uint32_t t = rest; t != kInvalid; t = (uint32_t)ld_word(slab_ptr(V, t) + 15)) ++k;
+    if (k == 0) continue;
+    uint32_t pos = 0;
+    if (gl == 0) pos = atomicAdd(V.pool_ctr + 1, k);
+    pos = gbcast(pos, 0);
+    for (uint32_t t = rest; t != kInvalid;) {
+      const uint64_t xt = ld_word(slab_ptr(V, t) + gl);
+      const uint32_t nx = (uint32_t)gbcast64(xt, 15);
+      slab_ptr(V, t)[gl] = gl == 15 ? kNextNone : kEmptyWord;
+      if (gl == 0) V.free_ids[pos % V.pool_cap] = t;
+      ++pos;
+      t = nx;
+    }
+    total += k;
+  }
+  if (gl == 0 && total) atomicAdd(freed, total);
+}
+
 __device__ inline uint32_t walk_cost(const DView& V, uint32_t u, uint32_t key, int op) {
   Slab sl;
   int nd;
@@ -512,6 +640,8 @@ bool layout(const mk_config* c, uint64_t m, char* base, mk_graph* g, size_t* tot
     uint32_t* nbk = cv.take<uint32_t>(N);
     uint32_t* deg = cv.take<uint32_t>(N);
     uint32_t* pctr = cv.take<uint32_t>(64);
+    uint32_t* free_ids = cv.take<uint32_t>(pc);
+    uint32_t* spare_ids = cv.take<uint32_t>(pc);
     if (g) {
       ViewHost& vh = g->view[v];
       vh.on = true;
@@ -522,6 +652,8 @@ bool layout(const mk_config* c, uint64_t m, char* base, mk_graph* g, size_t* tot
       vh.d.slab = slab;
       vh.d.deg = deg;
       vh.d.pool_ctr = pctr;
+      vh.d.free_ids = free_ids;
+      vh.d.spare_ids = spare_ids;
       vh.d.pool_cap = (uint32_t)pc;
     }
   }
@@ -612,15 +744,21 @@ uint32_t default_band(uint64_t m, uint32_t n, double mean_w) {
   return (uint32_t)std::min(b, (double)(1u << 30));
 }
 
+// Pool slabs in use = bump high-water mark minus the free-list entries not yet taken.
 mk_status refresh_pool(mk_graph* g, hipStream_t stream) {
   for (int v = 0; v < 3; ++v)
     if (g->view[v].on)
-      MK_HIP(g, hipMemcpyAsync(g->h_pin + v, g->view[v].d.pool_ctr, sizeof(uint32_t),
+      MK_HIP(g, hipMemcpyAsync(g->h_pin + 2 * v, g->view[v].d.pool_ctr, 3 * sizeof(uint32_t),
                                hipMemcpyDeviceToHost, stream));
   MK_HIP(g, hipStreamSynchronize(stream));
-  for (int v = 0; v < 3; ++v)
-    if (g->view[v].on)
-      g->view[v].pool_used_est = std::min<uint64_t>((uint32_t)g->h_pin[v], g->view[v].pool_cap);
+  for (int v = 0; v < 3; ++v) {
+    ViewHost& vh = g->view[v];
+    if (!vh.on) continue;
+    const uint32_t* c = reinterpret_cast<const uint32_t*>(g->h_pin + 2 * v);
+    const int32_t avail = std::max<int32_t>(0, (int32_t)(c[1] - c[2]));
+    vh.pool_hw = std::min<uint64_t>(c[0], vh.pool_cap);
+    vh.pool_used_est = vh.pool_hw - std::min<uint64_t>((uint64_t)avail, vh.pool_hw);
+  }
   return MK_OK;
 }
 
@@ -678,6 +816,8 @@ void launch_insert(mk_graph* g, const uint32_t* s, const uint32_t* d, const uint
   if (g->view[VR].on || g->view[VU].on)
     hipLaunchKernelGGL(k_insert_aux, dim3(grid_for_lanes(3 * n)), dim3(kBlock), 0, stream, dv(g, VR),
                        dv(g, VU), g->cfg.views, lg, n, &g->ctr->pad0[0]);
+  hipLaunchKernelGGL(k_spare_merge, dim3(3), dim3(kBlock), 0, stream, dv(g, VF), dv(g, VR), dv(g, VU),
+                     g->cfg.views | MK_VIEW_FWD);
 }
 
 }  // namespace
@@ -899,12 +1039,31 @@ mk_status mk_graph_check(mk_graph* g, uint64_t* h_bad, hipStream_t stream) {
     if (!g->view[v].on) continue;
     hipLaunchKernelGGL(k_check, dim3(grid_for_groups(std::min<uint64_t>(g->n, 1u << 20))),
                        dim3(kBlock), 0, stream, g->view[v].d, g->n, (uint32_t)g->view[v].n_head,
-                       (uint32_t)g->view[v].pool_used_est, bad);
+                       (uint32_t)g->view[v].pool_hw, bad);
     MK_LAUNCH(g, "k_check");
   }
   MK_HIP(g, hipMemcpyAsync(g->h_pin, bad, 8, hipMemcpyDeviceToHost, stream));
   MK_HIP(g, hipStreamSynchronize(stream));
   *h_bad = g->h_pin[0];
+  return MK_OK;
+}
+
+mk_status mk_compact(mk_graph* g, uint32_t min_tombstones, uint64_t* h_freed, hipStream_t stream) {
+  if (!g || !h_freed) return MK_ERR_INVALID_ARG;
+  unsigned long long* freed = &g->ctr->u64tmp[2];
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, stream, (uint32_t*)freed, 2, 0u);
+  for (int v = 0; v < 3; ++v) {
+    const ViewHost& vh = g->view[v];
+    if (!vh.on) continue;
+    hipLaunchKernelGGL(k_free_fix, dim3(1), dim3(64), 0, stream, vh.d.pool_ctr);
+    hipLaunchKernelGGL(k_compact, dim3(grid_for_groups(std::min<uint64_t>(vh.n_head, 1u << 20))),
+                       dim3(kBlock), 0, stream, vh.d, vh.n_head, g->n, min_tombstones, freed);
+    MK_LAUNCH(g, "k_compact");
+  }
+  MK_HIP(g, hipMemcpyAsync(g->h_pin + 10, freed, 8, hipMemcpyDeviceToHost, stream));
+  mk_status st = refresh_pool(g, stream);
+  if (st != MK_OK) return st;
+  *h_freed = g->h_pin[10];
   return MK_OK;
 }
 

@@ -33,7 +33,8 @@ struct ViewHost {
   uint64_t head_reserved = 0;  // head slabs the arena reserves (upper bound)
   uint64_t n_head = 0;         // head slabs in use (N primary + extra)
   uint64_t pool_cap = 0;       // chained slabs
-  uint64_t pool_used_est = 0;  // host-side upper bound of the pool counter
+  uint64_t pool_used_est = 0;  // host-side upper bound of the pool slabs in use
+  uint64_t pool_hw = 0;        // bump-pointer high-water mark read back last
 };
 
 struct AlgoState {

@@ -87,6 +87,7 @@ def load():
         "mk_graph_stats": [vp, ctypes.POINTER(MkStats), vp],
         "mk_graph_check": [vp, ctypes.POINTER(u64), vp],
         "mk_probe_cost": [vp, i32, i32, vp, vp, u64, ctypes.POINTER(u64), vp],
+        "mk_compact": [vp, u32, ctypes.POINTER(u64), vp],
         "mk_batch_features": [vp, i32, vp, vp, vp, u64, vp, vp, u64, ctypes.POINTER(ctypes.c_float), vp],
         "mk_mlp_forward": [vp, vp, u32, vp, vp],
         "mk_traverse_from": [vp, u32, i32, vp, ctypes.c_size_t, u32, vp, vp, vp],
@@ -278,6 +279,14 @@ class Graph:
                                         self._s()), "mk_graph_export")
         k = int(cnt.value)
         return s[:k], d[:k], w[:k]
+
+    def compact(self, min_tombstones: int = 1, stream=None) -> int:
+        """Reclaim slabs: pack chains with tombstones, return unneeded slabs to the free
+        lists.  Returns the number of slabs freed.  Must not overlap other calls."""
+        out = ctypes.c_uint64()
+        _check(self.lib.mk_compact(self.h, int(min_tombstones), ctypes.byref(out), self._s(stream)),
+               "mk_compact")
+        return int(out.value)
 
     def stats(self):
         out = MkStats()

@@ -271,3 +271,81 @@ def test_band_width_leaves_sssp_unchanged(delta):
         od, op = p.o.sssp(src)
         assert np.array_equal(u32(dist), np.asarray(od, np.uint32))
         assert np.array_equal(u32(par), np.asarray(op, np.uint32))
+
+
+def test_compaction_keeps_the_graph_and_frees_slabs():
+    """Delete churn leaves tombstones; compaction packs the chains and frees slabs, and the
+    arc set, queries and every incremental algorithm still equal the oracle afterwards."""
+    say("case: compaction after churn")
+    g = I.rmat_s(11)
+    p = make_pair(g, source=I.max_out_degree_vertex(g))
+    wl = I.Workload(g, 21)
+    for _ in range(3):
+        s, d, w = wl.insert_batch(3000)
+        p.insert(s, d, w)
+        s, d = wl.delete_batch(3000)
+        p.delete(s, d)
+    p.check_all()  # the incremental state is now current
+    used = sum(p.g.stats()["pool_used"])
+    freed = p.g.compact()
+    assert freed > 0 and sum(p.g.stats()["pool_used"]) == used - freed
+    p.check_structure()
+    qs, qd = wl.query_batch(5000)
+    p.query(qs, qd)
+    assert p.g.compact() == 0  # nothing left to reclaim
+    for b in (2000, 500):
+        s, d, w = wl.insert_batch(b)
+        p.insert(s, d, w)
+        p.check_structure()
+        p.check_all()
+        s, d = wl.delete_batch(b)
+        p.delete(s, d)
+        p.check_all()
+
+
+def test_compaction_of_one_long_chain_and_reuse():
+    """Hashing off: one source's chain of 200 slabs; after two thirds are deleted the chain
+    shrinks to the slabs its live arcs need and re-inserts draw from the free list."""
+    say("case: compaction of a long chain")
+    n = 4000
+    p = Pair(n, [1], [2], [5], source=0, load_factor=0.0)
+    rng = np.random.default_rng(8)
+    dst = rng.permutation(np.arange(1, n))[:3000]
+    p.insert(np.zeros(3000, np.int64), dst, rng.integers(1, 100, 3000))
+    p.delete(np.zeros(2000, np.int64), dst[:2000])
+    freed = p.g.compact()
+    assert freed >= 100, freed
+    p.check_structure()
+    p.query(np.zeros(n, np.int64), np.arange(n))
+    p.insert(np.zeros(2000, np.int64), dst[:2000], np.full(2000, 4))
+    p.check_structure()
+    p.check_all(algos=("bfs", "sssp", "wcc", "tc"))
+
+
+def test_compaction_lets_a_full_pool_take_more_inserts():
+    """A pool sized for a few batches runs out under insert/delete churn on one source;
+    after compaction the refused batch fits."""
+    say("case: compaction of a full pool")
+    n = 20000
+    p = Pair(n, [1], [2], [5], source=0, views=native.VIEW_FWD | native.VIEW_REV, pool_slabs=600,
+             load_factor=0.0)
+    refused = None
+    for r in range(40):
+        dst = 1 + r * 300 + np.arange(300)
+        try:
+            p.g.insert_edges(np.zeros(300, np.int64), dst, np.full(300, 2))
+        except native.MkError as e:
+            assert e.status == 2
+            refused = dst
+            break
+        p.o.insert(np.zeros(300, np.uint32), dst.astype(np.uint32), np.full(300, 2, np.uint32))
+        p.delete(np.zeros(300, np.int64), dst)
+    assert refused is not None, "the pool never filled"
+    p.check_structure()
+    say(f"  refused at round {r}: {p.g.stats()}")
+    freed = p.g.compact()
+    say(f"  freed {freed}: {p.g.stats()}")
+    assert freed > 0
+    p.insert(np.zeros(300, np.int64), refused, np.full(300, 2))
+    p.check_structure()
+    p.check_all(algos=("bfs", "sssp", "wcc"))
