@@ -422,6 +422,7 @@ def serving_bench(args):
         st = srv.run(reqs, realtime=True)
         srv.close()
         out[label] = st.summary()
+        out[label]["compactions"] = srv.compactions
         log(f"[serve] {label}: {out[label]}")
         del G, srv
         torch.cuda.empty_cache()

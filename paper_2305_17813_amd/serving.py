@@ -7,7 +7,9 @@ loop keeps the graph resident in HBM and:
 
 * merges consecutive update requests of one kind whose arcs do not overlap into one batch
   (each request's statuses are then exactly those it would get alone), admitted against
-  the slab-pool headroom (inserts that might not fit are rejected, nothing applied);
+  the slab-pool headroom; when an insert might not fit, the slabs that deletes left behind
+  are reclaimed first (compaction, while no read is in flight), and only then is the
+  insert rejected (nothing applied);
 * runs the reads between two updates concurrently, one per slot, each slot with its own
   HIP stream (default priority) and its own traversal workspace, so their kernels overlap
   on the device while new requests keep being admitted;
@@ -180,6 +182,7 @@ class Server:
         self.slot_cv = threading.Condition()
         self.pending_feats: Dict[str, np.ndarray] = {}
         st = G.stats()
+        self.compactions = 0
         self.headroom_est = None
         self._refresh_headroom(st)
         self._warm_up()
@@ -207,6 +210,11 @@ class Server:
             self.headroom_est -= n
             return True
         self._refresh_headroom()
+        if n > self.headroom_est:
+            # reclaim the slabs that deletes left behind (no read is in flight here), then retry
+            self.compactions += 1
+            self.G.compact()
+            self._refresh_headroom()
         if n <= self.headroom_est:
             self.headroom_est -= n
             return True

@@ -82,3 +82,26 @@ def test_mixed_run_equals_alone_poisson_with_cost_model():
     cm, hist, r = CM.fit(rec, epochs=150)
     st = _serve(cm, realtime=True, seed=32)
     assert st.summary()["p99_ms"] is not None
+
+
+def test_mixed_run_compacts_when_the_pool_runs_low():
+    """A pool with little headroom: before rejecting an insert the server reclaims slabs
+    (compaction, with no read in flight); every admitted request still equals its result
+    alone."""
+    say("case: serving with a tight pool")
+    g = I.rmat_s(12)
+    tracked = I.max_out_degree_vertex(g)
+    probe = native.Graph(g.n, g.src, g.dst, g.w)
+    used = max(probe.stats()["pool_used"])
+    del probe
+    G = native.Graph(g.n, g.src, g.dst, g.w, pool_slabs=used + 3000)
+    reqs = S.make_requests(g, I.Workload(g, 33), 160, rate=4000.0, seed=33, tracked=tracked,
+                           upd_median=600, upd_clip=(20, 4000), q_median=2000, q_clip=(10, 20000))
+    srv = S.Server(G, tracked, n_slots=4, keep_results=True)
+    st = srv.run(reqs, realtime=False)
+    srv.close()
+    say(f"  compactions {srv.compactions}, rejected {st.rejected}: {st.summary()['p99_ms']}")
+    assert srv.compactions >= 1
+    G2 = native.Graph(g.n, g.src, g.dst, g.w)
+    alone = S.run_alone(G2, reqs, tracked)
+    _compare(reqs, alone)
