@@ -81,6 +81,9 @@ def parse():
     ap.add_argument("--grid", action="store_true",
                     help="run the road-network benchmark (4096 x 4096 grid, batches of 1K/10K/100K "
                          "edges, incremental SSSP/BFS/WCC) instead of the step benchmark")
+    ap.add_argument("--ablation", action="store_true",
+                    help="hashing / load-factor ablation at R-MAT scale 22 (forward view): memory, "
+                         "1M insert / delete / query, static BFS and PageRank per load factor")
     ap.add_argument("--serve-requests", type=int, default=600)
     ap.add_argument("--serve-rate", type=float, default=150.0, help="requests per second")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -106,6 +109,8 @@ def main():
         return serving_bench(args)
     if args.grid:
         return grid_bench(args)
+    if args.ablation:
+        return ablation_bench(args)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if args.calibrate_copy:
@@ -307,6 +312,78 @@ def main():
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(g_in, steps[args.warmup], src_v, args, wall * 1e3 / K)
     print(json.dumps(result))
+
+
+def ablation_bench(args):
+    """The paper's hashing ablation, with the load factor swept: for each load factor (0 =
+    hashing off, one bucket per vertex) the forward view of the R-MAT graph is built and the
+    arena size, slabs, 1M-arc insert / delete / 1M query times (medians of 3 rounds), slabs
+    walked per op and the static BFS and PageRank times are reported."""
+    import numpy as np
+    import torch
+
+    from paper_2305_17813_amd import inputs as I
+    from paper_2305_17813_amd import native
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    g = I.rmat_s(args.scale, device=dev)
+    src_v = I.max_out_degree_vertex(g)
+    B = args.batch
+    rows = []
+    for lf in (0.0, 0.5, 0.7, 1.0, 2.0):
+        t0 = time.time()
+        G = native.Graph(g.n, g.src, g.dst, g.w, views=native.VIEW_FWD | native.VIEW_REV, load_factor=lf,
+                         device=dev)
+        torch.cuda.synchronize()
+        build_s = time.time() - t0
+        st = G.stats()
+        wl = I.Workload(g, args.seed + 40)
+        stream = G.stream
+        ev = lambda: torch.cuda.Event(enable_timing=True)
+        ti, td, tq, sl = [], [], [], {}
+        for r in range(3):
+            s, d, w = (native.as_u32(x, dev) for x in wl.insert_batch(B))
+            ds, dd = (native.as_u32(x, dev) for x in wl.delete_batch(B))
+            qs, qd = (native.as_u32(x, dev) for x in wl.query_batch(B))
+            if r == 0:
+                sl = {"insert": G.probe_cost(1, 0, s, d) / B, "delete": G.probe_cost(0, 0, ds, dd) / B,
+                      "query": G.probe_cost(0, 0, qs, qd) / B}
+            e = [ev() for _ in range(4)]
+            torch.cuda.synchronize()
+            e[0].record(stream)
+            G.insert_edges(s, d, w, status=False)
+            e[1].record(stream)
+            G.delete_edges(ds, dd, status=False)
+            e[2].record(stream)
+            G.query_edges(qs, qd)
+            e[3].record(stream)
+            e[3].synchronize()
+            ti.append(e[0].elapsed_time(e[1]))
+            td.append(e[1].elapsed_time(e[2]))
+            tq.append(e[2].elapsed_time(e[3]))
+        a, b = ev(), ev()
+        a.record(stream)
+        G.bfs(src_v, native.RECOMPUTE)
+        b.record(stream)
+        b.synchronize()
+        t_bfs = a.elapsed_time(b)
+        a.record(stream)
+        _, it = G.pagerank(mode=native.RECOMPUTE)
+        b.record(stream)
+        b.synchronize()
+        row = {"load_factor": lf, "arena_GB": G.arena_bytes / 1e9, "head_slabs_fwd": st["head_slabs"][0],
+               "pool_slabs_fwd": st["pool_used"][0], "build_s": build_s,
+               "insert_ms": float(np.median(ti)), "delete_ms": float(np.median(td)),
+               "query_ms": float(np.median(tq)), "slabs_per_op": sl, "bfs_static_ms": t_bfs,
+               "pagerank_static_ms": a.elapsed_time(b), "pagerank_iters": int(it.item())}
+        log(f"[ablation] {row}")
+        rows.append(row)
+        del G
+        torch.cuda.empty_cache()
+    print(json.dumps({"metric": "hashing / load-factor ablation", "unit": "ms",
+                      "config": {"workload": f"R-MAT scale {args.scale}, fwd + rev views, batches of {B}"},
+                      "rows": rows}))
 
 
 def grid_bench(args):
