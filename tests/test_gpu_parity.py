@@ -9,7 +9,7 @@ import torch
 
 from paper_2305_17813_amd import inputs as I
 from paper_2305_17813_amd import native
-from parity import Pair, say, u32
+from parity import PR_L1_TOL, Pair, say, u32
 
 pytestmark = pytest.mark.gpu
 
@@ -349,3 +349,60 @@ def test_compaction_lets_a_full_pool_take_more_inserts():
     p.insert(np.zeros(300, np.int64), refused, np.full(300, 2))
     p.check_structure()
     p.check_all(algos=("bfs", "sssp", "wcc"))
+
+
+def test_degenerate_graphs_and_empty_batches():
+    """One vertex; many vertices and no arc; an isolated source; empty batches (every
+    algorithm unchanged); a complete digraph, whose triangle count is C(n, 3); a directed
+    cycle, whose PageRank is uniform and whose BFS levels are distances along the cycle."""
+    say("case: degenerate graphs")
+    p = Pair(1, [], [], [], source=0)
+    p.check_all()
+    p = Pair(64, [], [], [], source=5)
+    p.check_all()
+    r, _ = p.g.pagerank()
+    assert np.allclose(r.cpu().numpy(), 1 / 64, atol=1e-7)
+    e = np.zeros(0, np.int64)
+    p.insert(e, e, e)
+    p.delete(e, e)
+    f, w = p.g.query_edges(e, e)
+    assert f.numel() == 0
+    p.check_all()
+    # complete digraph on 40 vertices
+    n = 40
+    s, d = np.nonzero(~np.eye(n, dtype=bool))
+    p = Pair(n, s, d, (s * 7 + d) % 100 + 1, source=3)
+    p.check_all()
+    assert int(p.g.triangles().item()) == n * (n - 1) * (n - 2) // 6
+    # directed cycle of 100
+    n = 100
+    s = np.arange(n)
+    p = Pair(n, s, (s + 1) % n, np.ones(n), source=0)
+    p.check_all()
+    lv, _ = p.g.bfs(0)
+    assert np.array_equal(u32(lv), np.arange(n, dtype=np.uint32))
+    r, _ = p.g.pagerank()
+    assert np.abs(r.double().cpu().numpy() - 1 / n).sum() <= PR_L1_TOL
+    # a source without out-arcs on R-MAT: everything else unreachable
+    g = I.rmat_s(10)
+    deg = np.bincount(u32(g.src), minlength=g.n)
+    p = make_pair(g, source=int(np.nonzero(deg == 0)[0][0]))
+    p.check_all(algos=("bfs", "sssp"))
+
+
+@pytest.mark.parametrize("b", [1, 63, 65, 255, 257, 4097])
+def test_ragged_batch_sizes(b):
+    """Batch sizes around the wave (64), block (256) and the 21-arc packing of the delete
+    kernel's view lanes."""
+    say(f"case: ragged batch {b}")
+    g = I.rmat_s(10)
+    p = make_pair(g, source=I.max_out_degree_vertex(g))
+    wl = I.Workload(g, 100 + b)
+    s, d, w = wl.insert_batch(b)
+    p.insert(s, d, w)
+    s, d = wl.delete_batch(b)
+    p.delete(s, d)
+    qs, qd = wl.query_batch(b)
+    p.query(qs, qd)
+    p.check_structure()
+    p.check_all(algos=("bfs", "sssp", "wcc", "tc"))
