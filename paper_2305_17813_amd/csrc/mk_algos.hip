@@ -74,26 +74,34 @@ __global__ void k_wcc_init(uint32_t* P, uint32_t nv) {
   for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) P[v] = v;
 }
 
+// Static WCC: union over every arc.  A neighbour whose parent already is u's root (as
+// found once per vertex; a stale root only means an older member of the same component)
+// is skipped without a union, and a lane issues the parent loads of a whole slab together.
 __global__ void __launch_bounds__(kBlock) k_wcc_all(DView F, uint32_t* P, uint32_t nv,
                                                     const uint32_t* heavy, const uint32_t* nheavy) {
   const uint32_t g0 = (blockIdx.x * kBlock + threadIdx.x) / kGroup;
   const uint32_t ng = gridDim.x * kGroupsPerBlock;
-  auto body = [&](uint32_t u, uint64_t x, bool data) {
+  auto body = [&](uint32_t u, uint32_t ru, uint64_t x, bool data) {
     const uint32_t v = (uint32_t)x;
-    if (data && valid_key(v)) uf_union(P, u, v);
+    if (data && valid_key(v) && ld_u32_coherent(P + v) != ru) uf_union(P, u, v);
   };
   // single-bucket vertices: one lane each
   for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < nv; u += gridDim.x * blockDim.x) {
     if (F.nbk[u] != 1 || F.deg[u] == 0) continue;
+    const uint32_t ru = uf_find(P, u);
     Slab sl;
     uint32_t t = u;
     while (true) {
       load_slab(F, t, sl);
+      uint32_t pv[kKeysPerSlab];
 #pragma unroll
       for (int j = 0; j < kKeysPerSlab; ++j) {
         const uint32_t v = (uint32_t)sl.w[j];
-        if (valid_key(v)) uf_union(P, u, v);
+        pv[j] = valid_key(v) ? ld_u32_coherent(P + v) : ru;
       }
+#pragma unroll
+      for (int j = 0; j < kKeysPerSlab; ++j)
+        if (pv[j] != ru) uf_union(P, u, (uint32_t)sl.w[j]);
       t = (uint32_t)sl.w[15];
       if (t == kInvalid) break;
     }
@@ -101,12 +109,14 @@ __global__ void __launch_bounds__(kBlock) k_wcc_all(DView F, uint32_t* P, uint32
   for (uint32_t u = g0; u < nv; u += ng) {
     const uint32_t nb = F.nbk[u];
     if (nb == 1 || nb > kHeavyBuckets || F.deg[u] == 0) continue;
-    for_each_slab(F, u, [&](uint64_t x, bool data) { body(u, x, data); });
+    const uint32_t ru = uf_find(P, u);
+    for_each_slab(F, u, [&](uint64_t x, bool data) { body(u, ru, x, data); });
   }
   const uint32_t nh = *nheavy, gib = threadIdx.x / kGroup;
   for (uint32_t j = blockIdx.x; j < nh; j += gridDim.x) {
     const uint32_t u = heavy[j];
-    for_each_slab_strided(F, u, gib, kGroupsPerBlock, [&](uint64_t x, bool data) { body(u, x, data); });
+    const uint32_t ru = uf_find(P, u);
+    for_each_slab_strided(F, u, gib, kGroupsPerBlock, [&](uint64_t x, bool data) { body(u, ru, x, data); });
   }
 }
 
