@@ -338,10 +338,11 @@ __device__ inline bool ranks_before(const uint32_t* deg, uint32_t a, uint32_t b)
 // |N(a) intersect N(b)| counted by the calling group: walk N(a), each lane probes its
 // neighbour in b's table.  Returns the group total in every lane.
 __device__ inline uint64_t group_intersect(const DView& U, uint32_t a, uint32_t b) {
+  const Table tb = group_table(U, b);
   uint64_t c = 0;
   for_each_slab(U, a, [&](uint64_t x, bool data) {
     const uint32_t k = (uint32_t)x;
-    if (data && valid_key(k) && k != b) c += lane_has(U, b, k);
+    if (data && valid_key(k) && k != b) c += lane_has(U, tb, k);
   });
   return gsum_u64(c);
 }
@@ -433,10 +434,11 @@ __global__ void __launch_bounds__(kBlock) k_tc_batch(DView U, const uint64_t* ke
     const uint64_t ulo = lower_bound_u64(keys, nk, (uint64_t)u << 32);
     const uint64_t uhi = lower_bound_u64(keys, nk, ((uint64_t)u + 1) << 32);
     uint64_t c2 = 0, c3 = 0;
+    const Table tu = group_table(U, u);
     for (uint64_t j = vlo + gl; j < vhi; j += kGroup) {
       const uint32_t x = (uint32_t)keys[j];
       if (x == u) continue;
-      c2 += lane_has(U, u, x);
+      c2 += lane_has(U, tu, x);
       if (canon) {
         const uint64_t want = ((uint64_t)u << 32) | x;
         const uint64_t p = lower_bound_u64(keys + ulo, uhi - ulo, want);
@@ -472,10 +474,11 @@ __global__ void __launch_bounds__(kBlock) k_tc_heavy_s1(DView U, const uint64_t*
     const uint32_t u = (uint32_t)(key >> 32), v = (uint32_t)key;
     const bool u_small = U.deg[u] <= U.deg[v];
     const uint32_t a = u_small ? u : v, b = u_small ? v : u;
+    const Table tb = group_table(U, b);
     uint64_t c = 0;
     for_each_slab_strided(U, a, (uint32_t)(it % kTcSplit), kTcSplit, [&](uint64_t x, bool data) {
       const uint32_t k = (uint32_t)x;
-      if (data && valid_key(k) && k != b) c += lane_has(U, b, k);
+      if (data && valid_key(k) && k != b) c += lane_has(U, tb, k);
     });
     c = gsum_u64(c);
     if (glane() == 0) acc += 2 * c;

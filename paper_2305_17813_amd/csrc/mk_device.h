@@ -342,11 +342,40 @@ __device__ inline uint64_t lane_probe(const DView& V, uint32_t u, uint32_t key) 
   }
 }
 
-// Single-lane membership test (each lane probes its own key; used where every lane of a
-// group has a different key, as in triangle counting).  Whole slabs are read with 16-byte
-// loads, so a probe waits one round trip per slab.
-__device__ inline bool lane_has(const DView& V, uint32_t u, uint32_t key) {
-  return lane_probe(V, u, key) != kEmptyWord;
+// Where the lanes of a group probe many keys in one table (triangle counting): u's bucket
+// count and first extra head slab, read once from u's primary slab by the whole group.
+struct Table {
+  uint32_t u, nb, xb;
+};
+__device__ inline Table group_table(const DView& V, uint32_t u) {
+  const uint64_t x = ld_word(slab_ptr(V, u) + glane());
+  const uint32_t nb = (uint32_t)(gbcast64(x, 15) >> 32);
+  return Table{u, nb, nb > 1 ? gbcast((uint32_t)x, 14) : 0u};
+}
+
+// Single-lane membership test of `key` in a table whose head is known: one round trip per
+// slab of the hashed chain (whole slabs are read with 16-byte loads).
+__device__ inline bool lane_has(const DView& V, const Table& t, uint32_t key) {
+  uint32_t s = t.u;
+  int nd = kKeysPerSlab;
+  if (t.nb > 1) {
+    const uint32_t b = bucket_of(key, t.nb, V.hash_a, V.hash_b);
+    if (b == 0) nd = kKeysPerSlab - 1;
+    else s = t.xb + b - 1;
+  }
+  Slab sl;
+  load_slab(V, s, sl);
+  while (true) {
+    int hit, empty;
+    uint64_t hitw;
+    scan_slab(sl, nd, key, 0, hit, hitw, empty);
+    if (hit >= 0) return true;
+    if (empty >= 0) return false;
+    s = (uint32_t)sl.w[15];
+    if (s == kInvalid) return false;
+    load_slab(V, s, sl);
+    nd = kKeysPerSlab;
+  }
 }
 
 }  // namespace mk
