@@ -180,7 +180,7 @@ class Server:
         self.maint = threading.Lock()
         self.free_slots = deque(range(n_slots))
         self.slot_cv = threading.Condition()
-        self.pending_feats: Dict[str, np.ndarray] = {}
+        self.pending: Dict[str, tuple] = {}
         st = G.stats()
         self.compactions = 0
         self.headroom_est = None
@@ -222,9 +222,16 @@ class Server:
 
     # ---------------------------------------------------------------- requests
     def _mode(self, algo: str) -> int:
-        if self.cm is None or algo not in self.pending_feats:
+        """The cost model's choice from the features of the latest update batch applied
+        since `algo` last ran, computed here rather than on the update path; AUTO without a
+        model or without a pending batch."""
+        pend = self.pending.get(algo)
+        if self.cm is None or pend is None:
             return native.AUTO
-        return int(self.cm.choose(self.pending_feats[algo][None, :])[0])
+        kind, s, d, w = pend
+        feats = self.G.batch_features(ALGO_ID[algo], (s, d, w) if kind == "insert" else None,
+                                      (s, d) if kind == "delete" else None)
+        return int(self.cm.choose(feats[None, :])[0])
 
     def _maintained(self, r: Request, stream):
         with self.maint:
@@ -237,7 +244,7 @@ class Server:
             else:
                 res = self.G.sssp(r.source, mode, stream=stream)
             stream.synchronize()
-            self.pending_feats.pop(algo, None)
+            self.pending.pop(algo, None)
             r.mode = mode
         return res
 
@@ -279,11 +286,9 @@ class Server:
                     r.t_done = time.perf_counter() - t0
                 stats.rejected += len(group)
                 return
-        if self.cm is not None:  # features of the batch for every maintained algorithm
-            for algo in ("bfs", "sssp", "pagerank"):
-                self.pending_feats[algo] = self.G.batch_features(
-                    ALGO_ID[algo], (s, d, w) if kind == "insert" else None,
-                    (s, d) if kind == "delete" else None)
+        if self.cm is not None:  # the latest batch, remembered until each algorithm next runs
+            for algo in ALGO_ID:
+                self.pending[algo] = (kind, s, d, w)
         main = self.G.stream
         if kind == "insert":
             st = self.G.insert_edges(s, d, w, stream=main)
