@@ -46,9 +46,9 @@ __global__ void k_zero_u32(uint32_t* p, uint32_t n) {
 // pointer goes to a smaller id and the final root of a component is its minimum id.
 __device__ inline uint32_t uf_find(uint32_t* P, uint32_t x) {
   while (true) {
-    const uint32_t p = ld_u32_coherent(P + x);
+    const uint32_t p = ld_u32(P + x);
     if (p == x) return x;
-    const uint32_t gp = ld_u32_coherent(P + p);
+    const uint32_t gp = ld_u32(P + p);
     if (gp != p) __hip_atomic_store(P + x, gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);  // halving
     x = gp;
   }
@@ -83,7 +83,7 @@ __global__ void __launch_bounds__(kBlock) k_wcc_all(DView F, uint32_t* P, uint32
   const uint32_t ng = gridDim.x * kGroupsPerBlock;
   auto body = [&](uint32_t u, uint32_t ru, uint64_t x, bool data) {
     const uint32_t v = (uint32_t)x;
-    if (data && valid_key(v) && ld_u32_coherent(P + v) != ru) uf_union(P, u, v);
+    if (data && valid_key(v) && ld_u32(P + v) != ru) uf_union(P, u, v);
   };
   // single-bucket vertices: one lane each
   for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < nv; u += gridDim.x * blockDim.x) {
@@ -97,7 +97,7 @@ __global__ void __launch_bounds__(kBlock) k_wcc_all(DView F, uint32_t* P, uint32
 #pragma unroll
       for (int j = 0; j < kKeysPerSlab; ++j) {
         const uint32_t v = (uint32_t)sl.w[j];
-        pv[j] = valid_key(v) ? ld_u32_coherent(P + v) : ru;
+        pv[j] = valid_key(v) ? ld_u32(P + v) : ru;
       }
 #pragma unroll
       for (int j = 0; j < kKeysPerSlab; ++j)

@@ -147,11 +147,15 @@ __device__ inline uint32_t wave_reserve(uint32_t* ctr, uint32_t cnt) {
 __device__ inline uint64_t ld_word(const uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
-__device__ inline uint32_t ld_u32_coherent(const uint32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Tree nodes and union-find parents are read the same way: a value another lane changes
+// during the kernel may be seen late (the L2 of each XCD caches it), which only delays
+// progress (a stale distance relaxes worse candidates, a stale parent makes a CAS fail and
+// return the true one).  Agent-scope loads would bypass that cache on every read.
+__device__ inline uint32_t ld_u32(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
-__device__ inline uint64_t ld_u64_coherent(const uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ inline uint64_t ld_u64(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
 __device__ inline uint64_t cas64(uint64_t* p, uint64_t expect, uint64_t desire) {
   return atomicCAS((unsigned long long*)p, (unsigned long long)expect, (unsigned long long)desire);

@@ -194,7 +194,7 @@ __global__ void __launch_bounds__(kBlock) k_expand(DView F, uint64_t* D, Queues 
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nl; i += gridDim.x * blockDim.x) {
     const uint32_t u = q.cur[0][i];
     if (F.nbk[u] != 1) continue;
-    const uint64_t du = ld_u64_coherent(D + u) >> 32;
+    const uint64_t du = ld_u64(D + u) >> 32;
     relax_bucket_lane<kUnit>(F, D, u, du, 0, 1, 0, q, r, T, mark, stamp);
   }
   const uint32_t g0 = (blockIdx.x * kBlock + threadIdx.x) / kGroup;
@@ -203,13 +203,13 @@ __global__ void __launch_bounds__(kBlock) k_expand(DView F, uint64_t* D, Queues 
     const uint32_t u = q.cur[0][i];
     const uint32_t nb = F.nbk[u];
     if (nb == 1 || (uint32_t)glane() >= nb) continue;
-    const uint64_t du = ld_u64_coherent(D + u) >> 32;
+    const uint64_t du = ld_u64(D + u) >> 32;
     relax_bucket_lane<kUnit>(F, D, u, du, glane(), nb, extra_base(F, u), q, r, T, mark, stamp);
   }
   for (uint32_t j = blockIdx.x; j < nh; j += gridDim.x) {
     const uint32_t u = q.cur[1][j];
     const uint32_t nb = F.nbk[u];
-    const uint64_t du = ld_u64_coherent(D + u) >> 32;
+    const uint64_t du = ld_u64(D + u) >> 32;
     const uint32_t xb = extra_base(F, u);
     for (uint32_t b = threadIdx.x; b < nb; b += kBlock)
       relax_bucket_lane<kUnit>(F, D, u, du, b, nb, xb, q, r, T, mark, stamp);
@@ -218,7 +218,7 @@ __global__ void __launch_bounds__(kBlock) k_expand(DView F, uint64_t* D, Queues 
   for (uint32_t it = blockIdx.x * kBlock + threadIdx.x; it < ngi * kGiantLanes; it += nthreads) {
     const uint32_t u = q.cur[2][it / kGiantLanes];
     const uint32_t nb = F.nbk[u];
-    const uint64_t du = ld_u64_coherent(D + u) >> 32;
+    const uint64_t du = ld_u64(D + u) >> 32;
     const uint32_t xb = extra_base(F, u);
     for (uint32_t b = it % kGiantLanes; b < nb; b += kGiantLanes)
       relax_bucket_lane<kUnit>(F, D, u, du, b, nb, xb, q, r, T, mark, stamp);
@@ -240,7 +240,7 @@ __global__ void k_band_min(const uint64_t* D, const uint32_t* far, const uint32_
   const uint32_t n = *far_cnt, told = *T;
   uint32_t m = 0xFFFFFFFFu;
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const uint32_t d = (uint32_t)(ld_u64_coherent(D + far[i]) >> 32);
+    const uint32_t d = (uint32_t)(ld_u64(D + far[i]) >> 32);
     if (d >= told && d < m) m = d;
   }
   for (int o = 32; o > 0; o >>= 1) m = min(m, (uint32_t)__shfl_xor((int)m, o));
@@ -264,7 +264,7 @@ __global__ void k_band_split(const uint32_t* nbk, const uint64_t* D, const uint3
     uint32_t v = 0, nb = 0;
     if (i < n) {
       v = far[i];
-      const uint32_t d = (uint32_t)(ld_u64_coherent(D + v) >> 32);
+      const uint32_t d = (uint32_t)(ld_u64(D + v) >> 32);
       near = d >= told && d < tnew;
       keep = d >= tnew;
     }
@@ -322,7 +322,7 @@ __global__ void k_relax_batch(DView F, uint64_t* D, Log lg, uint64_t n, PushQ Q,
     if (i < n && lg.st[i] == 1) {
       const uint32_t u = lg.s[i];
       v = lg.d[i];
-      const uint64_t du = ld_u64_coherent(D + u);
+      const uint64_t du = ld_u64(D + u);
       if (du != kTreeNone) {
         cand = tree_node((du >> 32) + (kUnit ? 1u : lg.w[i]), u);
         if (cand < D[v]) improve = amin64(D + v, cand) > cand;
@@ -345,7 +345,7 @@ __global__ void k_invalidate(DView F, uint64_t* D, Log lg, uint64_t n, PushQ Q, 
     if (i < n && lg.st[i] == 1) {
       const uint32_t u = lg.s[i];
       v = lg.d[i];
-      const uint64_t dv = ld_u64_coherent(D + v);
+      const uint64_t dv = ld_u64(D + v);
       if (dv != kTreeNone && (uint32_t)dv == u) hit = cas64(D + v, dv, kTreeNone) == dv;
     }
     wave_push(inval, inval_cnt, hit, v);
@@ -361,7 +361,7 @@ __device__ inline void inval_word(const DView& F, uint64_t* D, uint32_t x_parent
   const uint32_t y = (uint32_t)w;
   bool hit = false;
   if (data && valid_key(y)) {
-    const uint64_t dy = ld_u64_coherent(D + y);
+    const uint64_t dy = ld_u64(D + y);
     if (dy != kTreeNone && (uint32_t)dy == x_parent) hit = cas64(D + y, dy, kTreeNone) == dy;
   }
   wave_push(inval, inval_cnt, hit, y);
@@ -386,7 +386,7 @@ __global__ void __launch_bounds__(kBlock) k_propagate(DView F, uint64_t* D, Queu
 #pragma unroll
       for (int j = 0; j < kKeysPerSlab; ++j) {
         const uint32_t y = (uint32_t)sl.w[j];
-        dy[j] = valid_key(y) ? ld_u64_coherent(D + y) : kTreeNone;
+        dy[j] = valid_key(y) ? ld_u64(D + y) : kTreeNone;
       }
 #pragma unroll
       for (int j = 0; j < kKeysPerSlab; ++j) {
@@ -447,7 +447,7 @@ template <bool kUnit>
 __device__ inline uint64_t pull_word(const uint64_t* D, uint64_t x, bool data) {
   const uint32_t u = (uint32_t)x;
   if (!data || !valid_key(u)) return kTreeNone;
-  const uint64_t du = ld_u64_coherent(D + u);
+  const uint64_t du = ld_u64(D + u);
   if (du == kTreeNone) return kTreeNone;
   return tree_node((du >> 32) + (kUnit ? 1ull : (x >> 32)), u);
 }
