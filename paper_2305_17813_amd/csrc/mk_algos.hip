@@ -25,16 +25,21 @@ inline uint32_t blocks_for(uint64_t n, uint32_t cap = 4096) {
   return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((n + kBlock - 1) / kBlock, cap));
 }
 
-// Vertices of a view with more than kHeavyBuckets buckets.
+// Vertices of a view with more than kHeavyBuckets buckets (staged per block: they are
+// sparse, and one counter atomic per wave that finds one would serialize).
 __global__ void k_collect_heavy(const uint32_t* nbk, uint32_t nv, uint32_t* out, uint32_t* cnt) {
+  __shared__ Stage S[1];
+  stage_open(S[0], out, cnt);
+  __syncthreads();
   const uint64_t lane = threadIdx.x & 63;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x - lane; base < nv;
        base += stride) {
     const uint64_t v = base + lane;
     const bool heavy = v < nv && nbk[v] > kHeavyBuckets;
-    wave_push(out, cnt, heavy, (uint32_t)v);
+    stage_push(S[0], heavy, (uint32_t)v);
   }
+  stage_close(S);
 }
 
 __global__ void k_zero_u32(uint32_t* p, uint32_t n) {

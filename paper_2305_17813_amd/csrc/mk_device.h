@@ -139,6 +139,57 @@ __device__ inline uint32_t wave_reserve(uint32_t* ctr, uint32_t cnt) {
   return __shfl(base, leader) + excl;
 }
 
+// ----------------------------------------------------------------- block-staged appends
+// Appends to a queue whose counter would otherwise take one atomic per wave (sparse pushes
+// from many waves serialize on that one address) go to an LDS buffer per output, with one
+// LDS atomic per wave; when the kernel ends, the block reserves room for each buffer with a
+// single global atomic and copies it out.  A full buffer spills further appends straight to
+// its output.  Every thread of the block must reach stage_close (no early return).
+constexpr uint32_t kStage = 1024;
+struct Stage {
+  uint32_t n, base;
+  uint32_t* q;    // output queue and its counter
+  uint32_t* ctr;
+  uint32_t buf[kStage];
+};
+
+// Thread 0 opens the stages; the caller then synchronizes the block once.
+__device__ inline void stage_open(Stage& S, uint32_t* q, uint32_t* ctr) {
+  if (threadIdx.x == 0) {
+    S.n = 0;
+    S.q = q;
+    S.ctr = ctr;
+  }
+}
+
+__device__ inline void stage_push(Stage& S, bool p, uint32_t v) {
+  const uint64_t m = __ballot(p);
+  if (m == 0) return;
+  const int leader = __builtin_ctzll(m);
+  uint32_t b = 0;
+  if (lane64() == leader) b = atomicAdd(&S.n, (uint32_t)__popcll(m));
+  b = __shfl(b, leader) + lanes_below(m);
+  if (p) {
+    if (b < kStage) S.buf[b] = v;
+    else S.q[atomicAdd(S.ctr, 1u)] = v;
+  }
+}
+
+template <int K>
+__device__ inline void stage_close(Stage (&S)[K]) {
+  __syncthreads();
+  if (threadIdx.x < K) {
+    Stage& t = S[threadIdx.x];
+    const uint32_t n = min(t.n, kStage);
+    t.base = n ? atomicAdd(t.ctr, n) : 0u;
+  }
+  __syncthreads();
+  for (int k = 0; k < K; ++k) {
+    const uint32_t n = min(S[k].n, kStage);
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) S[k].q[S[k].base + i] = S[k].buf[i];
+  }
+}
+
 // ----------------------------------------------------------------- memory access
 // Slab words are read with relaxed atomic loads of wavefront scope: ordinary cached
 // loads for the hardware, but the compiler may not merge or hoist them across the CASes

@@ -82,6 +82,27 @@ __device__ inline void push_routed(const uint32_t* nbk, const PushQ& Q, const Ro
   push_vertex(nbk, Q, mark, stamp, near, v);
 }
 
+// push_routed through block stages: [0..2] the light, heavy and giant queues of Q, [3] the
+// far pile of r (opened by open_routed).
+__device__ inline void open_routed(Stage (&S)[4], const PushQ& Q, const Route& r) {
+  for (int k = 0; k < 3; ++k) stage_open(S[k], Q.q[k], Q.c[k]);
+  stage_open(S[3], r.far, r.far_cnt);
+  __syncthreads();
+}
+
+__device__ inline void push_staged(Stage (&S)[4], const uint32_t* nbk, const Route& r, uint32_t T,
+                                   uint32_t* mark, uint32_t stamp, bool p, uint32_t v, uint32_t dist) {
+  const bool near = p && dist < T;
+  bool take = false, take_far = false;
+  if (near) take = atomicExch(mark + v, stamp) != stamp;
+  else if (p) take_far = atomicExch(r.far_mark + v, r.band) != r.band;
+  const uint32_t nb = take ? nbk[v] : 0u;
+  stage_push(S[3], take_far, v);
+  stage_push(S[0], take && nb <= kHeavyBuckets, v);
+  stage_push(S[1], take && nb > kHeavyBuckets && nb <= kGiantBuckets, v);
+  stage_push(S[2], take && nb > kGiantBuckets, v);
+}
+
 struct Queues {
   const uint32_t* cur[3];  // light, heavy, giant
   PushQ next;
@@ -309,6 +330,8 @@ __global__ void k_seed_source(DView F, uint32_t src, PushQ Q, Route r, uint32_t*
 template <bool kUnit>
 __global__ void k_relax_batch(DView F, uint64_t* D, Log lg, uint64_t n, PushQ Q, Route r, uint32_t* mark,
                               uint32_t stamp) {
+  __shared__ Stage S[4];
+  open_routed(S, Q, r);
   const uint32_t T = band_limit(r);
   // whole waves step together so that the wave-wide push sees every lane
   const uint64_t lane = threadIdx.x & 63;
@@ -328,13 +351,19 @@ __global__ void k_relax_batch(DView F, uint64_t* D, Log lg, uint64_t n, PushQ Q,
         if (cand < D[v]) improve = amin64(D + v, cand) > cand;
       }
     }
-    push_routed(F.nbk, Q, r, T, mark, stamp, improve, v, (uint32_t)(cand >> 32));
+    push_staged(S, F.nbk, r, T, mark, stamp, improve, v, (uint32_t)(cand >> 32));
   }
+  stage_close(S);
 }
 
 // Delete prologue, step 1: a deleted arc (u, v) of the dependence tree invalidates v.
 __global__ void k_invalidate(DView F, uint64_t* D, Log lg, uint64_t n, PushQ Q, uint32_t* inval,
-                             uint32_t* inval_cnt, uint32_t* mark, uint32_t stamp) {
+                             uint32_t* inval_cnt) {
+  // a vertex is cut by exactly one successful CAS, so it needs no frontier mark
+  __shared__ Stage S[4];
+  for (int k = 0; k < 3; ++k) stage_open(S[k], Q.q[k], Q.c[k]);
+  stage_open(S[3], inval, inval_cnt);
+  __syncthreads();
   const uint64_t lane = threadIdx.x & 63;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x - lane; base < n;
@@ -348,9 +377,13 @@ __global__ void k_invalidate(DView F, uint64_t* D, Log lg, uint64_t n, PushQ Q, 
       const uint64_t dv = ld_u64(D + v);
       if (dv != kTreeNone && (uint32_t)dv == u) hit = cas64(D + v, dv, kTreeNone) == dv;
     }
-    wave_push(inval, inval_cnt, hit, v);
-    push_vertex(F.nbk, Q, mark, stamp, hit, v);
+    const uint32_t nb = hit ? F.nbk[v] : 0u;
+    stage_push(S[3], hit, v);
+    stage_push(S[0], hit && nb <= kHeavyBuckets, v);
+    stage_push(S[1], hit && nb > kHeavyBuckets && nb <= kGiantBuckets, v);
+    stage_push(S[2], hit && nb > kGiantBuckets, v);
   }
+  stage_close(S);
 }
 
 // Delete prologue, step 2: invalidate the subtree below each invalidated vertex x (its
@@ -456,6 +489,8 @@ template <bool kUnit>
 __global__ void __launch_bounds__(kBlock) k_dec_pull(DView F, DView R, uint64_t* D,
                                                      const uint32_t* inval, const uint32_t* inval_cnt,
                                                      PushQ Q, Route r, uint32_t* mark, uint32_t stamp) {
+  __shared__ Stage S[4];
+  open_routed(S, Q, r);
   const uint32_t n = *inval_cnt;
   const uint32_t T = band_limit(r);
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
@@ -476,7 +511,7 @@ __global__ void __launch_bounds__(kBlock) k_dec_pull(DView F, DView R, uint64_t*
     }
     bool improve = false;
     if (best != kTreeNone) improve = amin64(D + y, best) > best;
-    push_routed(F.nbk, Q, r, T, mark, stamp, improve, y, (uint32_t)(best >> 32));
+    push_staged(S, F.nbk, r, T, mark, stamp, improve, y, (uint32_t)(best >> 32));
   }
   const uint32_t g0 = (blockIdx.x * kBlock + threadIdx.x) / kGroup;
   const uint32_t ng = gridDim.x * kGroupsPerBlock;
@@ -492,7 +527,7 @@ __global__ void __launch_bounds__(kBlock) k_dec_pull(DView F, DView R, uint64_t*
     best = gmin_u64(best);
     bool improve = false;
     if (glane() == 0 && best != kTreeNone) improve = amin64(D + y, best) > best;
-    push_routed(F.nbk, Q, r, T, mark, stamp, improve, y, (uint32_t)(best >> 32));
+    push_staged(S, F.nbk, r, T, mark, stamp, improve, y, (uint32_t)(best >> 32));
   }
   const uint32_t gib = threadIdx.x / kGroup;
   for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
@@ -506,8 +541,9 @@ __global__ void __launch_bounds__(kBlock) k_dec_pull(DView F, DView R, uint64_t*
     best = gmin_u64(best);
     bool improve = false;
     if (glane() == 0 && best != kTreeNone) improve = amin64(D + y, best) > best;
-    push_routed(F.nbk, Q, r, T, mark, stamp, improve, y, (uint32_t)(best >> 32));
+    push_staged(S, F.nbk, r, T, mark, stamp, improve, y, (uint32_t)(best >> 32));
   }
+  stage_close(S);
 }
 
 __global__ void k_fill_mark(uint32_t* mark, uint32_t nv) {
@@ -720,7 +756,7 @@ mk_status traverse(mk_graph* g, AlgoState& st, uint64_t* D, uint32_t source, uin
         Log lg = g->log;
         lg.s += b->off; lg.d += b->off; lg.w += b->off; lg.st += b->off; lg.uf += b->off;
         hipLaunchKernelGGL(k_invalidate, dim3(blocks_for(b->n)), dim3(kBlock), 0, stream, F, D, lg, b->n,
-                           first_push(c), c.inval, c.inval_cnt, c.mark, stamp0);
+                           first_push(c), c.inval, c.inval_cnt);
       }
       MK_LAUNCH(g, "k_invalidate");
       mk_status s = run_frontier(g, c, stream, [&](Queues q, uint32_t stamp) {
