@@ -121,24 +121,6 @@ __device__ inline void wave_push(uint32_t* q, uint32_t* ctr, bool p, uint32_t v)
   if (p) q[base + lanes_below(m)] = v;
 }
 
-// Wave-aggregated reservation of `cnt` (0..15) slots per lane: one atomic per wave; the
-// exclusive prefix over the active lanes comes from one ballot per bit of the count, so
-// inactive lanes never contribute.  Returns this lane's first slot.
-__device__ inline uint32_t wave_reserve(uint32_t* ctr, uint32_t cnt) {
-  uint32_t excl = 0, total = 0;
-#pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    const uint64_t m = __ballot((cnt >> b) & 1u);
-    excl += lanes_below(m) << b;
-    total += (uint32_t)__popcll(m) << b;
-  }
-  if (total == 0) return 0;
-  const int leader = __builtin_ctzll(__ballot(true));
-  uint32_t base = 0;
-  if (lane64() == leader) base = atomicAdd(ctr, total);
-  return __shfl(base, leader) + excl;
-}
-
 // ----------------------------------------------------------------- block-staged appends
 // Appends to a queue whose counter would otherwise take one atomic per wave (sparse pushes
 // from many waves serialize on that one address) go to an LDS buffer per output, with one
@@ -162,17 +144,42 @@ __device__ inline void stage_open(Stage& S, uint32_t* q, uint32_t* ctr) {
   }
 }
 
-__device__ inline void stage_push(Stage& S, bool p, uint32_t v) {
-  const uint64_t m = __ballot(p);
-  if (m == 0) return;
-  const int leader = __builtin_ctzll(m);
-  uint32_t b = 0;
-  if (lane64() == leader) b = atomicAdd(&S.n, (uint32_t)__popcll(m));
-  b = __shfl(b, leader) + lanes_below(m);
-  if (p) {
-    if (b < kStage) S.buf[b] = v;
-    else S.q[atomicAdd(S.ctr, 1u)] = v;
+// Reserve `cnt` (0..15) staged slots per active lane: positions [pos, pos + cnt) of the
+// block's buffer, the part at or past kStage going straight to the output at
+// spill + (position - max(base, kStage)), with one global atomic per wave.
+struct StageSlots {
+  uint32_t pos, lo, spill;
+};
+__device__ inline StageSlots stage_reserve(Stage& S, uint32_t cnt, bool& any) {
+  uint32_t excl = 0, total = 0;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const uint64_t m = __ballot((cnt >> b) & 1u);
+    excl += lanes_below(m) << b;
+    total += (uint32_t)__popcll(m) << b;
   }
+  any = total != 0;
+  if (!any) return StageSlots{0, 0, 0};
+  const int leader = __builtin_ctzll(__ballot(true));
+  uint32_t base = 0;
+  if (lane64() == leader) base = atomicAdd(&S.n, total);
+  base = __shfl(base, leader);
+  const uint32_t lo = max(base, kStage);
+  uint32_t spill = 0;
+  if (base + total > kStage && lane64() == leader) spill = atomicAdd(S.ctr, base + total - lo);
+  spill = __shfl(spill, leader);
+  return StageSlots{base + excl, lo, spill};
+}
+
+__device__ inline void stage_put(Stage& S, const StageSlots& t, uint32_t pos, uint32_t v) {
+  if (pos < kStage) S.buf[pos] = v;
+  else S.q[t.spill + (pos - t.lo)] = v;
+}
+
+__device__ inline void stage_push(Stage& S, bool p, uint32_t v) {
+  bool any;
+  const StageSlots t = stage_reserve(S, p ? 1u : 0u, any);
+  if (p) stage_put(S, t, t.pos, v);
 }
 
 template <int K>

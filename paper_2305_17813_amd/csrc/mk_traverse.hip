@@ -110,14 +110,15 @@ struct Queues {
   int icur, iclear;
 };
 
-// Append the keys of the slab words selected by `mask` (bit j: word j) of every active lane
-// to q, with one counter atomic per wave.
-__device__ inline void push_words(uint32_t* q, uint32_t* ctr, uint32_t mask, const Slab& sl) {
-  if (__ballot(mask != 0) == 0) return;
-  uint32_t pos = wave_reserve(ctr, (uint32_t)__popc(mask));
+// Stage the keys of the slab words selected by `mask` (bit j: word j) of every active lane.
+__device__ inline void stage_words(Stage& S, uint32_t mask, const Slab& sl) {
+  bool any;
+  const StageSlots t = stage_reserve(S, (uint32_t)__popc(mask), any);
+  if (!any) return;
+  uint32_t pos = t.pos;
 #pragma unroll
   for (int j = 0; j < kKeysPerSlab; ++j)
-    if (mask >> j & 1) q[pos++] = (uint32_t)sl.w[j];
+    if (mask >> j & 1) stage_put(S, t, pos++, (uint32_t)sl.w[j]);
 }
 
 // Relax the 15 out-arcs of a whole slab held by one lane.  The distance loads, the atomic
@@ -125,7 +126,7 @@ __device__ inline void push_words(uint32_t* q, uint32_t* ctr, uint32_t mask, con
 // batch, and the pushes of the wave are appended with one counter atomic per queue.
 template <bool kUnit>
 __device__ inline void relax_slab_lane(const DView& F, uint64_t* D, uint32_t u, uint64_t du, const Slab& sl,
-                                       int nd, const Queues& q, const Route& r, uint32_t T, uint32_t* mark,
+                                       int nd, Stage (&S)[4], const Route& r, uint32_t T, uint32_t* mark,
                                        uint32_t stamp) {
   uint64_t cand[kKeysPerSlab], cur[kKeysPerSlab];
 #pragma unroll
@@ -168,23 +169,23 @@ __device__ inline void relax_slab_lane(const DView& F, uint64_t* D, uint32_t u, 
     if (tk[j] > kGiantBuckets) giant |= 1u << j;
     else if (tk[j] > kHeavyBuckets) heavy |= 1u << j;
   }
-  push_words(q.next.q[0], q.next.c[0], tn & ~(heavy | giant), sl);
-  push_words(q.next.q[1], q.next.c[1], heavy, sl);
-  push_words(q.next.q[2], q.next.c[2], giant, sl);
-  push_words(r.far, r.far_cnt, tf, sl);
+  stage_words(S[0], tn & ~(heavy | giant), sl);
+  stage_words(S[1], heavy, sl);
+  stage_words(S[2], giant, sl);
+  stage_words(S[3], tf, sl);
 }
 
 // Relax every arc in bucket b of u (nb buckets, extra head slabs from xb) with one lane.
 template <bool kUnit>
 __device__ inline void relax_bucket_lane(const DView& F, uint64_t* D, uint32_t u, uint64_t du, uint32_t b,
-                                         uint32_t nb, uint32_t xb, const Queues& q, const Route& r,
+                                         uint32_t nb, uint32_t xb, Stage (&S)[4], const Route& r,
                                          uint32_t T, uint32_t* mark, uint32_t stamp) {
   uint32_t t = b == 0 ? u : xb + b - 1;
   int nd = (b == 0 && nb > 1) ? kKeysPerSlab - 1 : kKeysPerSlab;
   Slab sl;
   while (true) {
     load_slab(F, t, sl);
-    relax_slab_lane<kUnit>(F, D, u, du, sl, nd, q, r, T, mark, stamp);
+    relax_slab_lane<kUnit>(F, D, u, du, sl, nd, S, r, T, mark, stamp);
     t = (uint32_t)sl.w[15];
     if (t == kInvalid) break;
     nd = kKeysPerSlab;
@@ -209,14 +210,16 @@ __global__ void __launch_bounds__(kBlock) k_expand(DView F, uint64_t* D, Queues 
                                                    uint32_t stamp) {
   const uint32_t nl = q.cnt[q.icur], nh = q.cnt[3 + q.icur], ngi = q.cnt[6 + q.icur];
   if (blockIdx.x == 0 && threadIdx.x < 3) q.cnt[3 * threadIdx.x + q.iclear] = 0;
-  if (nl == 0 && nh == 0 && ngi == 0) return;
+  if (nl == 0 && nh == 0 && ngi == 0) return;  // the same for the whole grid
+  __shared__ Stage S[4];
+  open_routed(S, q.next, r);
   const uint32_t T = band_limit(r);
   // single-bucket frontier vertices: one lane each (64 slab reads in flight per wave)
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nl; i += gridDim.x * blockDim.x) {
     const uint32_t u = q.cur[0][i];
     if (F.nbk[u] != 1) continue;
     const uint64_t du = ld_u64(D + u) >> 32;
-    relax_bucket_lane<kUnit>(F, D, u, du, 0, 1, 0, q, r, T, mark, stamp);
+    relax_bucket_lane<kUnit>(F, D, u, du, 0, 1, 0, S, r, T, mark, stamp);
   }
   const uint32_t g0 = (blockIdx.x * kBlock + threadIdx.x) / kGroup;
   const uint32_t ng = gridDim.x * kGroupsPerBlock;
@@ -225,7 +228,7 @@ __global__ void __launch_bounds__(kBlock) k_expand(DView F, uint64_t* D, Queues 
     const uint32_t nb = F.nbk[u];
     if (nb == 1 || (uint32_t)glane() >= nb) continue;
     const uint64_t du = ld_u64(D + u) >> 32;
-    relax_bucket_lane<kUnit>(F, D, u, du, glane(), nb, extra_base(F, u), q, r, T, mark, stamp);
+    relax_bucket_lane<kUnit>(F, D, u, du, glane(), nb, extra_base(F, u), S, r, T, mark, stamp);
   }
   for (uint32_t j = blockIdx.x; j < nh; j += gridDim.x) {
     const uint32_t u = q.cur[1][j];
@@ -233,7 +236,7 @@ __global__ void __launch_bounds__(kBlock) k_expand(DView F, uint64_t* D, Queues 
     const uint64_t du = ld_u64(D + u) >> 32;
     const uint32_t xb = extra_base(F, u);
     for (uint32_t b = threadIdx.x; b < nb; b += kBlock)
-      relax_bucket_lane<kUnit>(F, D, u, du, b, nb, xb, q, r, T, mark, stamp);
+      relax_bucket_lane<kUnit>(F, D, u, du, b, nb, xb, S, r, T, mark, stamp);
   }
   const uint32_t nthreads = gridDim.x * kBlock;
   for (uint32_t it = blockIdx.x * kBlock + threadIdx.x; it < ngi * kGiantLanes; it += nthreads) {
@@ -242,8 +245,9 @@ __global__ void __launch_bounds__(kBlock) k_expand(DView F, uint64_t* D, Queues 
     const uint64_t du = ld_u64(D + u) >> 32;
     const uint32_t xb = extra_base(F, u);
     for (uint32_t b = it % kGiantLanes; b < nb; b += kGiantLanes)
-      relax_bucket_lane<kUnit>(F, D, u, du, b, nb, xb, q, r, T, mark, stamp);
+      relax_bucket_lane<kUnit>(F, D, u, du, b, nb, xb, S, r, T, mark, stamp);
   }
+  stage_close(S);
 }
 
 // Band step, part 1: reset the pile minimum and the size of the pile about to be filled.
@@ -356,6 +360,16 @@ __global__ void k_relax_batch(DView F, uint64_t* D, Log lg, uint64_t n, PushQ Q,
   stage_close(S);
 }
 
+// A vertex cut from the tree (by exactly one successful CAS, so it needs no frontier
+// mark) is staged to [3] the invalidated list and [0..2] the light, heavy or giant queue.
+__device__ inline void stage_cut(Stage (&S)[4], const uint32_t* nbk, bool hit, uint32_t y) {
+  const uint32_t nb = hit ? nbk[y] : 0u;
+  stage_push(S[3], hit, y);
+  stage_push(S[0], hit && nb <= kHeavyBuckets, y);
+  stage_push(S[1], hit && nb > kHeavyBuckets && nb <= kGiantBuckets, y);
+  stage_push(S[2], hit && nb > kGiantBuckets, y);
+}
+
 // Delete prologue, step 1: a deleted arc (u, v) of the dependence tree invalidates v.
 __global__ void k_invalidate(DView F, uint64_t* D, Log lg, uint64_t n, PushQ Q, uint32_t* inval,
                              uint32_t* inval_cnt) {
@@ -377,11 +391,7 @@ __global__ void k_invalidate(DView F, uint64_t* D, Log lg, uint64_t n, PushQ Q, 
       const uint64_t dv = ld_u64(D + v);
       if (dv != kTreeNone && (uint32_t)dv == u) hit = cas64(D + v, dv, kTreeNone) == dv;
     }
-    const uint32_t nb = hit ? F.nbk[v] : 0u;
-    stage_push(S[3], hit, v);
-    stage_push(S[0], hit && nb <= kHeavyBuckets, v);
-    stage_push(S[1], hit && nb > kHeavyBuckets && nb <= kGiantBuckets, v);
-    stage_push(S[2], hit && nb > kGiantBuckets, v);
+    stage_cut(S, F.nbk, hit, v);
   }
   stage_close(S);
 }
@@ -389,24 +399,25 @@ __global__ void k_invalidate(DView F, uint64_t* D, Log lg, uint64_t n, PushQ Q, 
 // Delete prologue, step 2: invalidate the subtree below each invalidated vertex x (its
 // tree children are the out-neighbours y whose parent is x).
 __device__ inline void inval_word(const DView& F, uint64_t* D, uint32_t x_parent, uint64_t w,
-                                  bool data, const Queues& q, uint32_t* inval, uint32_t* inval_cnt,
-                                  uint32_t* mark, uint32_t stamp) {
+                                  bool data, Stage (&S)[4]) {
   const uint32_t y = (uint32_t)w;
   bool hit = false;
   if (data && valid_key(y)) {
     const uint64_t dy = ld_u64(D + y);
     if (dy != kTreeNone && (uint32_t)dy == x_parent) hit = cas64(D + y, dy, kTreeNone) == dy;
   }
-  wave_push(inval, inval_cnt, hit, y);
-  push_vertex(F.nbk, q.next, mark, stamp, hit, y);
+  stage_cut(S, F.nbk, hit, y);
 }
 
 __global__ void __launch_bounds__(kBlock) k_propagate(DView F, uint64_t* D, Queues q, uint32_t* inval,
-                                                      uint32_t* inval_cnt, uint32_t* mark,
-                                                      uint32_t stamp) {
+                                                      uint32_t* inval_cnt) {
   const uint32_t nl = q.cnt[q.icur], nh = q.cnt[3 + q.icur], ngi = q.cnt[6 + q.icur];
   if (blockIdx.x == 0 && threadIdx.x < 3) q.cnt[3 * threadIdx.x + q.iclear] = 0;
-  if (nl == 0 && nh == 0 && ngi == 0) return;
+  if (nl == 0 && nh == 0 && ngi == 0) return;  // the same for the whole grid
+  __shared__ Stage S[4];
+  for (int k = 0; k < 3; ++k) stage_open(S[k], q.next.q[k], q.next.c[k]);
+  stage_open(S[3], inval, inval_cnt);
+  __syncthreads();
   // single-bucket vertices: one lane each; the child tests of a slab are issued together
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nl; i += gridDim.x * blockDim.x) {
     const uint32_t x = q.cur[0][i];
@@ -431,7 +442,6 @@ __global__ void __launch_bounds__(kBlock) k_propagate(DView F, uint64_t* D, Queu
 #pragma unroll
       for (int j = 0; j < kKeysPerSlab; ++j)
         if (dy[j] == 0) cut |= 1u << j;
-      // a cut vertex is new to the invalidated set, so it needs no frontier mark
       uint32_t heavy = 0, giant = 0;
 #pragma unroll
       for (int j = 0; j < kKeysPerSlab; ++j) {
@@ -439,10 +449,10 @@ __global__ void __launch_bounds__(kBlock) k_propagate(DView F, uint64_t* D, Queu
         if (nb > kGiantBuckets) giant |= 1u << j;
         else if (nb > kHeavyBuckets) heavy |= 1u << j;
       }
-      push_words(inval, inval_cnt, cut, sl);
-      push_words(q.next.q[0], q.next.c[0], cut & ~(heavy | giant), sl);
-      push_words(q.next.q[1], q.next.c[1], heavy, sl);
-      push_words(q.next.q[2], q.next.c[2], giant, sl);
+      stage_words(S[3], cut, sl);
+      stage_words(S[0], cut & ~(heavy | giant), sl);
+      stage_words(S[1], heavy, sl);
+      stage_words(S[2], giant, sl);
       t = (uint32_t)sl.w[15];
       if (t == kInvalid) break;
     }
@@ -452,23 +462,22 @@ __global__ void __launch_bounds__(kBlock) k_propagate(DView F, uint64_t* D, Queu
   for (uint32_t i = g0; i < nl; i += ng) {
     const uint32_t x = q.cur[0][i];
     if (F.nbk[x] == 1) continue;
-    for_each_slab(F, x, [&](uint64_t w, bool data) {
-      inval_word(F, D, x, w, data, q, inval, inval_cnt, mark, stamp);
-    });
+    for_each_slab(F, x, [&](uint64_t w, bool data) { inval_word(F, D, x, w, data, S); });
   }
   const uint32_t gib = threadIdx.x / kGroup;
   for (uint32_t j = blockIdx.x; j < nh; j += gridDim.x) {
     const uint32_t x = q.cur[1][j];
     for_each_slab_strided(F, x, gib, kGroupsPerBlock, [&](uint64_t w, bool data) {
-      inval_word(F, D, x, w, data, q, inval, inval_cnt, mark, stamp);
+      inval_word(F, D, x, w, data, S);
     });
   }
   for (uint32_t it = g0; it < ngi * kGiantSplit; it += ng) {
     const uint32_t x = q.cur[2][it / kGiantSplit];
     for_each_slab_strided(F, x, it % kGiantSplit, kGiantSplit, [&](uint64_t w, bool data) {
-      inval_word(F, D, x, w, data, q, inval, inval_cnt, mark, stamp);
+      inval_word(F, D, x, w, data, S);
     });
   }
+  stage_close(S);
 }
 
 // Delete prologue, step 3: each invalidated vertex takes the best candidate offered by
@@ -761,7 +770,7 @@ mk_status traverse(mk_graph* g, AlgoState& st, uint64_t* D, uint32_t source, uin
       MK_LAUNCH(g, "k_invalidate");
       mk_status s = run_frontier(g, c, stream, [&](Queues q, uint32_t stamp) {
         hipLaunchKernelGGL(k_propagate, dim3(kExpandBlocks), dim3(kBlock), 0, stream, F, D, q, c.inval,
-                           c.inval_cnt, c.mark, stamp);
+                           c.inval_cnt);
       });
       if (s != MK_OK) return s;
       hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, stream, c.cnt, nullptr);
