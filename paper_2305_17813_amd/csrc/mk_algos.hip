@@ -18,6 +18,8 @@ using namespace mk;
 namespace {
 
 constexpr uint32_t kWalkBlocks = 4096;
+constexpr uint32_t kPrContribBlocks = 2048, kPrFinalBlocks = 512;
+static_assert(kPrContribBlocks + kWalkBlocks + kPrFinalBlocks <= kPrParts, "PageRank partial sums");
 constexpr uint32_t kPrChunk = 4;  // buckets per heavy-vertex work item
 constexpr int kPrSyncEvery = 4;
 
@@ -164,7 +166,7 @@ __global__ void k_pr_fill(float* x, uint32_t nv, float v) {
 __global__ void __launch_bounds__(kBlock) k_pr_contrib(const float* __restrict__ x,
                                                        const uint32_t* __restrict__ outdeg,
                                                        float* __restrict__ c, uint32_t nv,
-                                                       double* dang, const uint32_t* state) {
+                                                       double* dpart, const uint32_t* state) {
   __shared__ double lds[kBlock / 64];
   if (state[0]) return;
   double local = 0;
@@ -175,7 +177,23 @@ __global__ void __launch_bounds__(kBlock) k_pr_contrib(const float* __restrict__
     if (!o) local += xv;
   }
   const double s = block_sum(local, lds);
-  if (threadIdx.x == 0 && s != 0.0) atomicAdd(dang, s);
+  if (threadIdx.x == 0) dpart[blockIdx.x] = s;
+}
+
+// Sum of per-block partial sums in a fixed order (one block): every FP64 reduction of an
+// iteration is deterministic and takes no same-address atomics.
+__device__ inline double sum_parts(const double* part, uint32_t n, double* lds) {
+  double v = 0;
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) v += part[i];
+  return block_sum(v, lds);
+}
+
+__global__ void __launch_bounds__(kBlock) k_pr_sum(const double* part, uint32_t n, double* out,
+                                                   const uint32_t* state) {
+  __shared__ double lds[kBlock / 64];
+  if (state[0]) return;
+  const double s = sum_parts(part, n, lds);
+  if (threadIdx.x == 0) *out = s;
 }
 
 // Pull over in-arcs (reverse view): PR'[v] = (1-d)/N + d * (sum C[u] + dangling/N),
@@ -256,7 +274,7 @@ __global__ void __launch_bounds__(kBlock) k_pr_gather(DView R, const float* __re
     }
   }
   const double s = block_sum(local, lds);
-  if (threadIdx.x == 0 && s != 0.0) atomicAdd(delta, s);
+  if (threadIdx.x == 0) delta[blockIdx.x] = s;
 }
 
 // Work items per heavy vertex: ceil(buckets / kPrChunk).
@@ -287,16 +305,19 @@ __global__ void __launch_bounds__(kBlock) k_pr_heavy_final(const uint32_t* heavy
     local += fabs((double)nvl - (double)x[v]);
   }
   const double s = block_sum(local, lds);
-  if (threadIdx.x == 0 && s != 0.0) atomicAdd(delta, s);
+  if (threadIdx.x == 0) delta[blockIdx.x] = s;
 }
 
 // Convergence bookkeeping for one iteration (single thread): stop at delta <= tol, when
 // the change has not improved for three iterations (the FP32 noise floor), or at max_iter.
-__global__ void k_pr_check(Counters* C, int slot, double tol, uint32_t max_iter) {
-  if (threadIdx.x != 0) return;
+__global__ void __launch_bounds__(kBlock) k_pr_check(Counters* C, int slot, double tol, uint32_t max_iter,
+                                                     const double* dpart, uint32_t nparts) {
+  __shared__ double lds[kBlock / 64];
   uint32_t* st = C->pr_state;
   if (st[0]) return;
-  const double d = C->pr_acc[2 * slot + 1];
+  const double d = sum_parts(dpart, nparts, lds);  // the L1 change of this iteration
+  if (threadIdx.x != 0) return;
+  C->pr_acc[2 * slot + 1] = d;
   st[1] += 1;
   C->pr_last = d;
   if (d < C->pr_best * 0.999) {
@@ -306,9 +327,6 @@ __global__ void k_pr_check(Counters* C, int slot, double tol, uint32_t max_iter)
     st[2] += 1;
   }
   if (d <= tol || st[2] >= 3 || st[1] >= max_iter) st[0] = 1;
-  const int clr = (slot + 2) & 3;
-  C->pr_acc[2 * clr] = 0.0;
-  C->pr_acc[2 * clr + 1] = 0.0;
 }
 
 __global__ void k_pr_start(Counters* C) {
@@ -586,22 +604,27 @@ mk_status mk_incr_pagerank(mk_graph* g, float damping, double tol_l1, uint32_t m
   hipLaunchKernelGGL(k_pr_start, dim3(1), dim3(64), 0, stream, g->ctr);
   MK_LAUNCH(g, "pagerank setup");
   float* buf[2] = {g->pr_x, g->pr_y};
+  // per-block partial sums: the dangling mass (contribution blocks), then the L1 change
+  // (gather blocks, heavy-final blocks)
+  const uint32_t cb = blocks_for(N, kPrContribBlocks), hb = blocks_for(N, kPrFinalBlocks);
+  double* dpart = g->pr_part + kPrContribBlocks;
   uint32_t it = 0;
   while (true) {
     for (int k = 0; k < kPrSyncEvery; ++k, ++it) {
       const int slot = it & 3;
       const float* x = buf[it & 1];
       float* y = buf[(it + 1) & 1];
-      hipLaunchKernelGGL(k_pr_contrib, dim3(blocks_for(N, 2048)), dim3(kBlock), 0, stream, x,
-                         g->view[VF].d.deg, g->pr_c, N, &g->ctr->pr_acc[2 * slot], g->ctr->pr_state);
+      double* dang = &g->ctr->pr_acc[2 * slot];
+      hipLaunchKernelGGL(k_pr_contrib, dim3(cb), dim3(kBlock), 0, stream, x, g->view[VF].d.deg, g->pr_c,
+                         N, g->pr_part, g->ctr->pr_state);
+      hipLaunchKernelGGL(k_pr_sum, dim3(1), dim3(kBlock), 0, stream, g->pr_part, cb, dang, g->ctr->pr_state);
       hipLaunchKernelGGL(k_pr_gather, dim3(kWalkBlocks), dim3(kBlock), 0, stream, g->view[VR].d,
-                         g->pr_c, x, y, N, damping, &g->ctr->pr_acc[2 * slot],
-                         &g->ctr->pr_acc[2 * slot + 1], g->heavy_rev, nh, hcnt, hoff, hacc,
+                         g->pr_c, x, y, N, damping, dang, dpart, g->heavy_rev, nh, hcnt, hoff, hacc,
                          g->ctr->pr_state);
-      hipLaunchKernelGGL(k_pr_heavy_final, dim3(blocks_for(N, 512)), dim3(kBlock), 0, stream, g->heavy_rev,
-                         nh, hacc, x, y, N, damping, &g->ctr->pr_acc[2 * slot],
-                         &g->ctr->pr_acc[2 * slot + 1], g->ctr->pr_state);
-      hipLaunchKernelGGL(k_pr_check, dim3(1), dim3(64), 0, stream, g->ctr, slot, tol_l1, max_iter);
+      hipLaunchKernelGGL(k_pr_heavy_final, dim3(hb), dim3(kBlock), 0, stream, g->heavy_rev, nh, hacc, x, y,
+                         N, damping, dang, dpart + kWalkBlocks, g->ctr->pr_state);
+      hipLaunchKernelGGL(k_pr_check, dim3(1), dim3(kBlock), 0, stream, g->ctr, slot, tol_l1, max_iter, dpart,
+                         kWalkBlocks + hb);
       MK_LAUNCH(g, "pagerank iteration");
     }
     MK_HIP(g, hipMemcpyAsync(g->h_pin, g->ctr->pr_state, 8, hipMemcpyDeviceToHost, stream));

@@ -680,6 +680,7 @@ bool layout(const mk_config* c, uint64_t m, char* base, mk_graph* g, size_t* tot
   float* pc = cv.take<float>(N);
   uint32_t* hv = cv.take<uint32_t>(N);
   double* hacc = cv.take<double>(N);
+  double* prp = cv.take<double>(kPrParts);
   uint64_t* tk0 = nullptr;
   uint64_t* tk1 = nullptr;
   size_t sort_bytes = 0, scan_bytes = 0;
@@ -713,6 +714,7 @@ bool layout(const mk_config* c, uint64_t m, char* base, mk_graph* g, size_t* tot
     g->pr_c = pc;
     g->heavy_rev = hv;
     g->pr_hacc = hacc;
+    g->pr_part = prp;
     g->tc_keys[0] = tk0;
     g->tc_keys[1] = tk1;
     g->sort_tmp = sort_tmp;

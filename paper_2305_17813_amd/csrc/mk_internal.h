@@ -11,6 +11,7 @@ namespace mk {
 
 enum { VF = 0, VR = 1, VU = 2 };
 constexpr uint32_t kSlots = 16;  // concurrent one-off traversals (distinct streams)
+constexpr uint32_t kPrParts = 8192;  // FP64 partial sums of one PageRank iteration
 enum BatchKind { kInsertBatch = 0, kDeleteBatch = 1 };
 
 // One applied update batch, remembered for the incremental algorithms.  Its ops live in
@@ -96,6 +97,7 @@ struct mk_graph {
   float* pr_c = nullptr;      // contribution per vertex
   uint32_t* heavy_rev = nullptr;  // rev-view vertices split into bucket work items
   double* pr_hacc = nullptr;      // FP64 partial sums of the heavy vertices
+  double* pr_part = nullptr;      // FP64 per-block partial sums of one iteration (kPrParts)
   uint32_t n_heavy_rev = 0;
   bool heavy_rev_ok = false;
 
