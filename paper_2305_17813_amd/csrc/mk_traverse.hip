@@ -214,38 +214,108 @@ __global__ void __launch_bounds__(kBlock) k_expand(DView F, uint64_t* D, Queues 
   __shared__ Stage S[4];
   open_routed(S, q.next, r);
   const uint32_t T = band_limit(r);
-  // single-bucket frontier vertices: one lane each (64 slab reads in flight per wave)
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nl; i += gridDim.x * blockDim.x) {
-    const uint32_t u = q.cur[0][i];
-    if (F.nbk[u] != 1) continue;
-    const uint64_t du = ld_u64(D + u) >> 32;
-    relax_bucket_lane<kUnit>(F, D, u, du, 0, 1, 0, S, r, T, mark, stamp);
-  }
-  const uint32_t g0 = (blockIdx.x * kBlock + threadIdx.x) / kGroup;
+  const uint32_t gtid = blockIdx.x * kBlock + threadIdx.x, nthreads = gridDim.x * kBlock;
   const uint32_t ng = gridDim.x * kGroupsPerBlock;
-  for (uint32_t i = g0; i < nl; i += ng) {
-    const uint32_t u = q.cur[0][i];
-    const uint32_t nb = F.nbk[u];
-    if (nb == 1 || (uint32_t)glane() >= nb) continue;
-    const uint64_t du = ld_u64(D + u) >> 32;
-    relax_bucket_lane<kUnit>(F, D, u, du, glane(), nb, extra_base(F, u), S, r, T, mark, stamp);
+  if constexpr (kUnit) {  // one loop per path
+    for (uint32_t i = gtid; i < nl; i += nthreads) {
+      const uint32_t u = q.cur[0][i];
+      if (F.nbk[u] != 1) continue;
+      relax_bucket_lane<kUnit>(F, D, u, ld_u64(D + u) >> 32, 0, 1, 0, S, r, T, mark, stamp);
+    }
+    for (uint32_t i = gtid / kGroup; i < nl; i += ng) {
+      const uint32_t u = q.cur[0][i];
+      const uint32_t nb = F.nbk[u];
+      if (nb == 1 || (uint32_t)glane() >= nb) continue;
+      relax_bucket_lane<kUnit>(F, D, u, ld_u64(D + u) >> 32, glane(), nb, extra_base(F, u), S, r, T, mark,
+                               stamp);
+    }
+    for (uint32_t j = blockIdx.x; j < nh; j += gridDim.x) {
+      const uint32_t u = q.cur[1][j];
+      const uint32_t nb = F.nbk[u];
+      const uint64_t du = ld_u64(D + u) >> 32;
+      const uint32_t xb = extra_base(F, u);
+      for (uint32_t b = threadIdx.x; b < nb; b += kBlock)
+        relax_bucket_lane<kUnit>(F, D, u, du, b, nb, xb, S, r, T, mark, stamp);
+    }
+    for (uint32_t it = gtid; it < ngi * kGiantLanes; it += nthreads) {
+      const uint32_t u = q.cur[2][it / kGiantLanes];
+      const uint32_t nb = F.nbk[u];
+      const uint64_t du = ld_u64(D + u) >> 32;
+      const uint32_t xb = extra_base(F, u);
+      for (uint32_t b = it % kGiantLanes; b < nb; b += kGiantLanes)
+        relax_bucket_lane<kUnit>(F, D, u, du, b, nb, xb, S, r, T, mark, stamp);
+    }
+    stage_close(S);
+    return;
   }
-  for (uint32_t j = blockIdx.x; j < nh; j += gridDim.x) {
-    const uint32_t u = q.cur[1][j];
-    const uint32_t nb = F.nbk[u];
+  // Weighted: each thread walks its (vertex, bucket) work items of the four paths in turn
+  // through a single relaxation call site.  Four inlined copies of the weighted relaxation
+  // need 150 VGPRs (three waves per SIMD), one needs 92 (five).  Lanes in different paths
+  // still relax together.
+  int path = 0;       // 0 single-bucket, 1 group, 2 heavy, 3 giant, 4 done
+  uint32_t i = gtid;  // item index within the path
+  uint32_t b = 0;     // next bucket of the current heavy / giant vertex
+  while (path < 4) {
+    uint32_t u = 0, nb = 1, bk = 0;
+    bool have = false;
+    if (path == 0) {  // one lane per single-bucket vertex
+      if (i < nl) {
+        u = q.cur[0][i];
+        i += nthreads;
+        nb = F.nbk[u];
+        have = nb == 1;
+      } else {
+        path = 1;
+        i = gtid / kGroup;
+      }
+    } else if (path == 1) {  // 2 .. kHeavyBuckets buckets: a 16-lane group, a lane per bucket
+      if (i < nl) {
+        u = q.cur[0][i];
+        i += ng;
+        nb = F.nbk[u];
+        bk = (uint32_t)glane();
+        have = nb > 1 && bk < nb;
+      } else {
+        path = 2;
+        i = blockIdx.x;
+        b = threadIdx.x;
+      }
+    } else if (path == 2) {  // heavy: a block per vertex, a lane per bucket
+      if (i < nh) {
+        u = q.cur[1][i];
+        nb = F.nbk[u];
+        if (b < nb) {
+          bk = b;
+          b += kBlock;
+          have = true;
+        } else {
+          i += gridDim.x;
+          b = threadIdx.x;
+        }
+      } else {
+        path = 3;
+        i = gtid;
+        b = gtid % kGiantLanes;
+      }
+    } else {  // giant: kGiantLanes lanes per vertex
+      if (i < ngi * kGiantLanes) {
+        u = q.cur[2][i / kGiantLanes];
+        nb = F.nbk[u];
+        if (b < nb) {
+          bk = b;
+          b += kGiantLanes;
+          have = true;
+        } else {
+          i += nthreads;
+          b = i % kGiantLanes;
+        }
+      } else {
+        path = 4;
+      }
+    }
+    if (!have) continue;
     const uint64_t du = ld_u64(D + u) >> 32;
-    const uint32_t xb = extra_base(F, u);
-    for (uint32_t b = threadIdx.x; b < nb; b += kBlock)
-      relax_bucket_lane<kUnit>(F, D, u, du, b, nb, xb, S, r, T, mark, stamp);
-  }
-  const uint32_t nthreads = gridDim.x * kBlock;
-  for (uint32_t it = blockIdx.x * kBlock + threadIdx.x; it < ngi * kGiantLanes; it += nthreads) {
-    const uint32_t u = q.cur[2][it / kGiantLanes];
-    const uint32_t nb = F.nbk[u];
-    const uint64_t du = ld_u64(D + u) >> 32;
-    const uint32_t xb = extra_base(F, u);
-    for (uint32_t b = it % kGiantLanes; b < nb; b += kGiantLanes)
-      relax_bucket_lane<kUnit>(F, D, u, du, b, nb, xb, S, r, T, mark, stamp);
+    relax_bucket_lane<kUnit>(F, D, u, du, bk, nb, nb > 1 ? extra_base(F, u) : 0u, S, r, T, mark, stamp);
   }
   stage_close(S);
 }
