@@ -425,12 +425,28 @@ __device__ inline uint64_t lower_bound_u64(const uint64_t* a, uint64_t n, uint64
   return lo;
 }
 
+// Where each source's arcs start and end in the sorted batch keys (every vertex of a batch
+// arc is the source of the reverse arc too, so both ends of an arc have a segment).
+__global__ void k_tc_segs(const uint64_t* keys, uint64_t nk, uint32_t nv, uint32_t* seg_lo, uint32_t* seg_hi) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nk;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t src = (uint32_t)(keys[i] >> 32);
+    if (src >= nv) continue;  // sentinels sort last
+    if (i == 0 || (uint32_t)(keys[i - 1] >> 32) != src) seg_lo[src] = (uint32_t)i;
+    if (i + 1 == nk || (uint32_t)(keys[i + 1] >> 32) != src) seg_hi[src] = (uint32_t)(i + 1);
+  }
+}
+
 // S1, S2 and S3 of the batch identity, one group per batch arc (u, v):
 //   S1 += |N_G(u) & N_G(v)|, S2 += |N_G(u) & N_B(v)|, S3 += |N_B(u) & N_B(v)|
 // with G the graph after the batch and B the graph of the batch alone.
 __global__ void __launch_bounds__(kBlock) k_tc_batch(DView U, const uint64_t* keys, uint64_t nk,
+                                                     const uint32_t* seg_lo, const uint32_t* seg_hi,
                                                      uint32_t nv, unsigned long long* S,
                                                      uint32_t* heavy, uint32_t* nheavy) {
+  __shared__ Stage H[1];  // batch arcs left to k_tc_heavy_s1
+  stage_open(H[0], heavy, nheavy);
+  __syncthreads();
   const uint64_t g0 = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kGroup;
   const uint64_t ng = (uint64_t)gridDim.x * kGroupsPerBlock;
   uint64_t s1 = 0, s2 = 0, s3 = 0;
@@ -450,12 +466,10 @@ __global__ void __launch_bounds__(kBlock) k_tc_batch(DView U, const uint64_t* ke
       split = U.nbk[a] > kHeavyBuckets;
       if (!split) c1 = 2 * group_intersect(U, a, u_small ? v : u);
     }
-    wave_push(heavy, nheavy, split && gl == 0, (uint32_t)i);
-    // batch neighbourhoods from the sorted key list
-    const uint64_t vlo = lower_bound_u64(keys, nk, (uint64_t)v << 32);
-    const uint64_t vhi = lower_bound_u64(keys, nk, ((uint64_t)v + 1) << 32);
-    const uint64_t ulo = lower_bound_u64(keys, nk, (uint64_t)u << 32);
-    const uint64_t uhi = lower_bound_u64(keys, nk, ((uint64_t)u + 1) << 32);
+    stage_push(H[0], split && gl == 0, (uint32_t)i);
+    // batch neighbourhoods: the segments of v and u in the sorted key list
+    const uint64_t vlo = seg_lo[v], vhi = seg_hi[v];
+    const uint64_t ulo = seg_lo[u], uhi = seg_hi[u];
     uint64_t c2 = 0, c3 = 0;
     const Table tu = group_table(U, u);
     for (uint64_t j = vlo + gl; j < vhi; j += kGroup) {
@@ -481,6 +495,7 @@ __global__ void __launch_bounds__(kBlock) k_tc_batch(DView U, const uint64_t* ke
     if (s2) atomicAdd(S + 1, (unsigned long long)s2);
     if (s3) atomicAdd(S + 2, (unsigned long long)s3);
   }
+  stage_close(H);
 }
 
 // S1 of the batch arcs whose smaller side has many buckets: kTcSplit groups per arc, each
@@ -678,8 +693,12 @@ mk_status mk_count_triangles(mk_graph* g, uint64_t* d_count, mk_mode mode, hipSt
     uint32_t* hl = reinterpret_cast<uint32_t*>(g->tc_keys[0]);
     uint32_t* nhl = &g->ctr->pad0[4];
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, nhl, 1u);
+    // segment bounds per source vertex (scratch: two traversal queues, unused here)
+    hipLaunchKernelGGL(k_tc_segs, dim3(blocks_for(nk)), dim3(kBlock), 0, stream, g->tc_keys[1], nk, N,
+                       g->fq[4], g->fq[5]);
     hipLaunchKernelGGL(k_tc_batch, dim3(grid_for_groups(std::min<uint64_t>(nk, 1u << 20))),
-                       dim3(kBlock), 0, stream, U, g->tc_keys[1], nk, N, g->ctr->tc_s, hl, nhl);
+                       dim3(kBlock), 0, stream, U, g->tc_keys[1], nk, g->fq[4], g->fq[5], N, g->ctr->tc_s,
+                       hl, nhl);
     hipLaunchKernelGGL(k_tc_heavy_s1, dim3(kWalkBlocks), dim3(kBlock), 0, stream, U, g->tc_keys[1], hl, nhl,
                        g->ctr->tc_s);
     hipLaunchKernelGGL(k_tc_finish, dim3(1), dim3(64), 0, stream, g->ctr,
