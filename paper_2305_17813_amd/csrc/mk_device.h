@@ -226,24 +226,6 @@ __device__ inline uint64_t* slab_ptr(const DView& V, uint32_t s) {
   return V.slab + (uint64_t)s * kGroup;
 }
 
-// The first slab of the bucket of `key` in u's table, its data-word count, and this
-// lane's word of it (one access for single-bucket vertices, two otherwise).
-struct Head {
-  uint32_t s;
-  int nd;
-  uint64_t x;
-};
-__device__ inline Head head_of(const DView& V, uint32_t u, uint32_t key) {
-  const int gl = glane();
-  const uint64_t x = ld_word(slab_ptr(V, u) + gl);
-  const uint32_t nb = (uint32_t)(gbcast64(x, 15) >> 32);
-  if (nb <= 1) return Head{u, kKeysPerSlab, x};
-  const uint32_t b = bucket_of(key, nb, V.hash_a, V.hash_b);
-  if (b == 0) return Head{u, kKeysPerSlab - 1, x};
-  const uint32_t s = gbcast((uint32_t)x, 14) + b - 1;
-  return Head{s, kKeysPerSlab, ld_word(slab_ptr(V, s) + gl)};
-}
-
 // ----------------------------------------------------------------- slab iterator
 // Walk every slab of vertex v (all buckets, each chain to its end), calling
 // f(word, is_data) on the 16 lanes of the group for each slab.  This is the SlabIterator
@@ -306,25 +288,6 @@ __device__ inline void for_each_bucket_range(const DView& V, uint32_t v, uint32_
       const uint32_t s = xb + b - 1;
       walk_chain(V, s, ld_word(slab_ptr(V, s) + gl), kKeysPerSlab, f);
     }
-  }
-}
-
-// Group-cooperative membership probe (SearchEdge): walk only the hashed chain of `u`.
-// Returns the data word when found, or kEmptyWord when absent.
-__device__ inline uint64_t probe(const DView& V, uint32_t u, uint32_t key) {
-  Head h = head_of(V, u, key);
-  const int gl = glane();
-  uint64_t x = h.x;
-  int nd = h.nd;
-  while (true) {
-    const uint32_t k = (uint32_t)x;
-    const uint32_t hit = gballot(gl < nd && k == key);
-    if (hit) return gbcast64(x, __builtin_ctz(hit));
-    if (gballot(gl < nd && k == kEmptyKey)) return kEmptyWord;
-    const uint32_t s = gbcast(k, 15);
-    if (s == kInvalid) return kEmptyWord;
-    x = ld_word(slab_ptr(V, s) + gl);
-    nd = kKeysPerSlab;
   }
 }
 

@@ -49,17 +49,6 @@ struct PushQ {
   uint32_t* c[3];
 };
 
-__device__ inline void push_vertex(const uint32_t* nbk, const PushQ& Q, uint32_t* mark, uint32_t stamp,
-                                   bool p, uint32_t v) {
-  bool take = false;
-  if (p) take = atomicExch(mark + v, stamp) != stamp;
-  uint32_t nb = 0;
-  if (take) nb = nbk[v];
-  wave_push(Q.q[0], Q.c[0], take && nb <= kHeavyBuckets, v);
-  wave_push(Q.q[1], Q.c[1], take && nb > kHeavyBuckets && nb <= kGiantBuckets, v);
-  wave_push(Q.q[2], Q.c[2], take && nb > kGiantBuckets, v);
-}
-
 // Near-far routing of the weighted epilogue.  T == nullptr: every push is near.
 struct Route {
   const uint32_t* T;   // threshold of the current band
@@ -71,19 +60,10 @@ struct Route {
 
 __device__ inline uint32_t band_limit(const Route& r) { return r.T ? *r.T : 0xFFFFFFFFu; }
 
-// Push v, improved to distance `dist`, into the near queues when dist < T, else onto the
-// far pile (once per band).
-__device__ inline void push_routed(const uint32_t* nbk, const PushQ& Q, const Route& r, uint32_t T,
-                                   uint32_t* mark, uint32_t stamp, bool p, uint32_t v, uint32_t dist) {
-  const bool near = p && dist < T;
-  bool take_far = false;
-  if (p && !near) take_far = atomicExch(r.far_mark + v, r.band) != r.band;
-  wave_push(r.far, r.far_cnt, take_far, v);
-  push_vertex(nbk, Q, mark, stamp, near, v);
-}
 
-// push_routed through block stages: [0..2] the light, heavy and giant queues of Q, [3] the
-// far pile of r (opened by open_routed).
+// Routed pushes through block stages: a vertex improved to distance `dist` goes to the near
+// queues ([0..2] light, heavy, giant of Q) when dist < T, else onto the far pile of r ([3],
+// once per band); open_routed opens the four stages.
 __device__ inline void open_routed(Stage (&S)[4], const PushQ& Q, const Route& r) {
   for (int k = 0; k < 3; ++k) stage_open(S[k], Q.q[k], Q.c[k]);
   stage_open(S[3], r.far, r.far_cnt);
