@@ -208,6 +208,7 @@ def main():
         "i_fwd": G.probe_cost(1, 0, s, d), "i_rev": G.probe_cost(1, 1, s, d),
         "i_und": G.probe_cost(1, 2, s, d), "d_fwd": G.probe_cost(0, 0, ds, dd),
         "d_rev": G.probe_cost(0, 1, ds, dd), "d_und": G.probe_cost(0, 2, ds, dd),
+        "d_chk": G.probe_cost(0, 0, dd, ds),
         "q_fwd": G.probe_cost(0, 0, qs, qd),
     }
     evs = []
@@ -237,8 +238,10 @@ def main():
     # the status byte and the change-log record (14 B)
     q_bytes = Q * (8 + 8 + 1 + 4) + 128 * slabs["q_fwd"]
     i_bytes = B * (12 + 1 + 14 + 4 * (8 + 8 + 4)) + 128 * (slabs["i_fwd"] + slabs["i_rev"] + slabs["i_und"])
+    # a delete also leaves the undirected view only when the reverse arc is gone, which one
+    # forward probe per arc decides (8 B directory + its slabs)
     d_bytes = B * (8 + 1 + 14 + 2 * (8 + 8 + 4)) + 128 * (slabs["d_fwd"] + slabs["d_rev"]) \
-        + B * (8 + 2 * (8 + 8 + 4)) + 128 * slabs["d_und"]
+        + B * (8 + 2 * (8 + 8 + 4)) + 128 * slabs["d_und"] + B * 8 + 128 * slabs["d_chk"]
     ins_ms = med(times["insert"])
     q_ms = med(times["query"])
     del_ms = med(times["delete"])
