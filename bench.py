@@ -237,7 +237,8 @@ def main():
     # (128 B each), the CAS / tombstone word (8 B per view), degree counters (4 B per view),
     # the status byte and the change-log record (14 B)
     q_bytes = Q * (8 + 8 + 1 + 4) + 128 * slabs["q_fwd"]
-    i_bytes = B * (12 + 1 + 14 + 4 * (8 + 8 + 4)) + 128 * (slabs["i_fwd"] + slabs["i_rev"] + slabs["i_und"])
+    # (the views other than fwd read the applied op back from the change log: 13 B)
+    i_bytes = B * (12 + 1 + 14 + 13 + 4 * (8 + 8 + 4)) + 128 * (slabs["i_fwd"] + slabs["i_rev"] + slabs["i_und"])
     # a delete also leaves the undirected view only when the reverse arc is gone, which one
     # forward probe per arc decides (8 B directory + its slabs)
     d_bytes = B * (8 + 1 + 14 + 2 * (8 + 8 + 4)) + 128 * (slabs["d_fwd"] + slabs["d_rev"]) \
