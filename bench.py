@@ -233,16 +233,16 @@ def main():
     queries_per_s = Q * K / t_q
     med = lambda xs: float(np.median(xs))
 
-    # per op: read the op (8 or 12 B), directory entries (8 B per probe), the walked slabs
-    # (128 B each), the CAS / tombstone word (8 B per view), degree counters (4 B per view),
-    # the status byte and the change-log record (14 B)
-    q_bytes = Q * (8 + 8 + 1 + 4) + 128 * slabs["q_fwd"]
+    # per op: read the op (8 or 12 B), the walked slabs (128 B each; the head slab carries the
+    # bucket count, so there is no directory read), the CAS / tombstone word (8 B per view),
+    # degree counters (4 B per view), the status byte and the change-log record (14 B)
+    q_bytes = Q * (8 + 1 + 4) + 128 * slabs["q_fwd"]
     # (the views other than fwd read the applied op back from the change log: 13 B)
-    i_bytes = B * (12 + 1 + 14 + 13 + 4 * (8 + 8 + 4)) + 128 * (slabs["i_fwd"] + slabs["i_rev"] + slabs["i_und"])
+    i_bytes = B * (12 + 1 + 14 + 13 + 4 * (8 + 4)) + 128 * (slabs["i_fwd"] + slabs["i_rev"] + slabs["i_und"])
     # a delete also leaves the undirected view only when the reverse arc is gone, which one
-    # forward probe per arc decides (8 B directory + its slabs)
-    d_bytes = B * (8 + 1 + 14 + 2 * (8 + 8 + 4)) + 128 * (slabs["d_fwd"] + slabs["d_rev"]) \
-        + B * (8 + 2 * (8 + 8 + 4)) + 128 * slabs["d_und"] + B * 8 + 128 * slabs["d_chk"]
+    # forward probe per arc decides (its slabs)
+    d_bytes = B * (8 + 1 + 14 + 2 * (8 + 4)) + 128 * (slabs["d_fwd"] + slabs["d_rev"]) \
+        + B * (8 + 2 * (8 + 4)) + 128 * slabs["d_und"] + 128 * slabs["d_chk"]
     ins_ms = med(times["insert"])
     q_ms = med(times["query"])
     del_ms = med(times["delete"])
