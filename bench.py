@@ -163,8 +163,8 @@ def main():
     times = {p: [] for p in phases}
     pr_iters = []
 
-    def run_step(k, timed):
-        s, d, w, ds, dd, qs, qd = steps[k]
+    def run_step(k, timed, batches=None):
+        s, d, w, ds, dd, qs, qd = (batches or steps)[k]
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(phases) + 1)]
         ev[0].record(stream)
         G.insert_edges(s, d, w, status=False)
@@ -279,6 +279,25 @@ def main():
         r["frac"] = r["achieved"] / HBM_PEAK_GBS
 
     incr = {p: med(times[p]) for p in phases if p not in ("insert", "delete", "query")}
+
+    # smaller batches of the same workload (10K and 100K arcs), medians of 3 timed steps
+    by_batch = {}
+    for b2 in (10_000, 100_000):
+        small = []
+        for _ in range(4):
+            s, d, w = wl.insert_batch(b2)
+            ds, dd = wl.delete_batch(b2)
+            qs, qd = wl.query_batch(b2)
+            small.append(tuple(native.as_u32(x, dev) for x in (s, d, w, ds, dd, qs, qd)))
+        run_step(0, False, small)
+        tb = {p: [] for p in phases}
+        for k in range(1, 4):
+            ev, _ = run_step(k, True, small)
+            ev[-1].synchronize()
+            for i, p in enumerate(phases):
+                tb[p].append(ev[i].elapsed_time(ev[i + 1]))
+        by_batch[str(b2)] = {p: med(v) for p, v in tb.items()}
+    log(f"[bench] smaller batches: {by_batch}")
     result = {
         "metric": METRIC,
         "value": updates_per_s,
@@ -306,6 +325,7 @@ def main():
         "incr_sssp_ms_per_batch": (incr["sssp_i"] + incr["sssp_d"]) / 2,
         "incr_ms_per_batch": incr,
         "p90_ms_per_batch": {p: float(np.percentile(times[p], 90)) for p in phases},
+        "ms_by_batch_size": by_batch,
         "pagerank_iters": pr_iters,
         "build_s": build_s,
         "roofline": roof,
