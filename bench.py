@@ -84,6 +84,10 @@ def parse():
     ap.add_argument("--ablation", action="store_true",
                     help="hashing / load-factor ablation at R-MAT scale 22 (forward view): memory, "
                          "1M insert / delete / query, static BFS and PageRank per load factor")
+    ap.add_argument("--wcc-schemes", action="store_true",
+                    help="incremental-WCC scheme ablation (naive / SlabIterator / UpdateIterator / "
+                         "UpdateIterator + single bucket / change log) on R-MAT and the road-like "
+                         "grid, batches of 2K, 4K, 8K and 100K arcs")
     ap.add_argument("--serve-requests", type=int, default=600)
     ap.add_argument("--serve-rate", type=float, default=150.0, help="requests per second")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -111,6 +115,8 @@ def main():
         return grid_bench(args)
     if args.ablation:
         return ablation_bench(args)
+    if args.wcc_schemes:
+        return wcc_scheme_bench(args)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if args.calibrate_copy:
@@ -408,6 +414,67 @@ def ablation_bench(args):
     print(json.dumps({"metric": "hashing / load-factor ablation", "unit": "ms",
                       "config": {"workload": f"R-MAT scale {args.scale}, fwd + rev views, batches of {B}"},
                       "rows": rows}))
+
+
+def wcc_scheme_bench(args):
+    """The paper's incremental-WCC scheme comparison: on each graph (forward view), every
+    scheme starts from the same recomputed state and takes the same insert batches; each
+    scheme's incremental WCC after a batch is timed (median of 3 batches per size) and
+    reported with its speedup over the naive scheme."""
+    import numpy as np
+    import torch
+
+    from paper_2305_17813_amd import inputs as I
+    from paper_2305_17813_amd import native
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    variants = [("naive", native.WCC_NAIVE, 0.7), ("slab_iterator", native.WCC_SLAB, 0.7),
+                ("update_iterator", native.WCC_UPDATE, 0.7),
+                ("update_iterator_single_bucket", native.WCC_UPDATE, 0.0),
+                ("change_log", native.WCC_LOG, 0.7)]
+    sizes = (2000, 4000, 8000, 100000)
+    graphs = {f"R-MAT scale {args.scale}": lambda: I.rmat_s(args.scale, device=dev),
+              "grid 4096x4096": lambda: I.grid_graph(4096, 0x4D45524B + 2, device=dev)}
+    out = {}
+    for gname, make in graphs.items():
+        g = make()
+        res = {}
+        for vname, scheme, lf in variants:
+            G = native.Graph(g.n, g.src, g.dst, g.w, views=native.VIEW_FWD, load_factor=lf,
+                             log_capacity=1 << 21, device=dev)
+            stream = G.stream
+            G.wcc(native.RECOMPUTE, scheme=scheme)
+            wl = I.Workload(g, args.seed + 60)
+            row = {}
+            for B in sizes:
+                ts = []
+                for _ in range(3):
+                    s, d, w = (native.as_u32(x, dev) for x in wl.insert_batch(B))
+                    G.insert_edges(s, d, w, status=False)
+                    a = torch.cuda.Event(enable_timing=True)
+                    b = torch.cuda.Event(enable_timing=True)
+                    a.record(stream)
+                    G.wcc(native.INCR, scheme=scheme)
+                    b.record(stream)
+                    b.synchronize()
+                    ts.append(a.elapsed_time(b))
+                row[B] = float(np.median(ts))
+            res[vname] = row
+            log(f"[wcc-schemes] {gname} {vname}: {row}")
+            del G
+            torch.cuda.empty_cache()
+        naive = dict(res["naive"])
+        for vname in res:
+            res[vname] = {B: {"ms": res[vname][B], "speedup_vs_naive": naive[B] / res[vname][B]}
+                          for B in sizes}
+        out[gname] = res
+        del g
+        torch.cuda.empty_cache()
+    print(json.dumps({"metric": "incremental WCC ms per batch by scheme", "unit": "ms",
+                      "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+                      "config": {"workload": "insert batches of 2K/4K/8K/100K arcs, forward view"},
+                      "rows": out}))
 
 
 def grid_bench(args):

@@ -166,6 +166,29 @@ mk_status mk_traverse_from(mk_graph* g, uint32_t source, int weighted, void* d_w
  *   d_label : N uint32 (device): the smallest vertex id of the component. */
 mk_status mk_incr_wcc(mk_graph* g, uint32_t* d_label, mk_mode mode, hipStream_t stream);
 
+/* How incremental WCC finds the arcs to unite (the incremental-WCC schemes that section 5
+ * compares in its table of speedups over the naive scheme).  Every scheme gives the same
+ * labels; they differ only in the slabs they read. */
+typedef enum {
+  MK_WCC_LOG = 0,    /* the arcs the pending insert batches logged as applied (no slab is
+                        read; the default of mk_incr_wcc)                                   */
+  MK_WCC_NAIVE = 1,  /* every arc of the graph: all slab lists of all vertices             */
+  MK_WCC_SLAB = 2,   /* SlabIterator: all slabs of each vertex that gained out-arcs        */
+  MK_WCC_UPDATE = 3  /* UpdateIterator (section 3.4): of those vertices, only the words past
+                        each chain's update mark; the pass then moves the marks to the
+                        chains' ends (the paper's UpdateSlabPointers)                        */
+} mk_wcc_scheme;
+
+/* mk_incr_wcc with an explicit scheme.  Update marks are kept for the forward view, one
+ * per bucket chain: <slab, lane> of the first word not yet united.  They start at each
+ * chain's head, move only in MK_WCC_UPDATE passes (and in recomputes run with that
+ * scheme, which set every mark to its chain's end), and mk_compact resets the marks of
+ * the chains it rewrites to their heads.  A lagging mark only makes the pass read more.
+ * With hashing off (load_factor 0) every vertex has a single chain: the paper's
+ * "UpdateIterator + single bucket" variant.  MK_ERR_INVALID_ARG for an unknown scheme. */
+mk_status mk_incr_wcc_scheme(mk_graph* g, uint32_t* d_label, mk_mode mode, mk_wcc_scheme scheme,
+                             hipStream_t stream);
+
 /* PageRank (section 4.1): PR'(v) = (1-d)/N + d * (sum over in-arcs u->v of PR(u)/out(u)
  * + sum over zero-out-degree z of PR(z)/N), iterated from 1/N (first call, RECOMPUTE) or
  * from the previous vector (incremental and decremental batches) until the L1 change of
@@ -194,8 +217,9 @@ mk_status mk_graph_export(mk_graph* g, uint32_t* d_src, uint32_t* d_dst, uint32_
  * `min_tombstones` tombstones (0 is taken as 1) is rewritten with its live arcs packed from
  * its head slab, EMPTY lanes after them, and the chain cut after the last slab it still
  * needs; the slabs after the cut return to the view's free list, which inserts draw from
- * before the bump pointer.  The arc set, degrees and all incremental algorithm state are
- * unchanged.  Must not overlap any other call on the same graph (reads included).
+ * once the bump pointer has handed out the whole pool.  The arc set, degrees and all
+ * incremental algorithm state are unchanged; the forward view's update marks of the
+ * rewritten chains go back to their heads (see mk_incr_wcc_scheme).  Must not overlap any other call on the same graph (reads included).
  *   h_freed : host; receives the number of slabs returned to the free lists. */
 mk_status mk_compact(mk_graph* g, uint32_t min_tombstones, uint64_t* h_freed, hipStream_t stream);
 

@@ -133,10 +133,146 @@ __global__ void k_wcc_batch(uint32_t* P, Log lg, uint64_t n) {
     if (lg.st[i] == 1) uf_union(P, lg.s[i], lg.d[i]);
 }
 
+// ----------------------------------------------------------------- incremental WCC schemes
+// The vertices that gained out-arcs in a pending insert batch, each listed once (the
+// to_union flags of section 4.4): vertices with more than kHeavyBuckets buckets go to a
+// second list that is walked a block per vertex.
+__global__ void k_wcc_flag(Log lg, uint64_t n, const uint32_t* nbk, uint32_t* flag, uint32_t* light,
+                           uint32_t* nlight, uint32_t* heavy, uint32_t* nheavy) {
+  __shared__ Stage S[2];
+  stage_open(S[0], light, nlight);
+  stage_open(S[1], heavy, nheavy);
+  __syncthreads();
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
+    const uint64_t i = base + threadIdx.x;
+    bool p = false, hv = false;
+    uint32_t u = 0;
+    if (i < n && lg.st[i] == 1) {
+      u = lg.s[i];
+      p = ld_u32(flag + u) == 0u && atomicExch(flag + u, 1u) == 0u;
+      hv = p && nbk[u] > kHeavyBuckets;
+    }
+    stage_push(S[0], p && !hv, u);
+    stage_push(S[1], hv, u);
+  }
+  stage_close(S);
+}
+
+__global__ void k_wcc_unflag(uint32_t* flag, const uint32_t* light, const uint32_t* nlight,
+                             const uint32_t* heavy, const uint32_t* nheavy) {
+  const uint32_t nl = *nlight, nh = *nheavy;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nl + nh; i += gridDim.x * blockDim.x)
+    flag[i < nl ? light[i] : heavy[i - nl]] = 0u;
+}
+
+// UpdateIterator over one bucket chain (section 3.4).  The chain's mark is <slab + 1, lane>
+// of the first word the last pass did not unite (0: the head slab, lane 0).  As a chain's
+// filled words always form a prefix, everything inserted since then lies at or past the
+// mark, and the first EMPTY word met is the chain's new end: the mark moves there (the
+// paper's UpdateSlabPointers, done by the pass itself).  A chain with no new word costs one
+// slab read: the paper's per-chain is_updated flag is derived, not stored.
+__device__ inline void wcc_update_chain(const DView& F, uint64_t* marks, uint32_t* P, uint32_t h,
+                                        int nd0, uint32_t u, uint32_t ru) {
+  const int gl = glane();
+  const uint64_t m = ld_u64(marks + h);
+  uint32_t s = (uint32_t)m ? (uint32_t)m - 1u : h;
+  int l = (uint32_t)m ? (int)(m >> 32) : 0;
+  int nd = s == h ? nd0 : kKeysPerSlab;
+  while (true) {
+    const uint64_t x = ld_word(slab_ptr(F, s) + gl);
+    const uint32_t v = (uint32_t)x;
+    const bool data = gl >= l && gl < nd;
+    if (data && valid_key(v) && ld_u32(P + v) != ru) uf_union(P, u, v);
+    const uint32_t e = gballot(data && v == kEmptyKey);
+    if (e) {
+      l = __ffs(e) - 1;
+      break;
+    }
+    const uint32_t nx = gbcast(v, 15);
+    if (nx == kInvalid) {
+      l = nd;
+      break;
+    }
+    s = nx;
+    l = 0;
+    nd = kKeysPerSlab;
+  }
+  const uint64_t nm = ((uint64_t)(uint32_t)l << 32) | (s + 1u);
+  if (gl == 0 && nm != m) marks[h] = nm;
+}
+
+// Incremental WCC over the listed vertices: every slab of each (SlabIterator scheme, marks
+// null) or only the words past each chain's mark (UpdateIterator scheme).  Light vertices
+// take a 16-lane group each, heavy ones a block with its groups striding over the buckets.
+__global__ void __launch_bounds__(kBlock) k_wcc_listed(DView F, uint32_t* P, uint64_t* marks,
+                                                       const uint32_t* light, const uint32_t* nlight,
+                                                       const uint32_t* heavy, const uint32_t* nheavy) {
+  const uint32_t g0 = (blockIdx.x * kBlock + threadIdx.x) / kGroup;
+  const uint32_t ng = gridDim.x * kGroupsPerBlock;
+  const uint32_t gib = threadIdx.x / kGroup;
+  auto walk = [&](uint32_t u, uint32_t b0, uint32_t stride) {
+    const uint32_t ru = uf_find(P, u);
+    if (!marks) {
+      for_each_slab_strided(F, u, b0, stride, [&](uint64_t x, bool data) {
+        const uint32_t v = (uint32_t)x;
+        if (data && valid_key(v) && ld_u32(P + v) != ru) uf_union(P, u, v);
+      });
+      return;
+    }
+    const Table t = group_table(F, u);
+    for (uint32_t b = b0; b < t.nb; b += stride)
+      wcc_update_chain(F, marks, P, b ? t.xb + b - 1 : u,
+                       (b == 0 && t.nb > 1) ? kKeysPerSlab - 1 : kKeysPerSlab, u, ru);
+  };
+  const uint32_t nl = *nlight;
+  for (uint32_t i = g0; i < nl; i += ng) walk(light[i], 0, 1);
+  const uint32_t nh = *nheavy;
+  for (uint32_t j = blockIdx.x; j < nh; j += gridDim.x) walk(heavy[j], gib, kGroupsPerBlock);
+}
+
+// UpdateSlabPointers over every chain: each mark moves to its chain's end (the first EMPTY
+// word, or past the last slab's data words when the chain is full).  One group per chain.
+__global__ void __launch_bounds__(kBlock) k_mark_all(DView F, uint64_t* marks, uint64_t n_head,
+                                                     uint32_t nv) {
+  const uint64_t g0 = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kGroup;
+  const uint64_t ng = (uint64_t)gridDim.x * kGroupsPerBlock;
+  const int gl = glane();
+  for (uint64_t h = g0; h < n_head; h += ng) {
+    uint32_t s = (uint32_t)h;
+    uint64_t y = ld_word(slab_ptr(F, s) + gl);
+    int nd = (h < nv && (uint32_t)(gbcast64(y, 15) >> 32) > 1) ? kKeysPerSlab - 1 : kKeysPerSlab;
+    int l;
+    while (true) {
+      const uint32_t e = gballot(gl < nd && (uint32_t)y == kEmptyKey);
+      if (e) {
+        l = __ffs(e) - 1;
+        break;
+      }
+      const uint32_t nx = gbcast((uint32_t)y, 15);
+      if (nx == kInvalid) {
+        l = nd;
+        break;
+      }
+      s = nx;
+      nd = kKeysPerSlab;
+      y = ld_word(slab_ptr(F, s) + gl);
+    }
+    if (gl == 0) marks[h] = ((uint64_t)(uint32_t)l << 32) | (s + 1u);
+  }
+}
+
+// Full path compression and the labels.  No union runs here, so every root is final and
+// any parent a thread reads (the value the union kernels left, or the root another thread
+// has just stored) leads to it.  The walk must not halve paths: a halving store computed
+// from an earlier read could land after another thread's final store to the same vertex
+// and leave it pointing at a non-root.
 __global__ void k_wcc_compress(uint32_t* P, uint32_t nv, uint32_t* label) {
   for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
-    const uint32_t r = uf_find(P, v);
+    uint32_t r = v;
+    for (uint32_t p = ld_u32(P + r); p != r; p = ld_u32(P + r)) r = p;
     __hip_atomic_store(P + v, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    label[v] = r;
   }
 }
 
@@ -556,27 +692,58 @@ Log log_at(const mk_graph* g, uint64_t off) {
 extern "C" {
 
 mk_status mk_incr_wcc(mk_graph* g, uint32_t* d_label, mk_mode mode, hipStream_t stream) {
-  if (!g || !d_label) return MK_ERR_INVALID_ARG;
+  return mk_incr_wcc_scheme(g, d_label, mode, MK_WCC_LOG, stream);
+}
+
+mk_status mk_incr_wcc_scheme(mk_graph* g, uint32_t* d_label, mk_mode mode, mk_wcc_scheme scheme,
+                             hipStream_t stream) {
+  if (!g || !d_label || (uint32_t)scheme > (uint32_t)MK_WCC_UPDATE) return MK_ERR_INVALID_ARG;
   const uint32_t N = g->n;
   Pending p = pending_for(g, g->wcc);
   const bool full = mode == MK_RECOMPUTE || !g->wcc.valid || p.lost || (p.kinds & 2);
   uint32_t* P = g->wcc_parent;
-  if (full) {
+  const DView F = g->view[VF].d;
+  auto all_arcs = [&]() {  // union over every arc (collecting the heavy vertices first)
     uint32_t* nh = &g->ctr->pad0[1];
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, nh, 1u);
     hipLaunchKernelGGL(k_collect_heavy, dim3(blocks_for(N)), dim3(kBlock), 0, stream,
                        g->view[VF].nbk, N, g->fq[2], nh);
+    hipLaunchKernelGGL(k_wcc_all, dim3(kWalkBlocks), dim3(kBlock), 0, stream, F, P, N, g->fq[2], nh);
+  };
+  if (full) {
     hipLaunchKernelGGL(k_wcc_init, dim3(blocks_for(N)), dim3(kBlock), 0, stream, P, N);
-    hipLaunchKernelGGL(k_wcc_all, dim3(kWalkBlocks), dim3(kBlock), 0, stream, g->view[VF].d, P, N,
-                       g->fq[2], nh);
-  } else {
-    for (const BatchRec* b : p.list)
-      hipLaunchKernelGGL(k_wcc_batch, dim3(blocks_for(b->n)), dim3(kBlock), 0, stream, P,
-                         log_at(g, b->off), b->n);
+    all_arcs();
+    if (scheme == MK_WCC_UPDATE)
+      hipLaunchKernelGGL(k_mark_all, dim3(grid_for_groups(std::min<uint64_t>(g->view[VF].n_head, 1u << 20))),
+                         dim3(kBlock), 0, stream, F, g->upd_mark, g->view[VF].n_head, N);
+  } else if (!p.list.empty()) {
+    if (scheme == MK_WCC_LOG) {
+      for (const BatchRec* b : p.list)
+        hipLaunchKernelGGL(k_wcc_batch, dim3(blocks_for(b->n)), dim3(kBlock), 0, stream, P,
+                           log_at(g, b->off), b->n);
+    } else if (scheme == MK_WCC_NAIVE) {
+      all_arcs();
+    } else {
+      uint32_t* nl = &g->ctr->pad0[5];
+      uint32_t* nh = &g->ctr->pad0[6];
+      hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, nl, 2u);
+      uint64_t ops = 0;
+      for (const BatchRec* b : p.list) {
+        hipLaunchKernelGGL(k_wcc_flag, dim3(blocks_for(b->n)), dim3(kBlock), 0, stream,
+                           log_at(g, b->off), b->n, g->view[VF].nbk, g->wcc_flag, g->fq[0], nl,
+                           g->fq[1], nh);
+        ops += b->n;
+      }
+      hipLaunchKernelGGL(k_wcc_listed, dim3(blocks_for(ops * kGroup)), dim3(kBlock), 0, stream, F, P,
+                         scheme == MK_WCC_UPDATE ? g->upd_mark : nullptr, g->fq[0], nl, g->fq[1], nh);
+      hipLaunchKernelGGL(k_wcc_unflag, dim3(blocks_for(ops)), dim3(kBlock), 0, stream, g->wcc_flag,
+                         g->fq[0], nl, g->fq[1], nh);
+    }
   }
   if (full || !p.list.empty())
     hipLaunchKernelGGL(k_wcc_compress, dim3(blocks_for(N)), dim3(kBlock), 0, stream, P, N, d_label);
-  hipLaunchKernelGGL(k_copy_u32, dim3(blocks_for(N)), dim3(kBlock), 0, stream, P, d_label, N);
+  else  // nothing changed: the parents are the compressed labels of the last call
+    hipLaunchKernelGGL(k_copy_u32, dim3(blocks_for(N)), dim3(kBlock), 0, stream, P, d_label, N);
   MK_LAUNCH(g, "wcc");
   g->wcc.valid = true;
   mark_seen(g, g->wcc);

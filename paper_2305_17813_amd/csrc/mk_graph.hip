@@ -474,7 +474,7 @@ __global__ void k_free_fix(uint32_t* ctr) {
 // slabs after them).  Packing only moves a word to an earlier position of its own chain,
 // so the write position never passes the slab being read.
 __global__ void __launch_bounds__(kBlock) k_compact(DView V, uint64_t n_head, uint32_t nv, uint32_t min_tomb,
-                                                    unsigned long long* freed) {
+                                                    unsigned long long* freed, uint64_t* marks) {
   const uint64_t g0 = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kGroup;
   const uint64_t ng = (uint64_t)gridDim.x * kGroupsPerBlock;
   const int gl = glane();
@@ -497,6 +497,8 @@ __global__ void __launch_bounds__(kBlock) k_compact(DView V, uint64_t n_head, ui
       }
     }
     if (tomb < min_tomb || tomb == 0) continue;
+    // words move: the chain's update mark (if the view keeps marks) restarts at the head
+    if (marks && gl == 0) marks[h] = 0;
     uint32_t ws = head;  // slab being written, its capacity and fill
     int wcap = nd0, wpos = 0;
     uint64_t y = x;
@@ -630,12 +632,14 @@ bool layout(const mk_config* c, uint64_t m, char* base, mk_graph* g, size_t* tot
   Carver cv{base};
   const uint32_t N = c->n_vertices;
   const uint32_t views = c->views | MK_VIEW_FWD;
+  uint64_t hb_fwd = 0;
   for (int v = 0; v < 3; ++v) {
     const bool on = views & (1u << v);
     if (!on) continue;
     const uint64_t arcs = view_arcs(v, m);
     const uint64_t hb = head_bound(c, arcs), pc = pool_default(c, arcs);
     if (hb + pc >= 0xFFFFFFF0ull) return false;  // slab indices are u32
+    if (v == VF) hb_fwd = hb;
     uint64_t* slab = cv.take<uint64_t>((hb + pc) * kGroup);
     uint32_t* nbk = cv.take<uint32_t>(N);
     uint32_t* deg = cv.take<uint32_t>(N);
@@ -681,6 +685,8 @@ bool layout(const mk_config* c, uint64_t m, char* base, mk_graph* g, size_t* tot
   uint32_t* hv = cv.take<uint32_t>(N);
   double* hacc = cv.take<double>(N);
   double* prp = cv.take<double>(kPrParts);
+  uint64_t* umark = cv.take<uint64_t>(hb_fwd);
+  uint32_t* wflag = cv.take<uint32_t>(N);
   uint64_t* tk0 = nullptr;
   uint64_t* tk1 = nullptr;
   size_t sort_bytes = 0, scan_bytes = 0;
@@ -715,6 +721,8 @@ bool layout(const mk_config* c, uint64_t m, char* base, mk_graph* g, size_t* tot
     g->heavy_rev = hv;
     g->pr_hacc = hacc;
     g->pr_part = prp;
+    g->upd_mark = umark;
+    g->wcc_flag = wflag;
     g->tc_keys[0] = tk0;
     g->tc_keys[1] = tk1;
     g->sort_tmp = sort_tmp;
@@ -916,6 +924,10 @@ mk_status mk_graph_create(const mk_config* cfg, void* d_arena, size_t arena_byte
   }
   hipLaunchKernelGGL(k_fill_u32, dim3(nb_blocks), dim3(kBlock), 0, stream, g->mark, N, 0u);
   hipLaunchKernelGGL(k_fill_u32, dim3(nb_blocks), dim3(kBlock), 0, stream, g->far_mark, N, 0u);
+  hipLaunchKernelGGL(k_fill_u32, dim3(nb_blocks), dim3(kBlock), 0, stream, g->wcc_flag, N, 0u);
+  // update marks start at the chain heads (encoded 0)
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_stride_blocks(2 * g->view[VF].n_head)), dim3(kBlock), 0,
+                     stream, (uint32_t*)g->upd_mark, 2 * g->view[VF].n_head, 0u);
   // bulk insert, in chunks that fit the change log (used here as scratch)
   for (uint64_t off = 0; off < m; off += g->log_cap) {
     const uint64_t k = std::min<uint64_t>(g->log_cap, m - off);
@@ -1059,7 +1071,8 @@ mk_status mk_compact(mk_graph* g, uint32_t min_tombstones, uint64_t* h_freed, hi
     if (!vh.on) continue;
     hipLaunchKernelGGL(k_free_fix, dim3(1), dim3(64), 0, stream, vh.d.pool_ctr);
     hipLaunchKernelGGL(k_compact, dim3(grid_for_groups(std::min<uint64_t>(vh.n_head, 1u << 20))),
-                       dim3(kBlock), 0, stream, vh.d, vh.n_head, g->n, min_tombstones, freed);
+                       dim3(kBlock), 0, stream, vh.d, vh.n_head, g->n, min_tombstones, freed,
+                       v == VF ? g->upd_mark : nullptr);
     MK_LAUNCH(g, "k_compact");
   }
   MK_HIP(g, hipMemcpyAsync(g->h_pin + 10, freed, 8, hipMemcpyDeviceToHost, stream));

@@ -92,6 +92,8 @@ struct mk_graph {
   uint64_t* sssp_D = nullptr;
   mk::AlgoState bfs, sssp, wcc, pr, tc;
   uint32_t* wcc_parent = nullptr;
+  uint64_t* upd_mark = nullptr;   // forward-view update mark per bucket chain (head slab id)
+  uint32_t* wcc_flag = nullptr;   // per vertex: listed for the running incremental WCC pass
   float* pr_x = nullptr;      // current ranks
   float* pr_y = nullptr;      // next ranks
   float* pr_c = nullptr;      // contribution per vertex

@@ -20,6 +20,8 @@ HEADER = os.path.join(os.path.dirname(PKG), "include", "meerkat_mi355x.h")
 
 VIEW_FWD, VIEW_REV, VIEW_UND = 1, 2, 4
 AUTO, INCR, RECOMPUTE = 0, 1, 2
+# incremental-WCC schemes (mk_wcc_scheme)
+WCC_LOG, WCC_NAIVE, WCC_SLAB, WCC_UPDATE = 0, 1, 2, 3
 STATUS_NAMES = {0: "MK_OK", 1: "MK_ERR_INVALID_ARG", 2: "MK_ERR_OUT_OF_SLABS", 3: "MK_ERR_CAPACITY",
                 4: "MK_ERR_STATE", 5: "MK_ERR_HIP"}
 
@@ -81,6 +83,7 @@ def load():
         "mk_incr_bfs": [vp, u32, vp, vp, i32, vp],
         "mk_incr_sssp": [vp, u32, vp, vp, i32, vp],
         "mk_incr_wcc": [vp, vp, i32, vp],
+        "mk_incr_wcc_scheme": [vp, vp, i32, i32, vp],
         "mk_incr_pagerank": [vp, ctypes.c_float, ctypes.c_double, u32, vp, vp, i32, vp],
         "mk_count_triangles": [vp, vp, i32, vp],
         "mk_graph_export": [vp, vp, vp, vp, u64, ctypes.POINTER(u64), vp],
@@ -247,9 +250,15 @@ class Graph:
                "mk_incr_sssp")
         return di, pa
 
-    def wcc(self, mode: int = AUTO, stream=None):
+    def wcc(self, mode: int = AUTO, scheme: Optional[int] = None, stream=None):
+        """Component labels (smallest id); `scheme` picks the incremental-WCC scheme
+        (WCC_LOG, WCC_NAIVE, WCC_SLAB, WCC_UPDATE), None = mk_incr_wcc's default."""
         lab = torch.empty(self.n, dtype=torch.int32, device=self.device)
-        _check(self.lib.mk_incr_wcc(self.h, _ptr(lab), mode, self._s(stream)), "mk_incr_wcc")
+        if scheme is None:
+            _check(self.lib.mk_incr_wcc(self.h, _ptr(lab), mode, self._s(stream)), "mk_incr_wcc")
+        else:
+            _check(self.lib.mk_incr_wcc_scheme(self.h, _ptr(lab), mode, int(scheme), self._s(stream)),
+                   "mk_incr_wcc_scheme")
         return lab
 
     def pagerank(self, damping: float = 0.85, tol: float = 5e-8, max_iter: int = 500,

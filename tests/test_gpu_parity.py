@@ -406,3 +406,57 @@ def test_ragged_batch_sizes(b):
     p.query(qs, qd)
     p.check_structure()
     p.check_all(algos=("bfs", "sssp", "wcc", "tc"))
+
+
+@pytest.mark.parametrize("lf", [0.7, 0.0])
+@pytest.mark.parametrize("scheme", [native.WCC_LOG, native.WCC_NAIVE, native.WCC_SLAB, native.WCC_UPDATE])
+def test_wcc_schemes_agree(scheme, lf):
+    """Every incremental-WCC scheme gives the oracle's labels (hashing on, and off: the
+    single-bucket variant).  A graph of many small components plus a hub with 600 out-arcs
+    (a heavy vertex when hashing is on) takes insert batches that merge components (hub
+    arcs, in-batch duplicates, arcs already present), two pending batches at once, a delete
+    batch (a recompute), and a compaction between a pass and the next one, which moves the
+    words of chains that hold both tombstones and not-yet-united arcs."""
+    say(f"case: WCC scheme {scheme}, load factor {lf}")
+    rng = np.random.default_rng(40 + scheme)
+    n, hub = 6000, 7
+    src = np.concatenate([rng.integers(0, n, 2000), np.full(600, hub)])
+    dst = np.concatenate([rng.integers(0, n, 2000), rng.choice(n, 600, replace=False)])
+    keep = src != dst
+    src, dst = src[keep], dst[keep]
+    p = Pair(n, src, dst, rng.integers(1, 100, len(src)), views=native.VIEW_FWD, load_factor=lf)
+
+    def check():
+        lab = p.g.wcc(scheme=scheme)
+        assert np.array_equal(u32(lab), p.o.wcc())
+
+    def batch(b):
+        s, d = rng.integers(0, n, b), rng.integers(0, n, b)
+        s[: b // 3] = hub
+        if b > 4:
+            s[-2:], d[-2:] = s[:2], d[:2]  # duplicates inside the batch
+        # the weight is a function of the arc, so whichever copy of a duplicate applies,
+        # the stored weight is the same
+        p.insert(s, d, (s * 31 + d * 17) % 99 + 1, exact_status=False)
+
+    check()
+    for b in (1, 300, 2000):
+        batch(b)
+        check()
+    batch(500)
+    batch(500)
+    check()
+    os_, od, _ = p.o.export()
+    pick = rng.choice(len(os_), 400, replace=False)
+    pick = np.concatenate([pick, np.nonzero(os_ == hub)[0][:100]])
+    pick = np.unique(pick)
+    p.delete(os_[pick], od[pick])
+    check()
+    batch(300)
+    assert p.g.compact() >= 0
+    check()
+    batch(200)
+    check()
+    p.check_structure()
+    with pytest.raises(RuntimeError):
+        p.g.wcc(scheme=4)
