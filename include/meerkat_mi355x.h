@@ -129,10 +129,12 @@ mk_status mk_query_edges(mk_graph* g, const uint32_t* d_src, const uint32_t* d_d
 
 /* Breadth-first search levels from `source` kept up to date across batches (section 4.2:
  * BFS runs the SSSP kernels with unit weights).  A first call or a new source computes
- * from scratch; later calls apply the pending batches incrementally (insert prologue:
- * relax the inserted arcs; delete prologue: invalidate the dependence subtrees of
- * deleted tree arcs and pull from valid in-neighbours, which needs MK_VIEW_REV, else a
- * recompute) and then run the frontier epilogue to a fixed point.
+ * from scratch (with MK_VIEW_REV and a mean initial out-degree of at least 8: the
+ * direction-optimizing levels of mk_bfs_levels, then each vertex's parent from its
+ * in-arcs; otherwise the frontier kernels); later calls apply the pending batches
+ * incrementally (insert prologue: relax the inserted arcs; delete prologue: invalidate the
+ * dependence subtrees of deleted tree arcs and pull from valid in-neighbours, which needs
+ * MK_VIEW_REV, else a recompute) and then run the frontier epilogue to a fixed point.
  *   d_level  : N uint32 (device): hop distance, 0xFFFFFFFF if unreachable.
  *   d_parent : NULL or N uint32 (device): the smallest-id in-neighbour one level up;
  *              `source` for the source; 0xFFFFFFFF if unreachable. */
@@ -160,6 +162,27 @@ mk_status mk_incr_sssp(mk_graph* g, uint32_t source, uint32_t* d_dist, uint32_t*
 size_t mk_traversal_workspace_bytes(const mk_graph* g);
 mk_status mk_traverse_from(mk_graph* g, uint32_t source, int weighted, void* d_ws, size_t ws_bytes,
                            uint32_t slot, uint32_t* d_dist, uint32_t* d_parent, hipStream_t stream);
+
+/* Distance-only BFS levels from `source` (the "vanilla" BFS of the experimental section:
+ * 32-bit levels, no parents, against the tree variant that the maintained BFS/SSSP keep).
+ * Level-synchronous; each step is top-down (the frontier's out-arcs claim unreached vertices)
+ * or, with MK_VIEW_REV, bottom-up (each unreached vertex scans its in-arcs and stops at the
+ * first one on the current level), chosen on the device per step by direction optimization
+ * (Beamer et al.) recast for slabs: bottom-up when 2 nf + mf > 6 nu + N/2, with nf and mf
+ * the frontier's vertices and out-arcs and nu the unreached vertices.
+ * Reads the graph only; state lives in the caller's workspace, so it may overlap other reads
+ * (not updates) on other streams.
+ *   flags   : 0, or MK_BFS_TOP_DOWN_ONLY to never step bottom-up (also the behaviour without
+ *             MK_VIEW_REV).
+ *   d_ws/ws_bytes : device workspace of at least mk_bfs_levels_workspace_bytes(g) bytes.
+ *   slot    : 0..15, as for mk_traverse_from (pinned words for size read-backs).
+ *   d_level : N uint32 (device): the level (0 at the source), 0xFFFFFFFF if unreachable.
+ *   h_bottom_up_steps (nullable, host): number of bottom-up steps taken.
+ * Synchronizes `stream` every four levels. */
+enum { MK_BFS_TOP_DOWN_ONLY = 1 };
+size_t mk_bfs_levels_workspace_bytes(const mk_graph* g);
+mk_status mk_bfs_levels(mk_graph* g, uint32_t source, uint32_t flags, void* d_ws, size_t ws_bytes,
+                        uint32_t slot, uint32_t* d_level, uint32_t* h_bottom_up_steps, hipStream_t stream);
 
 /* Weakly connected components (section 4.4: union-find with full path compression).
  * Inserted arcs are united incrementally; any pending deletion forces a recompute.

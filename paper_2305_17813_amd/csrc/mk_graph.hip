@@ -687,6 +687,10 @@ bool layout(const mk_config* c, uint64_t m, char* base, mk_graph* g, size_t* tot
   double* prp = cv.take<double>(kPrParts);
   uint64_t* umark = cv.take<uint64_t>(hb_fwd);
   uint32_t* wflag = cv.take<uint32_t>(N);
+  char* lvc = cv.take<char>(256);
+  const uint64_t lv_cap = (uint64_t)N + hb_fwd / kBlock + 64;  // >= levels_multi_cap
+  uint32_t* lvm0 = cv.take<uint32_t>(lv_cap);
+  uint32_t* lvm1 = cv.take<uint32_t>(lv_cap);
   uint64_t* tk0 = nullptr;
   uint64_t* tk1 = nullptr;
   size_t sort_bytes = 0, scan_bytes = 0;
@@ -723,6 +727,9 @@ bool layout(const mk_config* c, uint64_t m, char* base, mk_graph* g, size_t* tot
     g->pr_part = prp;
     g->upd_mark = umark;
     g->wcc_flag = wflag;
+    g->lv_cnt = lvc;
+    g->lv_multi[0] = lvm0;
+    g->lv_multi[1] = lvm1;
     g->tc_keys[0] = tk0;
     g->tc_keys[1] = tk1;
     g->sort_tmp = sort_tmp;
@@ -855,6 +862,7 @@ mk_status mk_graph_create(const mk_config* cfg, void* d_arena, size_t arena_byte
   g->cfg = *cfg;
   g->cfg.views |= MK_VIEW_FWD;
   g->n = cfg->n_vertices;
+  g->m0 = m;
   g->arena = (char*)d_arena;
   g->arena_bytes = arena_bytes;
   layout(&g->cfg, m, g->arena, g, &g->used);

@@ -66,6 +66,7 @@ struct Counters {          // device-side scalars, one 4 KiB block
 struct mk_graph {
   mk_config cfg{};
   uint32_t n = 0;
+  uint64_t m0 = 0;            // arcs passed at creation
   mk::ViewHost view[3];
   char* arena = nullptr;
   size_t arena_bytes = 0, used = 0;
@@ -94,6 +95,8 @@ struct mk_graph {
   uint32_t* wcc_parent = nullptr;
   uint64_t* upd_mark = nullptr;   // forward-view update mark per bucket chain (head slab id)
   uint32_t* wcc_flag = nullptr;   // per vertex: listed for the running incremental WCC pass
+  void* lv_cnt = nullptr;         // counters of the level-synchronous BFS (256 B)
+  uint32_t* lv_multi[2] = {};     // its multi-bucket work items (vertex, chunk)
   float* pr_x = nullptr;      // current ranks
   float* pr_y = nullptr;      // next ranks
   float* pr_c = nullptr;      // contribution per vertex
@@ -141,4 +144,18 @@ struct Pending {
 };
 Pending pending_for(const mk_graph* g, const AlgoState& st);
 void mark_seen(mk_graph* g, AlgoState& st);
+
+// Buffers of one level-synchronous BFS (mk_levels.hip): a 256-byte counter block, two
+// frontier queues of N entries and two work-item arrays of levels_multi_cap(g) entries.
+struct LevelBufs {
+  void* cnt = nullptr;
+  uint32_t* q[2] = {};
+  uint32_t *multi_v = nullptr, *multi_c = nullptr;
+};
+size_t levels_multi_cap(const mk_graph* g);
+mk_status levels_run(mk_graph* g, uint32_t source, bool allow_bu, const LevelBufs& b, uint32_t* level,
+                     uint64_t* pin, uint32_t* h_bottom_up_steps, hipStream_t stream);
+// Static BFS of the maintained state through the levels (needs MK_VIEW_REV): levels into
+// `level`, then the tree nodes <level, smallest in-neighbour one level up> into D.
+mk_status bfs_tree_by_levels(mk_graph* g, uint32_t source, uint32_t* level, uint64_t* D, hipStream_t stream);
 }  // namespace mk

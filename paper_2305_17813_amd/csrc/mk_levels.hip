@@ -1,0 +1,496 @@
+// Distance-only ("vanilla") BFS levels, level-synchronous and direction-optimizing.
+//
+// The experimental section runs BFS in two variants: a vanilla one with 32-bit atomics that
+// computes only distances, and the tree variant (64-bit <distance, parent> nodes) that the
+// dynamic algorithms need; its static BFS is level-based.  This file is the vanilla variant:
+// one u32 level per vertex, one level per step.  A step is either top-down (the frontier's
+// out-arcs claim unreached vertices by CAS) or bottom-up (every unreached vertex scans its
+// in-arcs, through the reverse view, for a vertex of the current level and stops at the
+// first one).  A one-thread kernel picks the direction of each step on the device from the
+// frontier's size and out-arc count against the number of unreached vertices, so the host
+// only reads sizes back every few levels.
+//
+// The rule is Beamer's direction optimization recast for slabs.  A top-down step reads a slab
+// per frontier vertex and makes a random level read (and, for an unreached target, a CAS) per
+// out-arc; a bottom-up step reads at least one slab per unreached vertex and a level per
+// in-arc it scans until it meets the current level, and every bottom-up step also reads the
+// level of every vertex.  Counting a slab as two random accesses, bottom-up is taken when
+// 2 nf + mf > 6 nu + N / 2  (nf, mf: frontier vertices and out-arcs; nu: unreached
+// vertices).  On a power-law graph the hub's neighbourhood passes this at once (few vertices,
+// very many arcs).  On a road network the frontier has as few arcs per vertex as the
+// unreached part and most unreached vertices find no parent, so bottom-up steps there cost
+// more than top-down ones (measured); the N / 2 term keeps such a graph top-down.
+#include <rocprim/device/device_scan.hpp>
+
+#include <algorithm>
+
+#include "mk_internal.h"
+
+using namespace mk;
+
+namespace {
+
+constexpr uint32_t kLevelInf = 0xFFFFFFFFu;
+constexpr uint32_t kChunk = kBlock;       // buckets of a multi-bucket vertex per work item
+constexpr uint32_t kLevelsPerSync = 4;
+
+// Device counters of one call (in the caller's workspace).  Level L uses slot L mod 4.
+struct LvCnt {
+  uint32_t n[4];                // frontier sizes
+  uint32_t nm[4];               // multi-bucket work items of the level's top-down step
+  uint32_t mode;                // direction of the current step: 0 top-down, 1 bottom-up
+  uint32_t bu_steps;            // bottom-up steps taken
+  uint32_t reached;             // vertices reached before the current frontier
+  uint32_t pad[5];
+  unsigned long long arcs[4];   // out-arcs of each frontier
+};
+static_assert(sizeof(LvCnt) <= 256, "counter block");
+
+__global__ void k_lv_fill(uint32_t* level, uint32_t nv) {
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x)
+    level[v] = kLevelInf;
+}
+
+__global__ void k_lv_clear(LvCnt* c) {
+  uint32_t* w = reinterpret_cast<uint32_t*>(c);
+  for (uint32_t i = threadIdx.x; i < sizeof(LvCnt) / 4; i += blockDim.x) w[i] = 0;
+}
+
+__global__ void k_lv_seed(uint32_t* level, uint32_t* q0, LvCnt* c, const uint32_t* deg, uint32_t src) {
+  if (threadIdx.x != 0) return;
+  level[src] = 0;
+  q0[0] = src;
+  c->n[0] = 1;
+  c->arcs[0] = deg[src];
+  c->mode = 0;
+  c->reached = 0;
+}
+
+// Direction of level L's step, and the counters it fills.
+__global__ void k_lv_decide(LvCnt* c, uint32_t L, uint32_t nv, int allow_bu) {
+  if (threadIdx.x != 0) return;
+  const uint32_t s = L & 3, nx = (L + 1) & 3;
+  c->n[nx] = 0;
+  c->arcs[nx] = 0;
+  c->nm[s] = 0;
+  const uint64_t nf = c->n[s], mf = c->arcs[s];
+  if (L > 0) c->reached += c->n[(L - 1) & 3];
+  const uint64_t nu = (uint64_t)nv - c->reached - nf;
+  const uint32_t mode = allow_bu && nu > 0 && 2 * nf + mf > 6 * nu + nv / 2 ? 1u : 0u;
+  c->mode = mode;
+  if (nf) c->bu_steps += mode;
+}
+
+// Append the words of `sl` flagged in `found` (<= 15) to the staged next frontier.
+__device__ inline void push_found(Stage& S, uint32_t found, const Slab& sl) {
+  bool any;
+  const StageSlots t = stage_reserve(S, (uint32_t)__popc(found), any);
+  if (!any) return;
+  uint32_t k = 0;
+#pragma unroll
+  for (int j = 0; j < kKeysPerSlab; ++j)
+    if (found >> j & 1) stage_put(S, t, t.pos + k++, (uint32_t)sl.w[j]);
+}
+
+// Top-down on one slab: claim every unreached neighbour for level cur + 1 (the CAS winner
+// pushes it and counts its out-arcs).
+__device__ inline uint32_t claim_slab(const Slab& sl, int nd, uint32_t* level, const uint32_t* deg,
+                                      uint32_t cur, unsigned long long& arcs) {
+  uint32_t lv[kKeysPerSlab];
+#pragma unroll
+  for (int j = 0; j < kKeysPerSlab; ++j) {
+    const uint32_t v = (uint32_t)sl.w[j];
+    lv[j] = (j < nd && valid_key(v)) ? ld_u32(level + v) : 0u;
+  }
+  uint32_t found = 0;
+#pragma unroll
+  for (int j = 0; j < kKeysPerSlab; ++j) {
+    const uint32_t v = (uint32_t)sl.w[j];
+    if (lv[j] == kLevelInf && atomicCAS(level + v, kLevelInf, cur + 1) == kLevelInf) {
+      found |= 1u << j;
+      arcs += deg[v];
+    }
+  }
+  return found;
+}
+
+// Wave-wide exclusive prefix of k and one atomic per wave on *ctr: this lane's first slot.
+__device__ inline uint32_t wave_reserve(uint32_t* ctr, uint32_t k) {
+  const int lane = lane64();
+  uint32_t incl = k;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(incl, o);
+    if (lane >= o) incl += t;
+  }
+  const uint32_t total = __shfl(incl, 63);
+  uint32_t base = 0;
+  if (lane == 63 && total) base = atomicAdd(ctr, total);
+  base = __shfl(base, 63);
+  return base + incl - k;
+}
+
+__device__ inline void block_add(unsigned long long* acc, unsigned long long v, unsigned long long* out) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if ((threadIdx.x & 63) == 0 && v) atomicAdd(acc, v);
+  __syncthreads();
+  if (threadIdx.x == 0 && *acc) atomicAdd(out, *acc);
+}
+
+// Top-down step, single-bucket frontier vertices: a lane walks its vertex's chain.  A vertex
+// with several buckets becomes ceil(nb / kChunk) work items for k_lv_td_multi.
+__global__ void __launch_bounds__(kBlock) k_lv_td(DView F, LvCnt* c, uint32_t L, uint32_t* level,
+                                                  const uint32_t* fin, uint32_t* fout, uint32_t* mu_,
+                                                  uint32_t* mc_) {
+  const uint32_t s = L & 3;
+  if (c->mode != 0) return;
+  const uint32_t n = c->n[s];
+  if (n == 0) return;
+  __shared__ Stage S[1];
+  __shared__ unsigned long long acc;
+  stage_open(S[0], fout, &c->n[(L + 1) & 3]);
+  if (threadIdx.x == 0) acc = 0;
+  __syncthreads();
+  unsigned long long arcs = 0;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
+    const uint32_t i = base + threadIdx.x;
+    uint32_t u = 0, nb = 0;
+    if (i < n) {
+      u = fin[i];
+      nb = F.nbk[u];
+    }
+    const uint32_t k = nb > 1 ? (nb + kChunk - 1) / kChunk : 0u;
+    const uint32_t pos = wave_reserve(&c->nm[s], k);
+    for (uint32_t j = 0; j < k; ++j) {
+      mu_[pos + j] = u;
+      mc_[pos + j] = j;
+    }
+    bool active = i < n && nb == 1 && F.deg[u] > 0;
+    uint32_t t = u;
+    while (__ballot(active)) {
+      Slab sl;
+      uint32_t found = 0;
+      if (active) {
+        load_slab(F, t, sl);
+        found = claim_slab(sl, kKeysPerSlab, level, F.deg, L, arcs);
+        t = (uint32_t)sl.w[15];
+        active = t != kInvalid;
+      }
+      push_found(S[0], found, sl);
+    }
+  }
+  stage_close(S);
+  block_add(&acc, arcs, &c->arcs[(L + 1) & 3]);
+}
+
+// Top-down step, multi-bucket frontier vertices: a block per work item, a lane per bucket.
+__global__ void __launch_bounds__(kBlock) k_lv_td_multi(DView F, LvCnt* c, uint32_t L, uint32_t* level,
+                                                        uint32_t* fout, const uint32_t* mu_,
+                                                        const uint32_t* mc_) {
+  const uint32_t s = L & 3;
+  if (c->mode != 0) return;
+  const uint32_t nm = c->nm[s];
+  if (nm == 0) return;
+  __shared__ Stage S[1];
+  __shared__ unsigned long long acc;
+  stage_open(S[0], fout, &c->n[(L + 1) & 3]);
+  if (threadIdx.x == 0) acc = 0;
+  __syncthreads();
+  unsigned long long arcs = 0;
+  for (uint32_t it = blockIdx.x; it < nm; it += gridDim.x) {
+    const uint32_t u = mu_[it];
+    const uint64_t link = slab_ptr(F, u)[15];
+    const uint32_t nb = (uint32_t)(link >> 32);
+    const uint32_t xb = (uint32_t)slab_ptr(F, u)[14];
+    const uint32_t b = mc_[it] * kChunk + threadIdx.x;
+    bool active = b < nb;
+    uint32_t t = b == 0 ? u : xb + b - 1;
+    int nd = b == 0 ? kKeysPerSlab - 1 : kKeysPerSlab;
+    while (__ballot(active)) {
+      Slab sl;
+      uint32_t found = 0;
+      if (active) {
+        load_slab(F, t, sl);
+        found = claim_slab(sl, nd, level, F.deg, L, arcs);
+        t = (uint32_t)sl.w[15];
+        nd = kKeysPerSlab;
+        active = t != kInvalid;
+      }
+      push_found(S[0], found, sl);
+    }
+  }
+  stage_close(S);
+  block_add(&acc, arcs, &c->arcs[(L + 1) & 3]);
+}
+
+// Does some in-neighbour of v (reverse view) sit on level cur?  A lane walks v's buckets
+// and stops at the first slab that holds one.
+__device__ inline bool has_parent_at(const DView& R, uint32_t v, const uint32_t* level, uint32_t cur) {
+  Slab sl;
+  load_slab(R, v, sl);
+  const uint32_t nb = (uint32_t)(sl.w[15] >> 32);
+  const uint32_t xb = nb > 1 ? (uint32_t)sl.w[14] : 0u;
+  int nd = nb > 1 ? kKeysPerSlab - 1 : kKeysPerSlab;
+  for (uint32_t b = 0; b < nb; ++b) {
+    if (b > 0) {
+      load_slab(R, xb + b - 1, sl);
+      nd = kKeysPerSlab;
+    }
+    while (true) {
+      uint32_t lv[kKeysPerSlab];
+#pragma unroll
+      for (int j = 0; j < kKeysPerSlab; ++j) {
+        const uint32_t u = (uint32_t)sl.w[j];
+        lv[j] = (j < nd && valid_key(u)) ? ld_u32(level + u) : kLevelInf;
+      }
+      bool hit = false;
+#pragma unroll
+      for (int j = 0; j < kKeysPerSlab; ++j) hit |= lv[j] == cur;
+      if (hit) return true;
+      const uint32_t t = (uint32_t)sl.w[15];
+      if (t == kInvalid) break;
+      load_slab(R, t, sl);
+      nd = kKeysPerSlab;
+    }
+  }
+  return false;
+}
+
+// Bottom-up step: every unreached vertex with in-arcs looks for a parent on level L.  Only
+// the vertex's own lane writes its level, and no level changes to L during the step.
+__global__ void __launch_bounds__(kBlock) k_lv_bu(DView F, DView R, LvCnt* c, uint32_t L, uint32_t* level,
+                                                  uint32_t* fout, uint32_t nv) {
+  const uint32_t s = L & 3;
+  if (c->mode != 1 || c->n[s] == 0) return;
+  __shared__ Stage S[1];
+  __shared__ unsigned long long acc;
+  stage_open(S[0], fout, &c->n[(L + 1) & 3]);
+  if (threadIdx.x == 0) acc = 0;
+  __syncthreads();
+  unsigned long long arcs = 0;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t base = blockIdx.x * blockDim.x; base < nv; base += stride) {
+    const uint32_t v = base + threadIdx.x;
+    bool found = false;
+    if (v < nv && ld_u32(level + v) == kLevelInf && R.deg[v] > 0 && has_parent_at(R, v, level, L)) {
+      level[v] = L + 1;
+      arcs += F.deg[v];
+      found = true;
+    }
+    stage_push(S[0], found, v);
+  }
+  stage_close(S);
+  block_add(&acc, arcs, &c->arcs[(L + 1) & 3]);
+}
+
+inline uint32_t blocks_for(uint64_t n, uint32_t cap) {
+  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((n + kBlock - 1) / kBlock, cap));
+}
+
+size_t levels_ws_bytes(const mk_graph* g) {
+  return 256 + 2 * ((size_t)g->n * 4 + 256) + 2 * (levels_multi_cap(g) * 4 + 256) + 256;
+}
+
+// ----------------------------------------------------------------- tree nodes from levels
+// <level, INVALID> for every reached vertex but the source (<0, source>); unreached ones
+// get <INF, INVALID>.
+__global__ void k_lv_tree_init(const uint32_t* level, uint64_t* D, uint32_t nv, uint32_t src) {
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
+    const uint32_t lv = level[v];
+    D[v] = lv == kLevelInf ? kTreeNone : v == src ? (uint64_t)src : ((uint64_t)lv << 32) | kInvalid;
+  }
+}
+
+// Reached vertices (other than the source) with more than kHeavyBuckets buckets in the
+// reverse view, and their work items of kPrItem buckets.
+constexpr uint32_t kPrItem = 4;
+__global__ void k_lv_heavy(const uint32_t* nbk, const uint32_t* level, uint32_t nv, uint32_t src,
+                           uint32_t* out, uint32_t* cnt) {
+  __shared__ Stage S[1];
+  stage_open(S[0], out, cnt);
+  __syncthreads();
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t base = blockIdx.x * blockDim.x; base < nv; base += stride) {
+    const uint32_t v = base + threadIdx.x;
+    stage_push(S[0], v < nv && v != src && nbk[v] > kHeavyBuckets && level[v] != kLevelInf, v);
+  }
+  stage_close(S);
+}
+
+__global__ void k_lv_items(const uint32_t* nbk, const uint32_t* heavy, const uint32_t* nheavy, uint32_t* cnt) {
+  const uint32_t nh = *nheavy;
+  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < nh; j += gridDim.x * blockDim.x)
+    cnt[j] = (nbk[heavy[j]] + kPrItem - 1) / kPrItem;
+}
+
+// Parent of every reached vertex: the smallest in-neighbour one level up (the parent rule
+// of the tree variant).  One lane per single-bucket vertex, a 16-lane group per vertex of
+// 2 .. kHeavyBuckets buckets, and the heavy vertices' bucket items spread over every group,
+// which fold their minima in with a 64-bit atomic minimum.
+__global__ void __launch_bounds__(kBlock) k_lv_parents(DView R, const uint32_t* level, uint64_t* D, uint32_t nv,
+                                                       uint32_t src, const uint32_t* heavy,
+                                                       const uint32_t* nheavy, const uint32_t* hoff,
+                                                       const uint32_t* hcnt) {
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
+    if (R.nbk[v] != 1 || v == src) continue;
+    const uint32_t lv = level[v];
+    if (lv == kLevelInf) continue;
+    uint32_t best = kInvalid, t = v;
+    Slab sl;
+    while (true) {
+      load_slab(R, t, sl);
+      uint32_t lu[kKeysPerSlab];
+#pragma unroll
+      for (int j = 0; j < kKeysPerSlab; ++j) {
+        const uint32_t u = (uint32_t)sl.w[j];
+        lu[j] = valid_key(u) ? level[u] : kLevelInf;
+      }
+#pragma unroll
+      for (int j = 0; j < kKeysPerSlab; ++j)
+        if (lu[j] + 1 == lv) best = min(best, (uint32_t)sl.w[j]);
+      t = (uint32_t)sl.w[15];
+      if (t == kInvalid) break;
+    }
+    D[v] = ((uint64_t)lv << 32) | best;
+  }
+  const uint32_t g0 = (blockIdx.x * kBlock + threadIdx.x) / kGroup;
+  const uint32_t ng = gridDim.x * kGroupsPerBlock;
+  for (uint32_t v = g0; v < nv; v += ng) {
+    const uint32_t nb = R.nbk[v];
+    if (nb == 1 || nb > kHeavyBuckets || v == src) continue;
+    const uint32_t lv = level[v];
+    if (lv == kLevelInf) continue;
+    uint64_t best = kTreeNone;
+    for_each_slab(R, v, [&](uint64_t w, bool data) {
+      const uint32_t u = (uint32_t)w;
+      if (data && valid_key(u) && level[u] + 1 == lv) best = min(best, (uint64_t)u);
+    });
+    best = gmin_u64(best);
+    if (glane() == 0) D[v] = ((uint64_t)lv << 32) | (uint32_t)best;
+  }
+  const uint32_t nh = *nheavy;
+  if (nh == 0) return;
+  const uint32_t items = hoff[nh - 1] + hcnt[nh - 1];
+  for (uint32_t it = g0; it < items; it += ng) {
+    uint32_t lo = 0, hi = nh;  // the last j with hoff[j] <= it
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (hoff[mid] <= it) lo = mid;
+      else hi = mid;
+    }
+    const uint32_t v = heavy[lo];
+    const uint32_t lv = level[v];
+    const uint32_t b0 = (it - hoff[lo]) * kPrItem;
+    uint64_t best = kTreeNone;
+    for_each_bucket_range(R, v, b0, b0 + kPrItem, [&](uint64_t w, bool data) {
+      const uint32_t u = (uint32_t)w;
+      if (data && valid_key(u) && level[u] + 1 == lv) best = min(best, (uint64_t)u);
+    });
+    best = gmin_u64(best);
+    if (glane() == 0 && best != kTreeNone) amin64(D + v, ((uint64_t)lv << 32) | best);
+  }
+}
+
+}  // namespace
+
+namespace mk {
+
+size_t levels_multi_cap(const mk_graph* g) { return (size_t)g->n + g->view[VF].n_head / kChunk + 64; }
+
+mk_status levels_run(mk_graph* g, uint32_t source, bool allow_bu, const LevelBufs& b, uint32_t* level,
+                     uint64_t* pin, uint32_t* h_bottom_up_steps, hipStream_t stream) {
+  const uint32_t N = g->n;
+  LvCnt* c = reinterpret_cast<LvCnt*>(b.cnt);
+  const DView F = g->view[VF].d;
+  const DView R = g->view[VR].on ? g->view[VR].d : F;
+  allow_bu = allow_bu && g->view[VR].on;
+  hipLaunchKernelGGL(k_lv_clear, dim3(1), dim3(64), 0, stream, c);
+  hipLaunchKernelGGL(k_lv_fill, dim3(blocks_for(N, 4096)), dim3(kBlock), 0, stream, level, N);
+  hipLaunchKernelGGL(k_lv_seed, dim3(1), dim3(64), 0, stream, level, b.q[0], c, F.deg, source);
+  MK_LAUNCH(g, "k_lv_seed");
+  for (uint32_t L = 0;; ++L) {
+    uint32_t* fin = b.q[L & 1];
+    uint32_t* fout = b.q[(L + 1) & 1];
+    hipLaunchKernelGGL(k_lv_decide, dim3(1), dim3(64), 0, stream, c, L, N, (int)allow_bu);
+    hipLaunchKernelGGL(k_lv_td, dim3(blocks_for(N, 2048)), dim3(kBlock), 0, stream, F, c, L, level, fin,
+                       fout, b.multi_v, b.multi_c);
+    hipLaunchKernelGGL(k_lv_td_multi, dim3(2048), dim3(kBlock), 0, stream, F, c, L, level, fout, b.multi_v,
+                       b.multi_c);
+    if (allow_bu)
+      hipLaunchKernelGGL(k_lv_bu, dim3(blocks_for(N, 8192)), dim3(kBlock), 0, stream, F, R, c, L, level,
+                         fout, N);
+    MK_LAUNCH(g, "k_lv step");
+    if ((L + 1) % kLevelsPerSync == 0 || L + 1 >= N) {
+      MK_HIP(g, hipMemcpyAsync(pin, &c->n[(L + 1) & 3], 4, hipMemcpyDeviceToHost, stream));
+      MK_HIP(g, hipMemcpyAsync(pin + 1, &c->bu_steps, 4, hipMemcpyDeviceToHost, stream));
+      MK_HIP(g, hipStreamSynchronize(stream));
+      if ((uint32_t)pin[0] == 0 || L + 1 >= N) break;
+    }
+  }
+  if (h_bottom_up_steps) *h_bottom_up_steps = (uint32_t)pin[1];
+  return MK_OK;
+}
+
+mk_status bfs_tree_by_levels(mk_graph* g, uint32_t source, uint32_t* level, uint64_t* D, hipStream_t stream) {
+  const uint32_t N = g->n;
+  LevelBufs b;
+  b.cnt = g->lv_cnt;
+  b.q[0] = g->fq[0];
+  b.q[1] = g->fq[1];
+  b.multi_v = g->lv_multi[0];
+  b.multi_c = g->lv_multi[1];
+  mk_status s = levels_run(g, source, true, b, level, g->h_pin, nullptr, stream);
+  if (s != MK_OK) return s;
+  const DView R = g->view[VR].d;
+  uint32_t* heavy = g->fq[2];
+  uint32_t* hcnt = g->fq[3];
+  uint32_t* hoff = g->fq[4];
+  uint32_t* nh = reinterpret_cast<LvCnt*>(g->lv_cnt)->pad;
+  hipLaunchKernelGGL(k_lv_clear, dim3(1), dim3(64), 0, stream, reinterpret_cast<LvCnt*>(g->lv_cnt));
+  hipLaunchKernelGGL(k_lv_tree_init, dim3(blocks_for(N, 4096)), dim3(kBlock), 0, stream, level, D, N, source);
+  hipLaunchKernelGGL(k_lv_heavy, dim3(blocks_for(N, 4096)), dim3(kBlock), 0, stream, R.nbk, level, N, source,
+                     heavy, nh);
+  hipLaunchKernelGGL(k_lv_items, dim3(blocks_for(N, 1024)), dim3(kBlock), 0, stream, R.nbk, heavy, nh, hcnt);
+  size_t tb = g->scan_tmp_bytes;
+  if (rocprim::exclusive_scan(g->scan_tmp, tb, hcnt, hoff, 0u, (size_t)N, rocprim::plus<uint32_t>(), stream) !=
+      hipSuccess)
+    return MK_ERR_HIP;
+  hipLaunchKernelGGL(k_lv_parents, dim3(4096), dim3(kBlock), 0, stream, R, level, D, N, source, heavy, nh, hoff,
+                     hcnt);
+  MK_LAUNCH(g, "k_lv_parents");
+  return MK_OK;
+}
+
+}  // namespace mk
+
+extern "C" {
+
+mk_status mk_bfs_levels(mk_graph* g, uint32_t source, uint32_t flags, void* d_ws, size_t ws_bytes,
+                        uint32_t slot, uint32_t* d_level, uint32_t* h_bottom_up_steps, hipStream_t stream) {
+  if (!g || !d_ws || !d_level || source >= g->n || slot >= kSlots || (flags & ~MK_BFS_TOP_DOWN_ONLY))
+    return MK_ERR_INVALID_ARG;
+  if (ws_bytes < levels_ws_bytes(g)) return MK_ERR_CAPACITY;
+  if (!g->slot_pin[slot]) {
+    if (hipHostMalloc((void**)&g->slot_pin[slot], 64 * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess)
+      return MK_ERR_HIP;
+  }
+  const uint32_t N = g->n;
+  char* p = reinterpret_cast<char*>(((uintptr_t)d_ws + 255) & ~uintptr_t(255));
+  auto take = [&](size_t bytes) {
+    char* r = p;
+    p += (bytes + 255) & ~size_t(255);
+    return r;
+  };
+  LevelBufs b;
+  b.cnt = take(256);
+  b.q[0] = reinterpret_cast<uint32_t*>(take((size_t)N * 4));
+  b.q[1] = reinterpret_cast<uint32_t*>(take((size_t)N * 4));
+  b.multi_v = reinterpret_cast<uint32_t*>(take(levels_multi_cap(g) * 4));
+  b.multi_c = reinterpret_cast<uint32_t*>(take(levels_multi_cap(g) * 4));
+  return levels_run(g, source, !(flags & MK_BFS_TOP_DOWN_ONLY), b, d_level, g->slot_pin[slot],
+                    h_bottom_up_steps, stream);
+}
+
+size_t mk_bfs_levels_workspace_bytes(const mk_graph* g) { return g ? levels_ws_bytes(g) : 0; }
+
+}  // extern "C"

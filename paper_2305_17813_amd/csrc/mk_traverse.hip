@@ -796,7 +796,12 @@ mk_status traverse(mk_graph* g, AlgoState& st, uint64_t* D, uint32_t source, uin
   const bool full = mode == MK_RECOMPUTE || !st.valid || st.source != source || p.lost ||
                     p.kinds == 3 || (p.kinds == 2 && !can_dec);
   if (full) {
-    mk_status s = static_from<kUnit>(g, c, source, stream);
+    // BFS of a graph with the reverse view and a mean out-degree of at least 8:
+    // direction-optimizing levels, then the parents.  On sparser graphs bottom-up steps do
+    // not pay (a road network takes none), and one tree pass beats levels plus parents.
+    const bool by_levels = kUnit && can_dec && g->m0 >= 8ull * N;
+    mk_status s = by_levels ? bfs_tree_by_levels(g, source, d_out, D, stream)
+                            : static_from<kUnit>(g, c, source, stream);
     if (s != MK_OK) return s;
   } else if (!p.list.empty()) {
     const uint32_t stamp0 = ++g->stamp;

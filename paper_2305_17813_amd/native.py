@@ -94,6 +94,7 @@ def load():
         "mk_batch_features": [vp, i32, vp, vp, vp, u64, vp, vp, u64, ctypes.POINTER(ctypes.c_float), vp],
         "mk_mlp_forward": [vp, vp, u32, vp, vp],
         "mk_traverse_from": [vp, u32, i32, vp, ctypes.c_size_t, u32, vp, vp, vp],
+        "mk_bfs_levels": [vp, u32, u32, vp, ctypes.c_size_t, u32, vp, ctypes.POINTER(u32), vp],
         "mk_mlp_grad": [vp, vp, vp, vp, u32, vp, vp, ctypes.c_size_t, vp, vp],
         "mk_mlp_adam": [vp, vp, vp, vp, u32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                         ctypes.c_float, u32, vp],
@@ -104,6 +105,8 @@ def load():
         f.argtypes = args
     L.mk_traversal_workspace_bytes.restype = ctypes.c_size_t
     L.mk_traversal_workspace_bytes.argtypes = [vp]
+    L.mk_bfs_levels_workspace_bytes.restype = ctypes.c_size_t
+    L.mk_bfs_levels_workspace_bytes.argtypes = [vp]
     L.mk_mlp_workspace_bytes.restype = ctypes.c_size_t
     L.mk_mlp_workspace_bytes.argtypes = [u32]
     L.mk_status_string.restype = ctypes.c_char_p
@@ -234,6 +237,20 @@ class Graph:
                                          int(slot), _ptr(di), _ptr(pa), self._s(stream)),
                "mk_traverse_from")
         return di, pa
+
+    def bfs_levels(self, source: int, top_down_only: bool = False, ws: Optional[torch.Tensor] = None,
+                   slot: int = 0, stream=None):
+        """Distance-only, direction-optimizing BFS levels (read-only on the graph).
+        Returns (levels int32 tensor, number of bottom-up steps)."""
+        if ws is None:
+            ws = torch.empty(self.lib.mk_bfs_levels_workspace_bytes(self.h), dtype=torch.uint8,
+                             device=self.device)
+        lv = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        bu = ctypes.c_uint32()
+        _check(self.lib.mk_bfs_levels(self.h, int(source), 1 if top_down_only else 0, _ptr(ws), ws.numel(),
+                                      int(slot), _ptr(lv), ctypes.byref(bu), self._s(stream)),
+               "mk_bfs_levels")
+        return lv, int(bu.value)
 
     # ------------------------------------------------------------ algorithms
     def bfs(self, source: int, mode: int = AUTO, parents: bool = True, stream=None):

@@ -460,3 +460,44 @@ def test_wcc_schemes_agree(scheme, lf):
     p.check_structure()
     with pytest.raises(RuntimeError):
         p.g.wcc(scheme=4)
+
+
+@pytest.mark.parametrize("top_down_only", [False, True])
+def test_bfs_levels_distance_only(top_down_only):
+    """The distance-only, direction-optimizing BFS gives the oracle's levels: R-MAT from the
+    hub (bottom-up steps taken unless disabled) and from a low-degree vertex, after an insert
+    and a delete batch, on the road-like grid, on a graph without the reverse view (top-down
+    only), from a source without out-arcs, and on one vertex."""
+    say(f"case: BFS levels, top-down only = {top_down_only}")
+
+    def cmp(pair, src, expect_bu=None):
+        lv, bu = pair.g.bfs_levels(src, top_down_only)
+        lo, _ = pair.o.bfs(src)
+        assert np.array_equal(u32(lv), lo), f"levels differ at {np.nonzero(u32(lv) != lo)[0][:10]}"
+        if top_down_only:
+            assert bu == 0
+        elif expect_bu is not None:
+            assert (bu > 0) == expect_bu, bu
+        return bu
+
+    g = I.rmat_s(12)
+    hub = I.max_out_degree_vertex(g)
+    p = make_pair(g, source=hub)
+    cmp(p, hub, expect_bu=True)
+    deg = np.bincount(u32(g.src), minlength=g.n)
+    low = int(np.nonzero(deg == 1)[0][0])
+    cmp(p, low)
+    wl = I.Workload(g, 31)
+    s, d, w = wl.insert_batch(3000)
+    p.insert(s, d, w)
+    cmp(p, hub)
+    s, d = wl.delete_batch(3000)
+    p.delete(s, d)
+    cmp(p, hub)
+    cmp(p, low)
+    cmp(p, int(np.nonzero(deg == 0)[0][0]))
+    gg = I.grid_graph(64, 0x4D45524B + 2)
+    cmp(make_pair(gg), 0)
+    q = make_pair(g, source=hub, views=native.VIEW_FWD)
+    cmp(q, hub, expect_bu=False)
+    cmp(Pair(1, [], [], [], source=0), 0, expect_bu=False)
