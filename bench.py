@@ -304,6 +304,34 @@ def main():
                 tb[p].append(ev[i].elapsed_time(ev[i + 1]))
         by_batch[str(b2)] = {p: med(v) for p, v in tb.items()}
     log(f"[bench] smaller batches: {by_batch}")
+
+    # static computations on the final graph: the tree BFS of the maintained state (levels
+    # then parents), the distance-only direction-optimizing levels and their top-down-only
+    # form, the frontier SSSP and the static WCC; medians of 3
+    ws_lv = torch.empty(G.lib.mk_bfs_levels_workspace_bytes(G.h), dtype=torch.uint8, device=dev)
+    bu_steps = []
+
+    def med_ms(fn):
+        ts = []
+        for _ in range(3):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            b.synchronize()
+            ts.append(a.elapsed_time(b))
+        return med(ts)
+
+    static_ms = {
+        "bfs_tree_recompute": med_ms(lambda: G.bfs(src_v, native.RECOMPUTE)),
+        "bfs_levels_direction_optimizing": med_ms(lambda: bu_steps.append(G.bfs_levels(src_v, False, ws_lv)[1])),
+        "bfs_levels_top_down": med_ms(lambda: G.bfs_levels(src_v, True, ws_lv)),
+        "sssp_recompute": med_ms(lambda: G.sssp(src_v, native.RECOMPUTE)),
+        "wcc_recompute": med_ms(lambda: G.wcc(native.RECOMPUTE)),
+    }
+    static_ms["bfs_levels_bottom_up_steps"] = bu_steps[-1]
+    log(f"[bench] static: {static_ms}")
     result = {
         "metric": METRIC,
         "value": updates_per_s,
@@ -332,6 +360,7 @@ def main():
         "incr_ms_per_batch": incr,
         "p90_ms_per_batch": {p: float(np.percentile(times[p], 90)) for p in phases},
         "ms_by_batch_size": by_batch,
+        "static_ms": static_ms,
         "pagerank_iters": pr_iters,
         "build_s": build_s,
         "roofline": roof,
@@ -504,9 +533,12 @@ def grid_bench(args):
         b.synchronize()
         return a.elapsed_time(b)
 
+    ws_lv = torch.empty(G.lib.mk_bfs_levels_workspace_bytes(G.h), dtype=torch.uint8, device=dev)
     rec = {"sssp_ms": timed(lambda: G.sssp(0, native.RECOMPUTE)),
            "bfs_ms": timed(lambda: G.bfs(0, native.RECOMPUTE)),
-           "wcc_ms": timed(lambda: G.wcc(native.RECOMPUTE))}
+           "wcc_ms": timed(lambda: G.wcc(native.RECOMPUTE)),
+           "bfs_levels_ms": timed(lambda: G.bfs_levels(0, False, ws_lv)),
+           "bfs_levels_top_down_ms": timed(lambda: G.bfs_levels(0, True, ws_lv))}
     log(f"[grid] {g.n} vertices, {g.m} arcs; recompute {rec}")
     out = {"recompute": rec, "batches": {}}
     for B in (1000, 10000, 100000):
