@@ -35,13 +35,19 @@ def _cmp_traversals(G, O, src, with_pr=True, with_tc=True, state=None):
     lv, pa = G.bfs(src)
     lo, po = O.bfs(src)
     assert np.array_equal(u32(lv), lo) and np.array_equal(u32(pa), po), "BFS differs"
+    lvd, bu = G.bfs_levels(src)
+    assert np.array_equal(u32(lvd), lo), "distance-only BFS levels differ"
     di, pa = G.sssp(src)
     do, po = O.sssp(src)
     assert np.array_equal(u32(di), do), f"SSSP distances differ at {np.nonzero(u32(di) != do)[0][:8]}"
     assert np.array_equal(u32(pa), po), "SSSP parents differ"
     lab = G.wcc()
-    assert np.array_equal(u32(lab), O.wcc()), "WCC differs"
-    say(f"  BFS/SSSP/WCC equal ({time.time()-t:.1f}s)")
+    lo_w = O.wcc()
+    assert np.array_equal(u32(lab), lo_w), "WCC differs"
+    if state is not None:  # the UpdateIterator scheme on a graph of its own, kept in step
+        assert np.array_equal(u32(state["wcc_graph"].wcc(scheme=native.WCC_UPDATE)), lo_w), \
+            "WCC (UpdateIterator scheme) differs"
+    say(f"  BFS/SSSP/WCC equal, distance-only BFS took {bu} bottom-up steps ({time.time()-t:.1f}s)")
     if with_pr:
         t = time.time()
         r, it = G.pagerank()
@@ -65,7 +71,8 @@ def test_rmat_scale22_batches_of_1m():
     g = I.rmat_graph(22, 16, 0x4D45524B + 1, device="cuda")
     src = I.max_out_degree_vertex(g)
     G, O = _pair(g, src, log_capacity=1 << 22)
-    state = {}
+    state = {"wcc_graph": native.Graph(g.n, g.src, g.dst, g.w, views=native.VIEW_FWD, load_factor=0.7,
+                                       log_capacity=1 << 22)}
     # the oracle's triangle count takes ~2 minutes here: the GPU count is compared once, at
     # the end, where it has gone through the static count and both incremental updates
     G.triangles()
@@ -75,12 +82,14 @@ def test_rmat_scale22_batches_of_1m():
     s, d, w = wl.insert_batch(B)
     st = u32(G.insert_edges(s, d, w))
     assert np.array_equal(st, O.insert(u32(s), u32(d), u32(w)).astype(np.uint32))
+    state["wcc_graph"].insert_edges(s, d, w, status=False)
     say("  insert statuses equal")
     G.triangles()
     _cmp_traversals(G, O, src, state=state, with_tc=False)
     s, d = wl.delete_batch(B)
     st = u32(G.delete_edges(s, d))
     assert np.array_equal(st, O.delete(u32(s), u32(d)).astype(np.uint32))
+    state["wcc_graph"].delete_edges(s, d, status=False)
     say("  delete statuses equal")
     _cmp_traversals(G, O, src, state=state)
     qs, qd = wl.query_batch(1 << 20)
