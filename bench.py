@@ -307,8 +307,9 @@ def main():
 
     # static computations on the final graph: the tree BFS of the maintained state (levels
     # then parents), the distance-only direction-optimizing levels and their top-down-only
-    # form, the frontier SSSP and the static WCC; medians of 3
+    # form, the tree SSSP, the distance-only SSSP and the static WCC; medians of 3
     ws_lv = torch.empty(G.lib.mk_bfs_levels_workspace_bytes(G.h), dtype=torch.uint8, device=dev)
+    ws_ds = torch.empty(G.lib.mk_sssp_distances_workspace_bytes(G.h), dtype=torch.uint8, device=dev)
     bu_steps = []
 
     def med_ms(fn):
@@ -328,6 +329,7 @@ def main():
         "bfs_levels_direction_optimizing": med_ms(lambda: bu_steps.append(G.bfs_levels(src_v, False, ws_lv)[1])),
         "bfs_levels_top_down": med_ms(lambda: G.bfs_levels(src_v, True, ws_lv)),
         "sssp_recompute": med_ms(lambda: G.sssp(src_v, native.RECOMPUTE)),
+        "sssp_distances": med_ms(lambda: G.sssp_distances(src_v, ws_ds)),
         "wcc_recompute": med_ms(lambda: G.wcc(native.RECOMPUTE)),
     }
     static_ms["bfs_levels_bottom_up_steps"] = bu_steps[-1]
@@ -538,7 +540,8 @@ def grid_bench(args):
            "bfs_ms": timed(lambda: G.bfs(0, native.RECOMPUTE)),
            "wcc_ms": timed(lambda: G.wcc(native.RECOMPUTE)),
            "bfs_levels_ms": timed(lambda: G.bfs_levels(0, False, ws_lv)),
-           "bfs_levels_top_down_ms": timed(lambda: G.bfs_levels(0, True, ws_lv))}
+           "bfs_levels_top_down_ms": timed(lambda: G.bfs_levels(0, True, ws_lv)),
+           "sssp_distances_ms": timed(lambda: G.sssp_distances(0))}
     log(f"[grid] {g.n} vertices, {g.m} arcs; recompute {rec}")
     out = {"recompute": rec, "batches": {}}
     for B in (1000, 10000, 100000):

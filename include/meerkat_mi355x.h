@@ -184,6 +184,19 @@ size_t mk_bfs_levels_workspace_bytes(const mk_graph* g);
 mk_status mk_bfs_levels(mk_graph* g, uint32_t source, uint32_t flags, void* d_ws, size_t ws_bytes,
                         uint32_t slot, uint32_t* d_level, uint32_t* h_bottom_up_steps, hipStream_t stream);
 
+/* Distance-only SSSP from `source` (the vanilla SSSP of the experimental section: 32-bit
+ * distances relaxed by atomic minimum, no parents).  Near-far scheduling on the device: a
+ * vertex whose distance drops below the band limit joins the next frontier, any other waits
+ * on a far pile that is split at (its smallest distance + the graph's band width) when the
+ * frontier runs dry.  Read-only on the graph, state in the caller's workspace, as for
+ * mk_bfs_levels.  Weights must be >= 1.
+ *   d_dist : N uint32 (device): the distance (sums saturate at 0xFFFFFFFE), 0xFFFFFFFF if
+ *            unreachable.
+ * Synchronizes `stream` every four steps. */
+size_t mk_sssp_distances_workspace_bytes(const mk_graph* g);
+mk_status mk_sssp_distances(mk_graph* g, uint32_t source, void* d_ws, size_t ws_bytes, uint32_t slot,
+                            uint32_t* d_dist, hipStream_t stream);
+
 /* Weakly connected components (section 4.4: union-find with full path compression).
  * Inserted arcs are united incrementally; any pending deletion forces a recompute.
  *   d_label : N uint32 (device): the smallest vertex id of the component. */

@@ -1,4 +1,5 @@
-// Distance-only ("vanilla") BFS levels, level-synchronous and direction-optimizing.
+// Distance-only ("vanilla") traversals: BFS levels, level-synchronous and
+// direction-optimizing, and SSSP distances by near-far relaxation (further down).
 //
 // The experimental section runs BFS in two variants: a vanilla one with 32-bit atomics that
 // computes only distances, and the tree variant (64-bit <distance, parent> nodes) that the
@@ -49,6 +50,13 @@ static_assert(sizeof(LvCnt) <= 256, "counter block");
 __global__ void k_lv_fill(uint32_t* level, uint32_t nv) {
   for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x)
     level[v] = kLevelInf;
+}
+
+__global__ void k_zero_marks(uint32_t* a, uint32_t* b, uint32_t nv) {
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
+    a[v] = 0;
+    b[v] = 0;
+  }
 }
 
 __global__ void k_lv_clear(LvCnt* c) {
@@ -391,6 +399,218 @@ __global__ void __launch_bounds__(kBlock) k_lv_parents(DView R, const uint32_t* 
   }
 }
 
+
+// ----------------------------------------------------------------- distance-only SSSP
+// The vanilla SSSP: one u32 distance per vertex relaxed by 32-bit atomic minimum, no
+// parents.  Scheduling is near-far: a relaxed vertex whose new distance is below the band
+// limit T joins the next near frontier, any other the far pile; when the near frontier runs
+// dry, the far pile is split at T = (its smallest distance) + delta.  Every decision is made
+// on the device, so the host only reads sizes back every few steps.  Any schedule reaches the
+// same distances (label correcting), so the band width only changes the work.
+struct DsCnt {
+  uint32_t n[4];     // near frontier sizes by step mod 4
+  uint32_t nm[4];    // multi-bucket work items by step mod 4
+  uint32_t nfar[2];  // far pile sizes
+  uint32_t fpar;     // index of the current far pile
+  uint32_t T;        // band limit
+  uint32_t band;     // band number (far-pile duplicate stamps)
+  uint32_t fmin;     // smallest distance on the far pile (before a split)
+  uint32_t done;     // blocks of the running split that have finished
+  uint32_t pad[5];
+};
+static_assert(sizeof(DsCnt) <= 256, "counter block");
+
+__global__ void k_ds_seed(uint32_t* dist, uint32_t* q0, DsCnt* c, uint32_t src, uint32_t delta) {
+  if (threadIdx.x != 0) return;
+  dist[src] = 0;
+  q0[0] = src;
+  c->n[0] = 1;
+  c->T = delta;
+  c->band = 1;
+  c->fmin = kLevelInf;
+}
+
+// Relax one slab of u (distance du): a neighbour whose distance drops goes to the near
+// frontier (once per step, by the step stamp) or to the far pile (once per band).
+__device__ inline void relax_ds(const Slab& sl, int nd, uint32_t du, uint32_t* dist, uint32_t* mark,
+                                uint32_t* fmark, uint32_t stamp, uint32_t band, uint32_t T, uint32_t& near,
+                                uint32_t& far) {
+  uint32_t dv[kKeysPerSlab];
+#pragma unroll
+  for (int j = 0; j < kKeysPerSlab; ++j) {
+    const uint32_t v = (uint32_t)sl.w[j];
+    dv[j] = (j < nd && valid_key(v)) ? ld_u32(dist + v) : 0u;
+  }
+  near = far = 0;
+#pragma unroll
+  for (int j = 0; j < kKeysPerSlab; ++j) {
+    const uint32_t v = (uint32_t)sl.w[j];
+    const uint32_t nd_ = (uint32_t)min<uint64_t>((uint64_t)du + (sl.w[j] >> 32), 0xFFFFFFFEull);
+    if (nd_ < dv[j] && nd_ < atomicMin(dist + v, nd_)) {
+      if (nd_ < T) {
+        if (atomicExch(mark + v, stamp) != stamp) near |= 1u << j;
+      } else if (atomicExch(fmark + v, band) != band) {
+        far |= 1u << j;
+      }
+    }
+  }
+}
+
+__device__ inline void wave_min_to(uint32_t* out, uint32_t m) {
+  for (int o = 32; o > 0; o >>= 1) m = min(m, (uint32_t)__shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0 && m != kLevelInf) atomicMin(out, m);
+}
+
+struct DsArgs {
+  uint32_t *dist, *mark, *fmark, *far[2], *multi_v, *multi_c;
+};
+
+// Near step, single-bucket frontier vertices (a lane each); others become 256-bucket items.
+__global__ void __launch_bounds__(kBlock) k_ds_relax(DView F, DsCnt* c, uint32_t S, DsArgs a, const uint32_t* fin,
+                                                     uint32_t* fout) {
+  const uint32_t s = S & 3;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {  // counters of the next step (unused in this one)
+    c->n[(S + 2) & 3] = 0;
+    c->nm[(S + 1) & 3] = 0;
+  }
+  const uint32_t n = c->n[s];
+  if (n == 0) return;
+  const uint32_t T = c->T, band = c->band, fp = c->fpar, stamp = S + 1;
+  __shared__ Stage St[2];
+  stage_open(St[0], fout, &c->n[(S + 1) & 3]);
+  stage_open(St[1], a.far[fp], &c->nfar[fp]);
+  __syncthreads();
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
+    const uint32_t i = base + threadIdx.x;
+    uint32_t u = 0, nb = 0, du = 0;
+    if (i < n) {
+      u = fin[i];
+      nb = F.nbk[u];
+      du = ld_u32(a.dist + u);
+    }
+    const uint32_t k = nb > 1 ? (nb + kChunk - 1) / kChunk : 0u;
+    const uint32_t pos = wave_reserve(&c->nm[s], k);
+    for (uint32_t j = 0; j < k; ++j) {
+      a.multi_v[pos + j] = u;
+      a.multi_c[pos + j] = j;
+    }
+    bool active = i < n && nb == 1 && F.deg[u] > 0;
+    uint32_t t = u;
+    while (__ballot(active)) {
+      Slab sl;
+      uint32_t nr = 0, fr = 0;
+      if (active) {
+        load_slab(F, t, sl);
+        relax_ds(sl, kKeysPerSlab, du, a.dist, a.mark, a.fmark, stamp, band, T, nr, fr);
+        t = (uint32_t)sl.w[15];
+        active = t != kInvalid;
+      }
+      push_found(St[0], nr, sl);
+      push_found(St[1], fr, sl);
+    }
+  }
+  stage_close(St);
+}
+
+// Near step, multi-bucket frontier vertices: a block per item, a lane per bucket.
+__global__ void __launch_bounds__(kBlock) k_ds_relax_multi(DView F, DsCnt* c, uint32_t S, DsArgs a,
+                                                           uint32_t* fout) {
+  const uint32_t s = S & 3;
+  const uint32_t nm = c->nm[s];
+  if (nm == 0) return;
+  const uint32_t T = c->T, band = c->band, fp = c->fpar, stamp = S + 1;
+  __shared__ Stage St[2];
+  stage_open(St[0], fout, &c->n[(S + 1) & 3]);
+  stage_open(St[1], a.far[fp], &c->nfar[fp]);
+  __syncthreads();
+  for (uint32_t it = blockIdx.x; it < nm; it += gridDim.x) {
+    const uint32_t u = a.multi_v[it];
+    const uint32_t du = ld_u32(a.dist + u);
+    const uint32_t nb = (uint32_t)(slab_ptr(F, u)[15] >> 32);
+    const uint32_t xb = (uint32_t)slab_ptr(F, u)[14];
+    const uint32_t b = a.multi_c[it] * kChunk + threadIdx.x;
+    bool active = b < nb;
+    uint32_t t = b == 0 ? u : xb + b - 1;
+    int nd = b == 0 ? kKeysPerSlab - 1 : kKeysPerSlab;
+    while (__ballot(active)) {
+      Slab sl;
+      uint32_t nr = 0, fr = 0;
+      if (active) {
+        load_slab(F, t, sl);
+        relax_ds(sl, nd, du, a.dist, a.mark, a.fmark, stamp, band, T, nr, fr);
+        t = (uint32_t)sl.w[15];
+        nd = kKeysPerSlab;
+        active = t != kInvalid;
+      }
+      push_found(St[0], nr, sl);
+      push_found(St[1], fr, sl);
+    }
+  }
+  stage_close(St);
+}
+
+// When a step leaves the near frontier empty: the smallest distance on the far pile ...
+__global__ void k_ds_far_min(DsCnt* c, uint32_t S, DsArgs a) {
+  if (c->n[(S + 1) & 3] != 0) return;
+  const uint32_t fp = c->fpar, nf = c->nfar[fp];
+  uint32_t m = kLevelInf;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nf; i += gridDim.x * blockDim.x)
+    m = min(m, ld_u32(a.dist + a.far[fp][i]));
+  wave_min_to(&c->fmin, m);
+}
+
+// ... and the split at T' = fmin + delta: vertices below T' start the next near frontier,
+// the others move to the other pile, stamped with the next band.  The last block to finish
+// commits the new band limit, band number and pile (no block waits for another).
+__global__ void k_ds_split(DsCnt* c, uint32_t S, DsArgs a, uint32_t* fout, uint32_t delta) {
+  if (c->n[(S + 1) & 3] != 0) return;
+  const uint32_t fp = c->fpar, nf = c->nfar[fp];
+  if (nf == 0) return;
+  const uint32_t T2 = (uint32_t)min<uint64_t>((uint64_t)c->fmin + delta, 0xFFFFFFFFull);
+  const uint32_t nb = c->band + 1;
+  __shared__ Stage St[2];
+  __shared__ bool last;
+  stage_open(St[0], fout, &c->n[(S + 1) & 3]);
+  stage_open(St[1], a.far[fp ^ 1], &c->nfar[fp ^ 1]);
+  __syncthreads();
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t base = blockIdx.x * blockDim.x; base < nf; base += stride) {
+    const uint32_t i = base + threadIdx.x;
+    bool to_near = false, keep = false;
+    uint32_t v = 0;
+    if (i < nf) {
+      v = a.far[fp][i];
+      const uint32_t d = ld_u32(a.dist + v);
+      to_near = d < T2;
+      keep = !to_near;
+      if (keep) a.fmark[v] = nb;
+    }
+    stage_push(St[0], to_near, v);
+    stage_push(St[1], keep, v);
+  }
+  stage_close(St);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    last = atomicAdd(&c->done, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (last && threadIdx.x == 0) {
+    __threadfence();
+    c->T = T2;
+    c->band = nb;
+    c->nfar[fp] = 0;
+    c->fpar = fp ^ 1;
+    c->fmin = kLevelInf;
+    c->done = 0;
+  }
+}
+
+size_t dist_ws_bytes(const mk_graph* g) {
+  return 256 + 6 * ((size_t)g->n * 4 + 256) + 2 * (levels_multi_cap(g) * 4 + 256) + 256;
+}
+
 }  // namespace
 
 namespace mk {
@@ -492,5 +712,66 @@ mk_status mk_bfs_levels(mk_graph* g, uint32_t source, uint32_t flags, void* d_ws
 }
 
 size_t mk_bfs_levels_workspace_bytes(const mk_graph* g) { return g ? levels_ws_bytes(g) : 0; }
+
+mk_status mk_sssp_distances(mk_graph* g, uint32_t source, void* d_ws, size_t ws_bytes, uint32_t slot,
+                            uint32_t* d_dist, hipStream_t stream) {
+  if (!g || !d_ws || !d_dist || source >= g->n || slot >= kSlots) return MK_ERR_INVALID_ARG;
+  if (ws_bytes < dist_ws_bytes(g)) return MK_ERR_CAPACITY;
+  if (!g->slot_pin[slot]) {
+    if (hipHostMalloc((void**)&g->slot_pin[slot], 64 * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess)
+      return MK_ERR_HIP;
+  }
+  const uint32_t N = g->n;
+  char* p = reinterpret_cast<char*>(((uintptr_t)d_ws + 255) & ~uintptr_t(255));
+  auto take = [&](size_t bytes) {
+    char* r = p;
+    p += (bytes + 255) & ~size_t(255);
+    return r;
+  };
+  DsCnt* c = reinterpret_cast<DsCnt*>(take(256));
+  uint32_t* q[2];
+  q[0] = reinterpret_cast<uint32_t*>(take((size_t)N * 4));
+  q[1] = reinterpret_cast<uint32_t*>(take((size_t)N * 4));
+  DsArgs a;
+  a.dist = d_dist;
+  a.mark = reinterpret_cast<uint32_t*>(take((size_t)N * 4));
+  a.fmark = reinterpret_cast<uint32_t*>(take((size_t)N * 4));
+  a.far[0] = reinterpret_cast<uint32_t*>(take((size_t)N * 4));
+  a.far[1] = reinterpret_cast<uint32_t*>(take((size_t)N * 4));
+  a.multi_v = reinterpret_cast<uint32_t*>(take(levels_multi_cap(g) * 4));
+  a.multi_c = reinterpret_cast<uint32_t*>(take(levels_multi_cap(g) * 4));
+  const DView F = g->view[VF].d;
+  const uint32_t delta = std::max<uint32_t>(1u, g->sssp_delta);
+  hipLaunchKernelGGL(k_lv_clear, dim3(1), dim3(64), 0, stream, reinterpret_cast<LvCnt*>(c));
+  hipLaunchKernelGGL(k_lv_fill, dim3(blocks_for(N, 4096)), dim3(kBlock), 0, stream, d_dist, N);
+  hipLaunchKernelGGL(k_zero_marks, dim3(blocks_for(N, 4096)), dim3(kBlock), 0, stream, a.mark, a.fmark, N);
+  hipLaunchKernelGGL(k_ds_seed, dim3(1), dim3(64), 0, stream, d_dist, q[0], c, source, delta);
+  MK_LAUNCH(g, "k_ds_seed");
+  uint64_t* pin = g->slot_pin[slot];
+  // every step either relaxes a non-empty near frontier or splits a non-empty far pile, and
+  // positive weights bound the number of distance drops, so the loop ends; the cap is a guard
+  const uint64_t cap = std::min<uint64_t>(64ull * N + 1024, 1ull << 31);  // step stamps stay unique
+  for (uint64_t S = 0;; ++S) {
+    const uint32_t s32 = (uint32_t)S;
+    uint32_t* fin = q[S & 1];
+    uint32_t* fout = q[(S + 1) & 1];
+    hipLaunchKernelGGL(k_ds_relax, dim3(blocks_for(N, 2048)), dim3(kBlock), 0, stream, F, c, s32, a, fin, fout);
+    hipLaunchKernelGGL(k_ds_relax_multi, dim3(2048), dim3(kBlock), 0, stream, F, c, s32, a, fout);
+    hipLaunchKernelGGL(k_ds_far_min, dim3(blocks_for(N, 1024)), dim3(kBlock), 0, stream, c, s32, a);
+    hipLaunchKernelGGL(k_ds_split, dim3(blocks_for(N, 2048)), dim3(kBlock), 0, stream, c, s32, a, fout, delta);
+    MK_LAUNCH(g, "k_ds step");
+    if ((S + 1) % kLevelsPerSync == 0) {
+      MK_HIP(g, hipMemcpyAsync(pin, &c->n[(S + 1) & 3], 4, hipMemcpyDeviceToHost, stream));
+      MK_HIP(g, hipMemcpyAsync(pin + 1, &c->nfar[0], 8, hipMemcpyDeviceToHost, stream));
+      MK_HIP(g, hipStreamSynchronize(stream));
+      const uint32_t* h = reinterpret_cast<const uint32_t*>(pin + 1);
+      if ((uint32_t)pin[0] == 0 && h[0] == 0 && h[1] == 0) break;
+      if (S > cap) return MK_ERR_HIP;
+    }
+  }
+  return MK_OK;
+}
+
+size_t mk_sssp_distances_workspace_bytes(const mk_graph* g) { return g ? dist_ws_bytes(g) : 0; }
 
 }  // extern "C"

@@ -95,6 +95,7 @@ def load():
         "mk_mlp_forward": [vp, vp, u32, vp, vp],
         "mk_traverse_from": [vp, u32, i32, vp, ctypes.c_size_t, u32, vp, vp, vp],
         "mk_bfs_levels": [vp, u32, u32, vp, ctypes.c_size_t, u32, vp, ctypes.POINTER(u32), vp],
+        "mk_sssp_distances": [vp, u32, vp, ctypes.c_size_t, u32, vp, vp],
         "mk_mlp_grad": [vp, vp, vp, vp, u32, vp, vp, ctypes.c_size_t, vp, vp],
         "mk_mlp_adam": [vp, vp, vp, vp, u32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                         ctypes.c_float, u32, vp],
@@ -107,6 +108,8 @@ def load():
     L.mk_traversal_workspace_bytes.argtypes = [vp]
     L.mk_bfs_levels_workspace_bytes.restype = ctypes.c_size_t
     L.mk_bfs_levels_workspace_bytes.argtypes = [vp]
+    L.mk_sssp_distances_workspace_bytes.restype = ctypes.c_size_t
+    L.mk_sssp_distances_workspace_bytes.argtypes = [vp]
     L.mk_mlp_workspace_bytes.restype = ctypes.c_size_t
     L.mk_mlp_workspace_bytes.argtypes = [u32]
     L.mk_status_string.restype = ctypes.c_char_p
@@ -251,6 +254,16 @@ class Graph:
                                       int(slot), _ptr(lv), ctypes.byref(bu), self._s(stream)),
                "mk_bfs_levels")
         return lv, int(bu.value)
+
+    def sssp_distances(self, source: int, ws: Optional[torch.Tensor] = None, slot: int = 0, stream=None):
+        """Distance-only SSSP (32-bit distances, no parents; read-only on the graph)."""
+        if ws is None:
+            ws = torch.empty(self.lib.mk_sssp_distances_workspace_bytes(self.h), dtype=torch.uint8,
+                             device=self.device)
+        di = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        _check(self.lib.mk_sssp_distances(self.h, int(source), _ptr(ws), ws.numel(), int(slot), _ptr(di),
+                                          self._s(stream)), "mk_sssp_distances")
+        return di
 
     # ------------------------------------------------------------ algorithms
     def bfs(self, source: int, mode: int = AUTO, parents: bool = True, stream=None):

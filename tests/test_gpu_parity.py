@@ -501,3 +501,38 @@ def test_bfs_levels_distance_only(top_down_only):
     q = make_pair(g, source=hub, views=native.VIEW_FWD)
     cmp(q, hub, expect_bu=False)
     cmp(Pair(1, [], [], [], source=0), 0, expect_bu=False)
+
+
+@pytest.mark.parametrize("delta", [0, 1, 1 << 30])
+def test_sssp_distances_distance_only(delta):
+    """The distance-only SSSP gives the oracle's distances for any band width (0: the default):
+    R-MAT from the hub and from a low-degree vertex, after an insert and a delete batch, the
+    road-like grid (weights up to 1,000), a chain whose distances reach 0xFFFFFFFE (the
+    largest finite one), a source without out-arcs, and one vertex."""
+    say(f"case: SSSP distances, band width {delta}")
+
+    def cmp(pair, src):
+        di = pair.g.sssp_distances(src)
+        do, _ = pair.o.sssp(src)
+        assert np.array_equal(u32(di), do), f"distances differ at {np.nonzero(u32(di) != do)[0][:10]}"
+
+    g = I.rmat_s(12)
+    hub = I.max_out_degree_vertex(g)
+    p = make_pair(g, source=hub, sssp_delta=delta)
+    cmp(p, hub)
+    deg = np.bincount(u32(g.src), minlength=g.n)
+    low = int(np.nonzero(deg == 1)[0][0])
+    cmp(p, low)
+    wl = I.Workload(g, 41)
+    s, d, w = wl.insert_batch(3000)
+    p.insert(s, d, w)
+    cmp(p, hub)
+    s, d = wl.delete_batch(3000)
+    p.delete(s, d)
+    cmp(p, hub)
+    cmp(p, int(np.nonzero(deg == 0)[0][0]))
+    gg = I.grid_graph(64, 0x4D45524B + 2)
+    cmp(make_pair(gg, sssp_delta=delta), 0)
+    big = 0x7FFFFFFF
+    cmp(Pair(4, [0, 1, 0], [1, 2, 3], [big, big, 0xFFFFFFF0], sssp_delta=delta), 0)
+    cmp(Pair(1, [], [], [], sssp_delta=delta), 0)
