@@ -11,6 +11,13 @@ batches (sizes log-uniform, delete fraction uniform) to a graph and times, with 
 events, each algorithm's incremental update (after the insert part and after the delete
 part) and a recompute on the same graph state.  The fallback policy and the baseline of
 the regret is the plain rule of the paper: always incremental.
+
+The third output is trained by `slab_scale_records`: a graph is built at every slab scale
+(a multiplier of the head-slab count, i.e. load factor 0.7 / scale) and timed on the same
+work; the record carries log2 of the fastest scale, with its two timing targets masked.
+`CostModel.slab_scale` turns the prediction into the nearest measured scale and
+`load_factor_for` into the load factor to build the graph with (the default scale 1 is the
+fallback).
 """
 from __future__ import annotations
 
@@ -27,6 +34,13 @@ from .native import _check, _ptr, load
 
 N_IN, N_HID, N_OUT, N_PARAMS = 12, 64, 3, 5187
 ALGOS = ["bfs", "sssp", "wcc", "pagerank", "tc"]
+BASE_LOAD_FACTOR = 0.7
+SLAB_SCALES = (0.5, 1.0, 2.0)  # head-slab count multipliers tried by slab_scale_records
+
+
+def load_factor_for(scale: float) -> float:
+    """Load factor that builds `scale` times the head slabs of the default."""
+    return BASE_LOAD_FACTOR / scale
 
 
 class MLP:
@@ -104,15 +118,19 @@ class Records:
     algo: List[int] = field(default_factory=list)
     state: List[int] = field(default_factory=list)      # graph-state id (split key)
     slab_scale: List[float] = field(default_factory=list)  # log2 best slab scale, nan if unknown
+    scale_ms: dict = field(default_factory=dict)  # record index -> ms per SLAB_SCALES entry
 
     def arrays(self):
+        """Features, targets (log ms incremental, log ms recompute, log2 slab scale) and their
+        masks (a timing record has no slab scale; a slab-scale record has no timings)."""
         X = np.stack(self.X).astype(np.float32)
         ti = np.asarray(self.t_incr, np.float64)
         tr = np.asarray(self.t_rec, np.float64)
         sc = np.asarray(self.slab_scale, np.float64)
-        T = np.stack([np.log(ti), np.log(tr), np.nan_to_num(sc)], 1).astype(np.float32)
-        M = np.stack([np.ones_like(ti), np.ones_like(tr), (~np.isnan(sc)).astype(np.float64)], 1)
-        return X, T, M.astype(np.float32), ti, tr, np.asarray(self.algo), np.asarray(self.state)
+        with np.errstate(invalid="ignore"):
+            T = np.stack([np.nan_to_num(np.log(ti)), np.nan_to_num(np.log(tr)), np.nan_to_num(sc)], 1)
+        M = np.stack([np.isfinite(ti), np.isfinite(tr), np.isfinite(sc)], 1).astype(np.float32)
+        return X, T.astype(np.float32), M, ti, tr, np.asarray(self.algo), np.asarray(self.state)
 
 
 def _time_call(fn, stream):
@@ -175,6 +193,44 @@ def generate_records(G, wl, source: int, n_batches: int, bmin: int, bmax: int, s
     return rec
 
 
+def slab_scale_records(graphs, seed: int, rec: Optional[Records] = None, state_base: int = 0,
+                       device="cuda") -> Records:
+    """Supervision of the slab-scale output.  Each graph (an `inputs.EdgeList`) is built, with
+    the forward and reverse views, at every scale of SLAB_SCALES and timed on the same work:
+    one insert batch and one delete batch of m/16 arcs, as many queries, a static BFS and a
+    static PageRank from the vertex of largest out-degree.  The record holds the insert
+    batch's features (taken on the default-scale graph) and log2 of the fastest scale."""
+    from . import inputs as I
+    rec = rec or Records()
+    for k, g in enumerate(graphs):
+        wl = I.Workload(g, seed + k)
+        b = max(64, g.m // 16)
+        ins, dels, qs = wl.insert_batch(b), wl.delete_batch(b), wl.query_batch(b)
+        src = I.max_out_degree_vertex(g)
+        feats, ms = None, []
+        for sc in SLAB_SCALES:
+            G = native.Graph(g.n, g.src, g.dst, g.w, views=native.VIEW_FWD | native.VIEW_REV,
+                             load_factor=load_factor_for(sc), device=device)
+            if sc == 1.0:
+                feats = G.batch_features(0, ins, None)
+            st = G.stream
+            t = _time_call(lambda: G.insert_edges(*ins, status=False), st)
+            t += _time_call(lambda: G.delete_edges(*dels, status=False), st)
+            t += _time_call(lambda: G.query_edges(*qs), st)
+            t += _time_call(lambda: G.bfs(src, native.RECOMPUTE), st)
+            t += _time_call(lambda: G.pagerank(mode=native.RECOMPUTE), st)
+            ms.append(t)
+            del G
+        rec.scale_ms[len(rec.X)] = tuple(ms)
+        rec.X.append(feats)
+        rec.t_incr.append(float("nan"))
+        rec.t_rec.append(float("nan"))
+        rec.algo.append(-1)
+        rec.state.append(state_base + k)
+        rec.slab_scale.append(math.log2(SLAB_SCALES[int(np.argmin(ms))]))
+    return rec
+
+
 class CostModel:
     """Trained MLP + the decision rule (incremental iff predicted incremental < recompute)."""
 
@@ -192,6 +248,12 @@ class CostModel:
     def mode_for(self, G, algo: str, ins=None, dels=None) -> int:
         return int(self.choose(G.batch_features(ALGOS.index(algo), ins, dels)[None, :])[0])
 
+    def slab_scale(self, X: np.ndarray) -> np.ndarray:
+        """The measured scale (SLAB_SCALES) nearest in log2 to the prediction, per row."""
+        y = self.predict(X)[:, 2]
+        lg = np.log2(np.asarray(SLAB_SCALES))
+        return np.asarray(SLAB_SCALES)[np.argmin(np.abs(y[:, None] - lg[None, :]), 1)]
+
 
 def regret(t_incr, t_rec, choice):
     """Total time of the choices, of the best choices, and of always-incremental."""
@@ -203,8 +265,22 @@ def regret(t_incr, t_rec, choice):
             "heuristic_regret_ms": float(t_incr.sum() - best.sum())}
 
 
+def scale_regret(cm: CostModel, rec: Records, idx) -> dict:
+    """Total ms of the predicted slab scales, of the best ones and of the default scale 1,
+    over the slab-scale records `idx`."""
+    idx = [i for i in idx if i in rec.scale_ms]
+    if not idx:
+        return {}
+    ms = np.asarray([rec.scale_ms[i] for i in idx])
+    pick = cm.slab_scale(np.stack([rec.X[i] for i in idx]))
+    col = np.asarray([SLAB_SCALES.index(float(p)) for p in pick])
+    return {"policy_ms": float(ms[np.arange(len(idx)), col].sum()), "best_ms": float(ms.min(1).sum()),
+            "default_ms": float(ms[:, SLAB_SCALES.index(1.0)].sum())}
+
+
 def fit(rec: Records, holdout_frac=0.2, epochs=300, seed=0, device="cuda"):
-    """Train on the older graph states, evaluate regret on the newest ones."""
+    """Train on the older graph states, evaluate regret on the newest ones (the slab-scale
+    records, if any, are judged by `scale_regret`)."""
     X, T, M, ti, tr, algo, state = rec.arrays()
     cut = np.quantile(state, 1 - holdout_frac)
     tr_idx = state < cut
@@ -213,5 +289,6 @@ def fit(rec: Records, holdout_frac=0.2, epochs=300, seed=0, device="cuda"):
     hist = mlp.train(torch.from_numpy(X[tr_idx]), torch.from_numpy(T[tr_idx]), torch.from_numpy(M[tr_idx]),
                      epochs=epochs, seed=seed)
     cm = CostModel(mlp)
-    choice = cm.choose(X[te_idx])
-    return cm, hist, regret(ti[te_idx], tr[te_idx], choice)
+    timed = te_idx & np.isfinite(ti) & np.isfinite(tr)
+    choice = cm.choose(X[timed])
+    return cm, hist, regret(ti[timed], tr[timed], choice)

@@ -101,3 +101,32 @@ def test_trained_policy_beats_always_incremental():
     assert hist[-1] < 0.5 * hist[0]
     assert r["policy_ms"] < r["always_incremental_ms"]
     assert r["policy_regret_ms"] < r["heuristic_regret_ms"]
+
+
+def test_slab_scale_output_trains_and_its_picks_hold_up():
+    """The slab-scale output: graphs of several densities (R-MAT with edge factors 4, 16 and
+    48, road-like grids) are built at slab scales 0.5, 1 and 2 and timed on the same work;
+    the MLP (HIP kernels) trains on these records beside timing records, and on graphs it
+    has not seen its picks cost no more than the default scale (10 % slack for timing noise)."""
+    say("case: cost-model slab scale")
+    rec = CM.Records()
+    g0 = I.rmat_s(12)
+    G0 = native.Graph(g0.n, g0.src, g0.dst, g0.w)
+    CM.generate_records(G0, I.Workload(g0, 23), I.max_out_degree_vertex(g0), 12, 10, 2000, seed=3,
+                        rec=rec, state_base=0, algos=["bfs", "wcc"])
+    train = [I.rmat_graph(sc, ef, 100 + 7 * sc + ef) for sc in (13, 14) for ef in (4, 16, 48)]
+    train += [I.grid_side(side, seed=200 + side) for side in (96, 128)]
+    CM.slab_scale_records(train, seed=5, rec=rec, state_base=100)
+    n_train = len(rec.X)
+    test = [I.rmat_graph(14, ef, 300 + ef) for ef in (8, 32)] + [I.grid_side(112, seed=400)]
+    CM.slab_scale_records(test, seed=6, rec=rec, state_base=1000)
+    X, T, M, _, _, _, state = rec.arrays()
+    assert M[:, 2].sum() == len(train) + len(test) and np.isfinite(T).all()
+    cm, hist, _ = CM.fit(rec, holdout_frac=len(test) / len(rec.X) + 1e-6, epochs=300)
+    sr = CM.scale_regret(cm, rec, range(n_train, len(rec.X)))
+    picks = cm.slab_scale(np.stack(rec.X[n_train:]))
+    say(f"  loss {hist[0]:.3f} -> {hist[-1]:.4f}; held-out picks {picks.tolist()}, {sr}; "
+        f"labels {[2 ** v for v in rec.slab_scale[n_train:]]}")
+    assert hist[-1] < 0.5 * hist[0]
+    assert set(picks.tolist()) <= set(CM.SLAB_SCALES)
+    assert sr["policy_ms"] <= 1.1 * sr["default_ms"]
