@@ -688,7 +688,7 @@ bool layout(const mk_config* c, uint64_t m, char* base, mk_graph* g, size_t* tot
   uint64_t* umark = cv.take<uint64_t>(hb_fwd);
   uint32_t* wflag = cv.take<uint32_t>(N);
   char* lvc = cv.take<char>(256);
-  const uint64_t lv_cap = (uint64_t)N + hb_fwd / kBlock + 64;  // >= levels_multi_cap
+  const uint64_t lv_cap = (uint64_t)N + hb_fwd / kGroup + 64;  // >= levels_multi_cap
   uint32_t* lvm0 = cv.take<uint32_t>(lv_cap);
   uint32_t* lvm1 = cv.take<uint32_t>(lv_cap);
   uint64_t* tk0 = nullptr;

@@ -158,4 +158,7 @@ mk_status levels_run(mk_graph* g, uint32_t source, bool allow_bu, const LevelBuf
 // Static BFS of the maintained state through the levels (needs MK_VIEW_REV): levels into
 // `level`, then the tree nodes <level, smallest in-neighbour one level up> into D.
 mk_status bfs_tree_by_levels(mk_graph* g, uint32_t source, uint32_t* level, uint64_t* D, hipStream_t stream);
+// The same for SSSP: distance-only near-far relaxation into `dist`, then <dist, smallest
+// in-neighbour u with dist(u) + w(u, v) = dist(v)> into D.
+mk_status sssp_tree_by_distances(mk_graph* g, uint32_t source, uint32_t* dist, uint64_t* D, hipStream_t stream);
 }  // namespace mk

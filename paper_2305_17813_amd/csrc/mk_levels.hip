@@ -32,7 +32,7 @@ using namespace mk;
 namespace {
 
 constexpr uint32_t kLevelInf = 0xFFFFFFFFu;
-constexpr uint32_t kChunk = kBlock;       // buckets of a multi-bucket vertex per work item
+constexpr uint32_t kChunk = kGroup;       // buckets of a multi-bucket vertex per work item
 constexpr uint32_t kLevelsPerSync = 4;
 
 // Device counters of one call (in the caller's workspace).  Level L uses slot L mod 4.
@@ -145,7 +145,7 @@ __device__ inline void block_add(unsigned long long* acc, unsigned long long v, 
 }
 
 // Top-down step, single-bucket frontier vertices: a lane walks its vertex's chain.  A vertex
-// with several buckets becomes ceil(nb / kChunk) work items for k_lv_td_multi.
+// with several buckets becomes ceil(nb / 16) work items for k_lv_td_multi.
 __global__ void __launch_bounds__(kBlock) k_lv_td(DView F, LvCnt* c, uint32_t L, uint32_t* level,
                                                   const uint32_t* fin, uint32_t* fout, uint32_t* mu_,
                                                   uint32_t* mc_) {
@@ -191,7 +191,8 @@ __global__ void __launch_bounds__(kBlock) k_lv_td(DView F, LvCnt* c, uint32_t L,
   block_add(&acc, arcs, &c->arcs[(L + 1) & 3]);
 }
 
-// Top-down step, multi-bucket frontier vertices: a block per work item, a lane per bucket.
+// Top-down step, multi-bucket frontier vertices: a 16-lane group per work item (16 buckets),
+// a lane per bucket chain.
 __global__ void __launch_bounds__(kBlock) k_lv_td_multi(DView F, LvCnt* c, uint32_t L, uint32_t* level,
                                                         uint32_t* fout, const uint32_t* mu_,
                                                         const uint32_t* mc_) {
@@ -205,13 +206,17 @@ __global__ void __launch_bounds__(kBlock) k_lv_td_multi(DView F, LvCnt* c, uint3
   if (threadIdx.x == 0) acc = 0;
   __syncthreads();
   unsigned long long arcs = 0;
-  for (uint32_t it = blockIdx.x; it < nm; it += gridDim.x) {
-    const uint32_t u = mu_[it];
-    const uint64_t link = slab_ptr(F, u)[15];
-    const uint32_t nb = (uint32_t)(link >> 32);
-    const uint32_t xb = (uint32_t)slab_ptr(F, u)[14];
-    const uint32_t b = mc_[it] * kChunk + threadIdx.x;
-    bool active = b < nb;
+  const uint32_t gib = threadIdx.x / kGroup;
+  for (uint32_t base = blockIdx.x * kGroupsPerBlock; base < nm; base += gridDim.x * kGroupsPerBlock) {
+    const uint32_t it = base + gib;  // one item per 16-lane group, a lane per bucket
+    uint32_t u = 0, nb = 0, xb = 0, b = 0;
+    if (it < nm) {
+      u = mu_[it];
+      nb = (uint32_t)(slab_ptr(F, u)[15] >> 32);
+      xb = (uint32_t)slab_ptr(F, u)[14];
+      b = mc_[it] * kChunk + glane();
+    }
+    bool active = it < nm && b < nb;
     uint32_t t = b == 0 ? u : xb + b - 1;
     int nd = b == 0 ? kKeysPerSlab - 1 : kKeysPerSlab;
     while (__ballot(active)) {
@@ -331,10 +336,20 @@ __global__ void k_lv_items(const uint32_t* nbk, const uint32_t* heavy, const uin
     cnt[j] = (nbk[heavy[j]] + kPrItem - 1) / kPrItem;
 }
 
-// Parent of every reached vertex: the smallest in-neighbour one level up (the parent rule
-// of the tree variant).  One lane per single-bucket vertex, a 16-lane group per vertex of
-// 2 .. kHeavyBuckets buckets, and the heavy vertices' bucket items spread over every group,
-// which fold their minima in with a 64-bit atomic minimum.
+// Is u (distance du, arc weight w) a parent of a vertex at distance dv: du + w == dv, with
+// the sum saturated below INF as the tree traversal does; BFS counts every arc as 1.
+template <bool kUnit>
+__device__ inline bool parent_arc(uint32_t du, uint64_t word, uint32_t dv) {
+  if (du == kLevelInf) return false;
+  const uint64_t w = kUnit ? 1ull : (word >> 32);
+  return (uint32_t)min<uint64_t>((uint64_t)du + w, 0xFFFFFFFEull) == dv;
+}
+
+// Parent of every reached vertex: the smallest in-neighbour u with dist(u) + w(u, v) =
+// dist(v) (the parent rule of the tree variant).  One lane per single-bucket vertex, a
+// 16-lane group per vertex of 2 .. kHeavyBuckets buckets, and the heavy vertices' bucket
+// items spread over every group, which fold their minima in with a 64-bit atomic minimum.
+template <bool kUnit>
 __global__ void __launch_bounds__(kBlock) k_lv_parents(DView R, const uint32_t* level, uint64_t* D, uint32_t nv,
                                                        uint32_t src, const uint32_t* heavy,
                                                        const uint32_t* nheavy, const uint32_t* hoff,
@@ -355,7 +370,7 @@ __global__ void __launch_bounds__(kBlock) k_lv_parents(DView R, const uint32_t* 
       }
 #pragma unroll
       for (int j = 0; j < kKeysPerSlab; ++j)
-        if (lu[j] + 1 == lv) best = min(best, (uint32_t)sl.w[j]);
+        if (parent_arc<kUnit>(lu[j], sl.w[j], lv)) best = min(best, (uint32_t)sl.w[j]);
       t = (uint32_t)sl.w[15];
       if (t == kInvalid) break;
     }
@@ -371,7 +386,7 @@ __global__ void __launch_bounds__(kBlock) k_lv_parents(DView R, const uint32_t* 
     uint64_t best = kTreeNone;
     for_each_slab(R, v, [&](uint64_t w, bool data) {
       const uint32_t u = (uint32_t)w;
-      if (data && valid_key(u) && level[u] + 1 == lv) best = min(best, (uint64_t)u);
+      if (data && valid_key(u) && parent_arc<kUnit>(level[u], w, lv)) best = min(best, (uint64_t)u);
     });
     best = gmin_u64(best);
     if (glane() == 0) D[v] = ((uint64_t)lv << 32) | (uint32_t)best;
@@ -392,7 +407,7 @@ __global__ void __launch_bounds__(kBlock) k_lv_parents(DView R, const uint32_t* 
     uint64_t best = kTreeNone;
     for_each_bucket_range(R, v, b0, b0 + kPrItem, [&](uint64_t w, bool data) {
       const uint32_t u = (uint32_t)w;
-      if (data && valid_key(u) && level[u] + 1 == lv) best = min(best, (uint64_t)u);
+      if (data && valid_key(u) && parent_arc<kUnit>(level[u], w, lv)) best = min(best, (uint64_t)u);
     });
     best = gmin_u64(best);
     if (glane() == 0 && best != kTreeNone) amin64(D + v, ((uint64_t)lv << 32) | best);
@@ -465,7 +480,7 @@ struct DsArgs {
   uint32_t *dist, *mark, *fmark, *far[2], *multi_v, *multi_c;
 };
 
-// Near step, single-bucket frontier vertices (a lane each); others become 256-bucket items.
+// Near step, single-bucket frontier vertices (a lane each); others become 16-bucket items.
 __global__ void __launch_bounds__(kBlock) k_ds_relax(DView F, DsCnt* c, uint32_t S, DsArgs a, const uint32_t* fin,
                                                      uint32_t* fout) {
   const uint32_t s = S & 3;
@@ -513,7 +528,7 @@ __global__ void __launch_bounds__(kBlock) k_ds_relax(DView F, DsCnt* c, uint32_t
   stage_close(St);
 }
 
-// Near step, multi-bucket frontier vertices: a block per item, a lane per bucket.
+// Near step, multi-bucket frontier vertices: a 16-lane group per item, a lane per bucket.
 __global__ void __launch_bounds__(kBlock) k_ds_relax_multi(DView F, DsCnt* c, uint32_t S, DsArgs a,
                                                            uint32_t* fout) {
   const uint32_t s = S & 3;
@@ -524,13 +539,18 @@ __global__ void __launch_bounds__(kBlock) k_ds_relax_multi(DView F, DsCnt* c, ui
   stage_open(St[0], fout, &c->n[(S + 1) & 3]);
   stage_open(St[1], a.far[fp], &c->nfar[fp]);
   __syncthreads();
-  for (uint32_t it = blockIdx.x; it < nm; it += gridDim.x) {
-    const uint32_t u = a.multi_v[it];
-    const uint32_t du = ld_u32(a.dist + u);
-    const uint32_t nb = (uint32_t)(slab_ptr(F, u)[15] >> 32);
-    const uint32_t xb = (uint32_t)slab_ptr(F, u)[14];
-    const uint32_t b = a.multi_c[it] * kChunk + threadIdx.x;
-    bool active = b < nb;
+  const uint32_t gib = threadIdx.x / kGroup;
+  for (uint32_t base = blockIdx.x * kGroupsPerBlock; base < nm; base += gridDim.x * kGroupsPerBlock) {
+    const uint32_t it = base + gib;  // one item per 16-lane group, a lane per bucket
+    uint32_t u = 0, du = 0, nb = 0, xb = 0, b = 0;
+    if (it < nm) {
+      u = a.multi_v[it];
+      du = ld_u32(a.dist + u);
+      nb = (uint32_t)(slab_ptr(F, u)[15] >> 32);
+      xb = (uint32_t)slab_ptr(F, u)[14];
+      b = a.multi_c[it] * kChunk + glane();
+    }
+    bool active = it < nm && b < nb;
     uint32_t t = b == 0 ? u : xb + b - 1;
     int nd = b == 0 ? kKeysPerSlab - 1 : kKeysPerSlab;
     while (__ballot(active)) {
@@ -651,8 +671,31 @@ mk_status levels_run(mk_graph* g, uint32_t source, bool allow_bu, const LevelBuf
   return MK_OK;
 }
 
-mk_status bfs_tree_by_levels(mk_graph* g, uint32_t source, uint32_t* level, uint64_t* D, hipStream_t stream) {
+// Tree nodes <dist, smallest parent> from finished distances (BFS levels when kUnit).
+template <bool kUnit>
+mk_status tree_from_dist(mk_graph* g, uint32_t source, const uint32_t* dist, uint64_t* D, hipStream_t stream) {
   const uint32_t N = g->n;
+  const DView R = g->view[VR].d;
+  uint32_t* heavy = g->fq[2];
+  uint32_t* hcnt = g->fq[3];
+  uint32_t* hoff = g->fq[4];
+  uint32_t* nh = reinterpret_cast<LvCnt*>(g->lv_cnt)->pad;
+  hipLaunchKernelGGL(k_lv_clear, dim3(1), dim3(64), 0, stream, reinterpret_cast<LvCnt*>(g->lv_cnt));
+  hipLaunchKernelGGL(k_lv_tree_init, dim3(blocks_for(N, 4096)), dim3(kBlock), 0, stream, dist, D, N, source);
+  hipLaunchKernelGGL(k_lv_heavy, dim3(blocks_for(N, 4096)), dim3(kBlock), 0, stream, R.nbk, dist, N, source,
+                     heavy, nh);
+  hipLaunchKernelGGL(k_lv_items, dim3(blocks_for(N, 1024)), dim3(kBlock), 0, stream, R.nbk, heavy, nh, hcnt);
+  size_t tb = g->scan_tmp_bytes;
+  if (rocprim::exclusive_scan(g->scan_tmp, tb, hcnt, hoff, 0u, (size_t)N, rocprim::plus<uint32_t>(), stream) !=
+      hipSuccess)
+    return MK_ERR_HIP;
+  hipLaunchKernelGGL(k_lv_parents<kUnit>, dim3(4096), dim3(kBlock), 0, stream, R, dist, D, N, source, heavy, nh,
+                     hoff, hcnt);
+  MK_LAUNCH(g, "k_lv_parents");
+  return MK_OK;
+}
+
+mk_status bfs_tree_by_levels(mk_graph* g, uint32_t source, uint32_t* level, uint64_t* D, hipStream_t stream) {
   LevelBufs b;
   b.cnt = g->lv_cnt;
   b.q[0] = g->fq[0];
@@ -661,24 +704,58 @@ mk_status bfs_tree_by_levels(mk_graph* g, uint32_t source, uint32_t* level, uint
   b.multi_c = g->lv_multi[1];
   mk_status s = levels_run(g, source, true, b, level, g->h_pin, nullptr, stream);
   if (s != MK_OK) return s;
-  const DView R = g->view[VR].d;
-  uint32_t* heavy = g->fq[2];
-  uint32_t* hcnt = g->fq[3];
-  uint32_t* hoff = g->fq[4];
-  uint32_t* nh = reinterpret_cast<LvCnt*>(g->lv_cnt)->pad;
-  hipLaunchKernelGGL(k_lv_clear, dim3(1), dim3(64), 0, stream, reinterpret_cast<LvCnt*>(g->lv_cnt));
-  hipLaunchKernelGGL(k_lv_tree_init, dim3(blocks_for(N, 4096)), dim3(kBlock), 0, stream, level, D, N, source);
-  hipLaunchKernelGGL(k_lv_heavy, dim3(blocks_for(N, 4096)), dim3(kBlock), 0, stream, R.nbk, level, N, source,
-                     heavy, nh);
-  hipLaunchKernelGGL(k_lv_items, dim3(blocks_for(N, 1024)), dim3(kBlock), 0, stream, R.nbk, heavy, nh, hcnt);
-  size_t tb = g->scan_tmp_bytes;
-  if (rocprim::exclusive_scan(g->scan_tmp, tb, hcnt, hoff, 0u, (size_t)N, rocprim::plus<uint32_t>(), stream) !=
-      hipSuccess)
-    return MK_ERR_HIP;
-  hipLaunchKernelGGL(k_lv_parents, dim3(4096), dim3(kBlock), 0, stream, R, level, D, N, source, heavy, nh, hoff,
-                     hcnt);
-  MK_LAUNCH(g, "k_lv_parents");
+  return tree_from_dist<true>(g, source, level, D, stream);
+}
+
+// Every step either relaxes a non-empty near frontier or splits a non-empty far pile, and
+// positive weights bound the number of distance drops, so the loop ends; the cap is a guard
+// (and keeps the step stamps unique).
+mk_status dist_run(mk_graph* g, uint32_t source, void* cnt, uint32_t* const q[2], const DsArgs& a,
+                   uint64_t* pin, hipStream_t stream) {
+  const uint32_t N = g->n;
+  DsCnt* c = reinterpret_cast<DsCnt*>(cnt);
+  const DView F = g->view[VF].d;
+  const uint32_t delta = std::max<uint32_t>(1u, g->sssp_delta);
+  hipLaunchKernelGGL(k_lv_clear, dim3(1), dim3(64), 0, stream, reinterpret_cast<LvCnt*>(c));
+  hipLaunchKernelGGL(k_lv_fill, dim3(blocks_for(N, 4096)), dim3(kBlock), 0, stream, a.dist, N);
+  hipLaunchKernelGGL(k_zero_marks, dim3(blocks_for(N, 4096)), dim3(kBlock), 0, stream, a.mark, a.fmark, N);
+  hipLaunchKernelGGL(k_ds_seed, dim3(1), dim3(64), 0, stream, a.dist, q[0], c, source, delta);
+  MK_LAUNCH(g, "k_ds_seed");
+  const uint64_t cap = std::min<uint64_t>(64ull * N + 1024, 1ull << 31);
+  for (uint64_t S = 0;; ++S) {
+    const uint32_t s32 = (uint32_t)S;
+    uint32_t* fin = q[S & 1];
+    uint32_t* fout = q[(S + 1) & 1];
+    hipLaunchKernelGGL(k_ds_relax, dim3(blocks_for(N, 2048)), dim3(kBlock), 0, stream, F, c, s32, a, fin, fout);
+    hipLaunchKernelGGL(k_ds_relax_multi, dim3(2048), dim3(kBlock), 0, stream, F, c, s32, a, fout);
+    hipLaunchKernelGGL(k_ds_far_min, dim3(blocks_for(N, 1024)), dim3(kBlock), 0, stream, c, s32, a);
+    hipLaunchKernelGGL(k_ds_split, dim3(blocks_for(N, 2048)), dim3(kBlock), 0, stream, c, s32, a, fout, delta);
+    MK_LAUNCH(g, "k_ds step");
+    if ((S + 1) % kLevelsPerSync == 0) {
+      MK_HIP(g, hipMemcpyAsync(pin, &c->n[(S + 1) & 3], 4, hipMemcpyDeviceToHost, stream));
+      MK_HIP(g, hipMemcpyAsync(pin + 1, &c->nfar[0], 8, hipMemcpyDeviceToHost, stream));
+      MK_HIP(g, hipStreamSynchronize(stream));
+      const uint32_t* h = reinterpret_cast<const uint32_t*>(pin + 1);
+      if ((uint32_t)pin[0] == 0 && h[0] == 0 && h[1] == 0) break;
+      if (S > cap) return MK_ERR_HIP;
+    }
+  }
   return MK_OK;
+}
+
+mk_status sssp_tree_by_distances(mk_graph* g, uint32_t source, uint32_t* dist, uint64_t* D, hipStream_t stream) {
+  uint32_t* q[2] = {g->fq[0], g->fq[1]};
+  DsArgs a;
+  a.dist = dist;
+  a.mark = g->fq[2];  // scratch here; the maintained traversals' stamps stay untouched
+  a.fmark = g->fq[3];
+  a.far[0] = g->far[0];
+  a.far[1] = g->far[1];
+  a.multi_v = g->lv_multi[0];
+  a.multi_c = g->lv_multi[1];
+  mk_status s = dist_run(g, source, g->lv_cnt, q, a, g->h_pin, stream);
+  if (s != MK_OK) return s;
+  return tree_from_dist<false>(g, source, dist, D, stream);
 }
 
 }  // namespace mk
@@ -740,36 +817,7 @@ mk_status mk_sssp_distances(mk_graph* g, uint32_t source, void* d_ws, size_t ws_
   a.far[1] = reinterpret_cast<uint32_t*>(take((size_t)N * 4));
   a.multi_v = reinterpret_cast<uint32_t*>(take(levels_multi_cap(g) * 4));
   a.multi_c = reinterpret_cast<uint32_t*>(take(levels_multi_cap(g) * 4));
-  const DView F = g->view[VF].d;
-  const uint32_t delta = std::max<uint32_t>(1u, g->sssp_delta);
-  hipLaunchKernelGGL(k_lv_clear, dim3(1), dim3(64), 0, stream, reinterpret_cast<LvCnt*>(c));
-  hipLaunchKernelGGL(k_lv_fill, dim3(blocks_for(N, 4096)), dim3(kBlock), 0, stream, d_dist, N);
-  hipLaunchKernelGGL(k_zero_marks, dim3(blocks_for(N, 4096)), dim3(kBlock), 0, stream, a.mark, a.fmark, N);
-  hipLaunchKernelGGL(k_ds_seed, dim3(1), dim3(64), 0, stream, d_dist, q[0], c, source, delta);
-  MK_LAUNCH(g, "k_ds_seed");
-  uint64_t* pin = g->slot_pin[slot];
-  // every step either relaxes a non-empty near frontier or splits a non-empty far pile, and
-  // positive weights bound the number of distance drops, so the loop ends; the cap is a guard
-  const uint64_t cap = std::min<uint64_t>(64ull * N + 1024, 1ull << 31);  // step stamps stay unique
-  for (uint64_t S = 0;; ++S) {
-    const uint32_t s32 = (uint32_t)S;
-    uint32_t* fin = q[S & 1];
-    uint32_t* fout = q[(S + 1) & 1];
-    hipLaunchKernelGGL(k_ds_relax, dim3(blocks_for(N, 2048)), dim3(kBlock), 0, stream, F, c, s32, a, fin, fout);
-    hipLaunchKernelGGL(k_ds_relax_multi, dim3(2048), dim3(kBlock), 0, stream, F, c, s32, a, fout);
-    hipLaunchKernelGGL(k_ds_far_min, dim3(blocks_for(N, 1024)), dim3(kBlock), 0, stream, c, s32, a);
-    hipLaunchKernelGGL(k_ds_split, dim3(blocks_for(N, 2048)), dim3(kBlock), 0, stream, c, s32, a, fout, delta);
-    MK_LAUNCH(g, "k_ds step");
-    if ((S + 1) % kLevelsPerSync == 0) {
-      MK_HIP(g, hipMemcpyAsync(pin, &c->n[(S + 1) & 3], 4, hipMemcpyDeviceToHost, stream));
-      MK_HIP(g, hipMemcpyAsync(pin + 1, &c->nfar[0], 8, hipMemcpyDeviceToHost, stream));
-      MK_HIP(g, hipStreamSynchronize(stream));
-      const uint32_t* h = reinterpret_cast<const uint32_t*>(pin + 1);
-      if ((uint32_t)pin[0] == 0 && h[0] == 0 && h[1] == 0) break;
-      if (S > cap) return MK_ERR_HIP;
-    }
-  }
-  return MK_OK;
+  return dist_run(g, source, c, q, a, g->slot_pin[slot], stream);
 }
 
 size_t mk_sssp_distances_workspace_bytes(const mk_graph* g) { return g ? dist_ws_bytes(g) : 0; }

@@ -796,12 +796,14 @@ mk_status traverse(mk_graph* g, AlgoState& st, uint64_t* D, uint32_t source, uin
   const bool full = mode == MK_RECOMPUTE || !st.valid || st.source != source || p.lost ||
                     p.kinds == 3 || (p.kinds == 2 && !can_dec);
   if (full) {
-    // BFS of a graph with the reverse view and a mean out-degree of at least 8:
-    // direction-optimizing levels, then the parents.  On sparser graphs bottom-up steps do
-    // not pay (a road network takes none), and one tree pass beats levels plus parents.
-    const bool by_levels = kUnit && can_dec && g->m0 >= 8ull * N;
-    mk_status s = by_levels ? bfs_tree_by_levels(g, source, d_out, D, stream)
-                            : static_from<kUnit>(g, c, source, stream);
+    // A graph with the reverse view and a mean out-degree of at least 8: distances first
+    // (direction-optimizing BFS levels, or the distance-only SSSP), then every vertex's
+    // parent from its in-arcs.  On sparser graphs (a road network) the tree traversal in
+    // one pass beats distances plus parents.
+    const bool by_dist = can_dec && g->m0 >= 8ull * N;
+    mk_status s = !by_dist ? static_from<kUnit>(g, c, source, stream)
+                  : kUnit  ? bfs_tree_by_levels(g, source, d_out, D, stream)
+                           : sssp_tree_by_distances(g, source, d_out, D, stream);
     if (s != MK_OK) return s;
   } else if (!p.list.empty()) {
     const uint32_t stamp0 = ++g->stamp;
