@@ -144,6 +144,9 @@ mk_status mk_incr_bfs(mk_graph* g, uint32_t source, uint32_t* d_level, uint32_t*
 /* Single-source shortest paths (section 4.2, the dynamic SSSP algorithm), maintained as
  * for BFS with the arc weights.  The <distance, parent> pair of each vertex is one 64-bit
  * word updated by atomic minimum, so among equal distances the smallest parent id wins.
+ * A recompute on a graph with MK_VIEW_REV and a mean initial out-degree of at least 8 runs
+ * the distances of mk_sssp_distances and then gives each vertex the smallest in-neighbour
+ * u with dist(u) + w(u, v) = dist(v); the result is the same.
  *   d_dist   : N uint32 (device): distance (saturates at 0xFFFFFFFE), 0xFFFFFFFF if
  *              unreachable.
  *   d_parent : NULL or N uint32 (device), as for BFS. */
