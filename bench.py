@@ -98,7 +98,7 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; --gpus must be 1",
+        print(json.dumps({"error": "bench.py runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         log("bench.py runs on exactly one GPU: multi-GPU sharding is a design only.")
         sys.exit(2)
