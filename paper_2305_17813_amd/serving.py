@@ -15,8 +15,8 @@ loop keeps the graph resident in HBM and:
   on the device while new requests keep being admitted;
 * replays pre-captured HIP graphs for query batches (one per slot and power-of-two size
   class; a short batch is padded with an out-of-range id, which a query reports absent);
-* answers a BFS from any other source with hop distances (the direction-optimizing levels)
-  and an SSSP from any other source with distances and parents, in the slot's workspace;
+* answers a BFS or SSSP from any other source with distances only (the direction-optimizing
+  levels, or the distance-only SSSP), in the slot's workspace;
 * brings the maintained algorithms (PageRank, and BFS/SSSP from the tracked source) up to
   date incrementally or by recompute, as the learned cost model decides, or always
   incrementally without it;
@@ -176,7 +176,7 @@ class Server:
         self.max_merge = max_merge
         self.keep = keep_results
         self.streams = [torch.cuda.Stream(G.device) for _ in range(n_slots)]
-        ws_bytes = max(G.lib.mk_traversal_workspace_bytes(G.h), G.lib.mk_bfs_levels_workspace_bytes(G.h))
+        ws_bytes = max(G.lib.mk_bfs_levels_workspace_bytes(G.h), G.lib.mk_sssp_distances_workspace_bytes(G.h))
         self.ws = [torch.empty(ws_bytes, dtype=torch.uint8, device=G.device) for _ in range(n_slots)]
         self.qg = QueryGraphs(G, self.streams) if capture_queries else None
         self.pool = ThreadPoolExecutor(max_workers=n_slots)
@@ -260,10 +260,10 @@ class Server:
                            else self.G.query_edges(r.src, r.dst, stream=stream))
                 elif r.kind == "pagerank" or r.source == self.tracked:
                     res = self._maintained(r, stream)
-                elif r.kind == "bfs":  # hop distances only: the direction-optimizing levels
+                elif r.kind == "bfs":  # distances only: the direction-optimizing levels
                     res = (self.G.bfs_levels(r.source, False, self.ws[slot], slot, stream)[0], None)
-                else:
-                    res = self.G.traverse_from(r.source, True, self.ws[slot], slot, stream)
+                else:  # distances only: the distance-only SSSP
+                    res = (self.G.sssp_distances(r.source, self.ws[slot], slot, stream), None)
                 stream.synchronize()
             r.t_done = time.perf_counter() - t0
             r.result = res if self.keep else None

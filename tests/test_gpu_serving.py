@@ -47,8 +47,8 @@ def _compare(reqs, alone):
         elif r.kind == "pagerank":
             l1 = float((r.result[0].double() - a[0].double()).abs().sum())
             assert l1 <= PR_L1_TOL, l1
-        elif r.result[1] is None:  # a BFS from an untracked source answers levels only
-            assert r.kind == "bfs" and torch.equal(r.result[0], a[0])
+        elif r.result[1] is None:  # a BFS / SSSP from an untracked source answers distances
+            assert r.kind in ("bfs", "sssp") and torch.equal(r.result[0], a[0])
         else:
             assert torch.equal(r.result[0], a[0]) and torch.equal(r.result[1], a[1]), r.kind
 
