@@ -3,6 +3,8 @@
 Integers (statuses, membership, weights, BFS levels, SSSP distances, parents, component
 labels, triangle counts) must be bit-exact; PageRank must be within 1e-6 in L1.
 """
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -536,3 +538,32 @@ def test_sssp_distances_distance_only(delta):
     big = 0x7FFFFFFF
     cmp(Pair(4, [0, 1, 0], [1, 2, 3], [big, big, 0xFFFFFFF0], sssp_delta=delta), 0)
     cmp(Pair(1, [], [], [], sssp_delta=delta), 0)
+
+
+def test_distance_only_entry_points_reject_bad_arguments():
+    """Host-side checks of the distance-only traversals: a source out of range, a slot out of
+    range, a workspace one byte short and an unknown flag are refused with their statuses."""
+    say("case: distance-only entry points, bad arguments")
+    g = I.rmat_s(10)
+    G = native.Graph(g.n, g.src, g.dst, g.w)
+    lib = G.lib
+    n_lv, n_ds = lib.mk_bfs_levels_workspace_bytes(G.h), lib.mk_sssp_distances_workspace_bytes(G.h)
+    ws = torch.empty(max(n_lv, n_ds), dtype=torch.uint8, device=G.device)
+    out = torch.empty(g.n, dtype=torch.int32, device=G.device)
+    p = lambda t: ctypes.c_void_p(t.data_ptr())
+    s = ctypes.c_void_p(G.stream.cuda_stream)
+    bu = ctypes.c_uint32()
+    assert lib.mk_bfs_levels(G.h, g.n, 0, p(ws), n_lv, 0, p(out), ctypes.byref(bu), s) == 1
+    assert lib.mk_bfs_levels(G.h, 0, 0, p(ws), n_lv, 16, p(out), ctypes.byref(bu), s) == 1
+    assert lib.mk_bfs_levels(G.h, 0, 2, p(ws), n_lv, 0, p(out), ctypes.byref(bu), s) == 1
+    assert lib.mk_bfs_levels(G.h, 0, 0, p(ws), n_lv - 1, 0, p(out), ctypes.byref(bu), s) == 3
+    assert lib.mk_sssp_distances(G.h, g.n, p(ws), n_ds, 0, p(out), s) == 1
+    assert lib.mk_sssp_distances(G.h, 0, p(ws), n_ds, 16, p(out), s) == 1
+    assert lib.mk_sssp_distances(G.h, 0, p(ws), n_ds - 1, 0, p(out), s) == 3
+    lab = torch.empty(g.n, dtype=torch.int32, device=G.device)
+    assert lib.mk_incr_wcc_scheme(G.h, p(lab), 0, 4, s) == 1
+    # the same calls with good arguments still work afterwards
+    lv, _ = G.bfs_levels(0, ws=ws)
+    di = G.sssp_distances(0, ws=ws)
+    torch.cuda.synchronize()
+    assert int(lv[0].item()) == 0 and int(di[0].item()) == 0
