@@ -108,7 +108,8 @@ mk_status mk_graph_destroy(mk_graph* g);
  *   d_src/d_dst/d_w : n arcs (device).  d_w may be NULL (weight 1).
  *   d_status        : NULL or n bytes (device): 1 inserted, 0 already present (weight
  *                     unchanged), 2 rejected (id >= N, self-loop or reserved id).  Copies
- *                     of one arc inside a batch: exactly one copy reports 1.
+ *                     of one arc inside a batch: exactly one copy reports 1; they must carry
+ *                     one weight (each view keeps the copy that wins its own race).
  * MK_ERR_OUT_OF_SLABS when the pool might not hold the batch (nothing applied);
  * MK_ERR_CAPACITY when n exceeds the change-log capacity. */
 mk_status mk_insert_edges(mk_graph* g, const uint32_t* d_src, const uint32_t* d_dst,

@@ -194,31 +194,58 @@ __global__ void __launch_bounds__(kBlock) k_insert_fwd(DView F, const uint32_t* 
   log.uf[op] = 0;
 }
 
-// The other views of an insert batch: three lanes per applied arc (reverse view, and
-// both directions of the undirected view).  The canonical undirected direction (small
-// id -> large id) decides which op reports the undirected edge as new.
-__global__ void __launch_bounds__(kBlock) k_insert_aux(DView R, DView U, uint32_t views, Log log,
-                                                       uint64_t n, uint32_t* overflow) {
+// Every view of an insert batch in one launch, four lanes per arc: the forward view (status
+// and change log), the reverse view, and both directions of the undirected view.  The other
+// views take the arc straight from the batch rather than waiting for the forward view's
+// status: the views hold one arc set, so an arc the forward view already has is in the
+// others too and its insert there is a no-op.  Copies of one arc inside a batch must carry
+// one weight, since each view keeps the copy that wins its own CAS.  The canonical
+// undirected direction (small id -> large id) decides which op reports the undirected edge
+// as new.
+__global__ void __launch_bounds__(kBlock) k_insert_all(DView F, DView R, DView U, uint32_t views,
+                                                       const uint32_t* __restrict__ src,
+                                                       const uint32_t* __restrict__ dst,
+                                                       const uint32_t* __restrict__ w, uint64_t n,
+                                                       uint32_t nv, uint8_t* status, Log log,
+                                                       uint32_t* overflow) {
   const uint64_t gid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-  const uint64_t op = gid / 3;
-  const int task = (int)(gid % 3);
+  const uint64_t op = gid >> 2;
+  const int task = (int)(gid & 3);
   if (op >= n) return;
-  if (task == 0 && !(views & MK_VIEW_REV)) return;
-  if (task != 0 && !(views & MK_VIEW_UND)) return;
-  if (log.st[op] != 1) return;
-  const uint32_t s = log.s[op], d = log.d[op];
-  int r;
+  if (task == 1 && !(views & MK_VIEW_REV)) return;
+  if (task >= 2 && !(views & MK_VIEW_UND)) return;
+  const uint32_t s = src[op], d = dst[op];
+  const uint32_t wt = w ? w[op] : 1u;
+  const bool bad = bad_arc(s, d, nv);
   if (task == 0) {
-    r = insert_key(R, d, s, log.w[op]);
+    int st = 2;
+    if (!bad) st = insert_key(F, s, d, wt);
+    if (st == 1) atomicAdd(F.deg + s, 1u);
+    if (st == 3) atomicOr(overflow, 1u);
+    if (status) status[op] = (uint8_t)st;
+    log.s[op] = s;
+    log.d[op] = d;
+    log.w[op] = wt;
+    log.st[op] = (uint8_t)st;
+    if (!(views & MK_VIEW_UND)) log.uf[op] = 0;
+    return;
+  }
+  if (bad) {
+    if (task == 2) log.uf[op] = 0;
+    return;
+  }
+  int r;
+  if (task == 1) {
+    r = insert_key(R, d, s, wt);
     if (r == 1) atomicAdd(R.deg + d, 1u);
   } else {
-    const uint32_t a = task == 1 ? min(s, d) : max(s, d);
-    const uint32_t b = task == 1 ? max(s, d) : min(s, d);
+    const uint32_t a = task == 2 ? min(s, d) : max(s, d);
+    const uint32_t b = task == 2 ? max(s, d) : min(s, d);
     r = insert_key(U, a, b, 1u);
     if (r == 1) atomicAdd(U.deg + a, 1u);
-    if (task == 1) log.uf[op] = r == 1;
+    if (task == 2) log.uf[op] = r == 1;
   }
-  if (r == 3) atomicOr(overflow, task == 0 ? 2u : 4u);
+  if (r == 3) atomicOr(overflow, task == 1 ? 2u : 4u);
 }
 
 __global__ void __launch_bounds__(kBlock) k_delete_fwd(DView F, const uint32_t* __restrict__ src,
@@ -828,11 +855,12 @@ DView dv(const mk_graph* g, int v) { return g->view[v].on ? g->view[v].d : g->vi
 
 void launch_insert(mk_graph* g, const uint32_t* s, const uint32_t* d, const uint32_t* w, uint64_t n,
                    uint8_t* status, const Log& lg, hipStream_t stream) {
-  hipLaunchKernelGGL(k_insert_fwd, dim3(grid_for_lanes(n)), dim3(kBlock), 0, stream, dv(g, VF), s, d, w,
-                     n, g->n, status, lg, &g->ctr->pad0[0]);
   if (g->view[VR].on || g->view[VU].on)
-    hipLaunchKernelGGL(k_insert_aux, dim3(grid_for_lanes(3 * n)), dim3(kBlock), 0, stream, dv(g, VR),
-                       dv(g, VU), g->cfg.views, lg, n, &g->ctr->pad0[0]);
+    hipLaunchKernelGGL(k_insert_all, dim3(grid_for_lanes(4 * n)), dim3(kBlock), 0, stream, dv(g, VF), dv(g, VR),
+                       dv(g, VU), g->cfg.views, s, d, w, n, g->n, status, lg, &g->ctr->pad0[0]);
+  else
+    hipLaunchKernelGGL(k_insert_fwd, dim3(grid_for_lanes(n)), dim3(kBlock), 0, stream, dv(g, VF), s, d, w,
+                       n, g->n, status, lg, &g->ctr->pad0[0]);
   hipLaunchKernelGGL(k_spare_merge, dim3(3), dim3(kBlock), 0, stream, dv(g, VF), dv(g, VR), dv(g, VU),
                      g->cfg.views | MK_VIEW_FWD);
 }
