@@ -32,7 +32,8 @@ using namespace mk;
 namespace {
 
 constexpr uint32_t kExpandBlocks = 2048;  // 256 CUs x 8 resident blocks
-constexpr int kSyncEvery = 4;            // frontier launches between size read-backs
+constexpr int kSyncFirst = 4, kSyncMax = 16;  // frontier launches between size read-backs: 4,
+                                              // then doubling while the frontier lasts
 
 __device__ inline uint64_t tree_node(uint64_t dist, uint32_t parent) {
   if (dist >= 0xFFFFFFFFull) dist = 0xFFFFFFFEull;  // saturate below INF
@@ -708,8 +709,9 @@ template <class Launch>
 mk_status run_frontier(mk_graph* g, const TravCtx& c, hipStream_t stream, Launch&& launch,
                        uint64_t* it_io = nullptr) {
   uint64_t it = it_io ? *it_io : 0;
-  while (true) {
-    for (int k = 0; k < kSyncEvery; ++k, ++it) {
+  int every = kSyncFirst;
+  for (;; every = every < kSyncMax ? 2 * every : kSyncMax) {
+    for (int k = 0; k < every; ++k, ++it) {
       launch(queues(c, it), ++*c.stamp);
       MK_LAUNCH(g, "frontier kernel");
     }
