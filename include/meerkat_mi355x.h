@@ -182,7 +182,7 @@ mk_status mk_traverse_from(mk_graph* g, uint32_t source, int weighted, void* d_w
  *   slot    : 0..15, as for mk_traverse_from (pinned words for size read-backs).
  *   d_level : N uint32 (device): the level (0 at the source), 0xFFFFFFFF if unreachable.
  *   h_bottom_up_steps (nullable, host): number of bottom-up steps taken.
- * Synchronizes `stream` every four levels. */
+ * Synchronizes `stream` after 4, 8, 16 and 32 levels, then every 16. */
 enum { MK_BFS_TOP_DOWN_ONLY = 1 };
 size_t mk_bfs_levels_workspace_bytes(const mk_graph* g);
 mk_status mk_bfs_levels(mk_graph* g, uint32_t source, uint32_t flags, void* d_ws, size_t ws_bytes,
@@ -196,7 +196,7 @@ mk_status mk_bfs_levels(mk_graph* g, uint32_t source, uint32_t flags, void* d_ws
  * mk_bfs_levels.  Weights must be >= 1.
  *   d_dist : N uint32 (device): the distance (sums saturate at 0xFFFFFFFE), 0xFFFFFFFF if
  *            unreachable.
- * Synchronizes `stream` every four steps. */
+ * Synchronizes `stream` after 4, 8, 16 and 32 steps, then every 16. */
 size_t mk_sssp_distances_workspace_bytes(const mk_graph* g);
 mk_status mk_sssp_distances(mk_graph* g, uint32_t source, void* d_ws, size_t ws_bytes, uint32_t slot,
                             uint32_t* d_dist, hipStream_t stream);

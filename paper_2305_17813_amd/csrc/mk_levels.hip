@@ -9,7 +9,7 @@
 // in-arcs, through the reverse view, for a vertex of the current level and stops at the
 // first one).  A one-thread kernel picks the direction of each step on the device from the
 // frontier's size and out-arc count against the number of unreached vertices, so the host
-// only reads sizes back every few levels.
+// only reads sizes back after 4, 8, 16 and 32 levels, then every 16.
 //
 // The rule is Beamer's direction optimization recast for slabs.  A top-down step reads a slab
 // per frontier vertex and makes a random level read (and, for an unreached target, a CAS) per
@@ -33,7 +33,8 @@ namespace {
 
 constexpr uint32_t kLevelInf = 0xFFFFFFFFu;
 constexpr uint32_t kChunk = kGroup;       // buckets of a multi-bucket vertex per work item
-constexpr uint32_t kLevelsPerSync = 4;
+constexpr uint32_t kSyncFirst = 4, kSyncMax = 16;  // steps between size read-backs: 4, 4,
+                                                    // then doubling while the traversal lasts
 
 // Device counters of one call (in the caller's workspace).  Level L uses slot L mod 4.
 struct LvCnt {
@@ -648,6 +649,7 @@ mk_status levels_run(mk_graph* g, uint32_t source, bool allow_bu, const LevelBuf
   hipLaunchKernelGGL(k_lv_fill, dim3(blocks_for(N, 4096)), dim3(kBlock), 0, stream, level, N);
   hipLaunchKernelGGL(k_lv_seed, dim3(1), dim3(64), 0, stream, level, b.q[0], c, F.deg, source);
   MK_LAUNCH(g, "k_lv_seed");
+  uint64_t every = kSyncFirst, next_sync = kSyncFirst;
   for (uint32_t L = 0;; ++L) {
     uint32_t* fin = b.q[L & 1];
     uint32_t* fout = b.q[(L + 1) & 1];
@@ -660,7 +662,9 @@ mk_status levels_run(mk_graph* g, uint32_t source, bool allow_bu, const LevelBuf
       hipLaunchKernelGGL(k_lv_bu, dim3(blocks_for(N, 8192)), dim3(kBlock), 0, stream, F, R, c, L, level,
                          fout, N);
     MK_LAUNCH(g, "k_lv step");
-    if ((L + 1) % kLevelsPerSync == 0 || L + 1 >= N) {
+    if (L + 1 == next_sync || L + 1 >= N) {
+      if (next_sync >= 2 * kSyncFirst) every = std::min<uint64_t>(2 * every, kSyncMax);
+      next_sync += every;
       MK_HIP(g, hipMemcpyAsync(pin, &c->n[(L + 1) & 3], 4, hipMemcpyDeviceToHost, stream));
       MK_HIP(g, hipMemcpyAsync(pin + 1, &c->bu_steps, 4, hipMemcpyDeviceToHost, stream));
       MK_HIP(g, hipStreamSynchronize(stream));
@@ -722,6 +726,7 @@ mk_status dist_run(mk_graph* g, uint32_t source, void* cnt, uint32_t* const q[2]
   hipLaunchKernelGGL(k_ds_seed, dim3(1), dim3(64), 0, stream, a.dist, q[0], c, source, delta);
   MK_LAUNCH(g, "k_ds_seed");
   const uint64_t cap = std::min<uint64_t>(64ull * N + 1024, 1ull << 31);
+  uint64_t every = kSyncFirst, next_sync = kSyncFirst;
   for (uint64_t S = 0;; ++S) {
     const uint32_t s32 = (uint32_t)S;
     uint32_t* fin = q[S & 1];
@@ -731,7 +736,9 @@ mk_status dist_run(mk_graph* g, uint32_t source, void* cnt, uint32_t* const q[2]
     hipLaunchKernelGGL(k_ds_far_min, dim3(blocks_for(N, 1024)), dim3(kBlock), 0, stream, c, s32, a);
     hipLaunchKernelGGL(k_ds_split, dim3(blocks_for(N, 2048)), dim3(kBlock), 0, stream, c, s32, a, fout, delta);
     MK_LAUNCH(g, "k_ds step");
-    if ((S + 1) % kLevelsPerSync == 0) {
+    if (S + 1 == next_sync) {
+      if (next_sync >= 2 * kSyncFirst) every = std::min<uint64_t>(2 * every, kSyncMax);
+      next_sync += every;
       MK_HIP(g, hipMemcpyAsync(pin, &c->n[(S + 1) & 3], 4, hipMemcpyDeviceToHost, stream));
       MK_HIP(g, hipMemcpyAsync(pin + 1, &c->nfar[0], 8, hipMemcpyDeviceToHost, stream));
       MK_HIP(g, hipStreamSynchronize(stream));
