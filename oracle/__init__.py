@@ -65,6 +65,8 @@ def lib():
         L.orc_triangles.argtypes = [vp]
         L.orc_triangles_brute.restype = u64
         L.orc_triangles_brute.argtypes = [vp]
+        L.orc_triangles_touching.restype = u64
+        L.orc_triangles_touching.argtypes = [vp, U32P, U32P, u64]
         _lib = L
     return _lib
 
@@ -176,3 +178,9 @@ class OracleGraph:
 
     def triangles_brute(self) -> int:
         return int(lib().orc_triangles_brute(self.h))
+
+    def triangles_touching(self, a, b) -> int:
+        """Triangles of the underlying undirected graph with at least one edge among the
+        pairs {a[i], b[i]} (each counted once)."""
+        x, y = _u32(a), _u32(b)
+        return int(lib().orc_triangles_touching(self.h, x, y, x.size))

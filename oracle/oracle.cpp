@@ -349,6 +349,44 @@ uint64_t orc_triangles_brute(void* h) {
   return t;
 }
 
+// Triangles of the underlying undirected simple graph that have at least one edge among
+// the k listed vertex pairs {a[i], b[i]} (order inside a pair, repeats, self-pairs and pairs
+// that are not edges are ignored).  Every such triangle is counted once: from the smallest
+// of its listed edges, so no triangle needs to be stored.  With the edges a batch added
+// (removed), this is the count after (before) the batch minus the count before (after).
+uint64_t orc_triangles_touching(void* h, const uint32_t* a, const uint32_t* b, uint64_t k) {
+  const Graph& g = *static_cast<Graph*>(h);
+  auto nb = undirected(g);
+  auto key = [](uint32_t x, uint32_t y) {
+    return x < y ? ((uint64_t)x << 32) | y : ((uint64_t)y << 32) | x;
+  };
+  auto is_edge = [&](uint32_t x, uint32_t y) { return std::binary_search(nb[x].begin(), nb[x].end(), y); };
+  std::vector<uint64_t> listed;
+  for (uint64_t i = 0; i < k; ++i)
+    if (a[i] < g.n && b[i] < g.n && a[i] != b[i] && is_edge(a[i], b[i])) listed.push_back(key(a[i], b[i]));
+  std::sort(listed.begin(), listed.end());
+  listed.erase(std::unique(listed.begin(), listed.end()), listed.end());
+  auto is_listed = [&](uint64_t e) { return std::binary_search(listed.begin(), listed.end(), e); };
+  uint64_t t = 0;
+  for (uint64_t e : listed) {
+    const uint32_t u = uint32_t(e >> 32), v = uint32_t(e);
+    const auto& x = nb[u];
+    const auto& y = nb[v];
+    size_t i = 0, j = 0;
+    while (i < x.size() && j < y.size()) {
+      if (x[i] < y[j]) { ++i; continue; }
+      if (x[i] > y[j]) { ++j; continue; }
+      const uint32_t w = x[i];
+      ++i;
+      ++j;
+      const uint64_t e1 = key(u, w), e2 = key(v, w);
+      if ((e1 < e && is_listed(e1)) || (e2 < e && is_listed(e2))) continue;  // counted from a smaller edge
+      ++t;
+    }
+  }
+  return t;
+}
+
 // Undirected degree of every vertex in the underlying simple graph.
 void orc_undirected_degree(void* h, uint32_t* deg) {
   const Graph& g = *static_cast<Graph*>(h);

@@ -300,3 +300,39 @@ def test_inclusion_exclusion_reading(orc):
             g.delete([a for a, b in arcs], [b for a, b in arcs])
             delta = (S1 + S2 + S3 // 3) // 2
             assert t0 - g.triangles() == delta
+
+
+# ---------------------------------------------------------------- triangles touching a batch
+@pytest.mark.parametrize("n", [4, 6, 9])
+def test_triangles_touching_closed_forms(orc, n):
+    """In K_n an edge lies in n-2 triangles, two edges sharing a vertex in 2(n-2)-1, two
+    disjoint edges in 2(n-2), and the edge set of K_n touches all C(n,3) triangles; pairs that
+    are not edges, self-pairs and repeats add nothing."""
+    arcs = [(a, b) for a in range(n) for b in range(n) if a != b]
+    g = mk(orc, n, arcs)
+    assert g.triangles_touching([0], [1]) == n - 2
+    assert g.triangles_touching([1, 0, 0], [0, 1, 0]) == n - 2
+    assert g.triangles_touching([0, 0], [1, 2]) == 2 * (n - 2) - 1
+    assert g.triangles_touching([0, 2], [1, 3]) == 2 * (n - 2)
+    a, b = zip(*itertools.combinations(range(n), 2))
+    assert g.triangles_touching(a, b) == math.comb(n, 3)
+    g2 = mk(orc, n, [(i, (i + 1) % n) for i in range(n)])  # a cycle: no triangle
+    assert g2.triangles_touching(a, b) == (1 if n == 3 else 0)
+    assert g.triangles_touching([], []) == 0
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_triangles_touching_equals_brute_difference(orc, seed):
+    """On random graphs, the triangles touching a random set of pairs equal the triple-loop
+    count minus the triple-loop count with those undirected edges removed."""
+    rng = np.random.default_rng(900 + seed)
+    n = int(rng.integers(5, 30))
+    arcs, _ = rand_digraph(rng, n, int(rng.integers(n, n * (n - 1) // 2)))
+    g = mk(orc, n, arcs)
+    k = int(rng.integers(1, 25))
+    a = rng.integers(0, n, k)
+    b = rng.integers(0, n, k)
+    touched = g.triangles_touching(a, b)
+    drop = {(int(x), int(y)) for x, y in zip(a, b)} | {(int(y), int(x)) for x, y in zip(a, b)}
+    rest = [e for e in arcs if e not in drop]
+    assert touched == g.triangles_brute() - mk(orc, n, rest).triangles_brute()
