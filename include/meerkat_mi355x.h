@@ -13,13 +13,25 @@
  *     few pinned host words per graph (hipHostMalloc) for size read-backs.
  *   - Every call is ordered on the given HIP stream.  Calls that must read a size back
  *     (traversal frontier sizes, PageRank convergence, mk_graph_stats) synchronize that
- *     stream; the update and query calls never synchronize.
+ *     stream.  Delete and query calls never synchronize.  An insert call synchronizes only
+ *     when the host cannot otherwise show that the slab pools hold the batch: the host keeps
+ *     an upper bound of the slabs in use (one per inserted arc and view), tightened without
+ *     waiting by pool snapshots that earlier inserts left behind events; only when both fall
+ *     short is the stream synchronized for the exact figures.  Under stream capture an
+ *     insert never synchronizes (it returns MK_ERR_OUT_OF_SLABS instead), and replays of a
+ *     captured insert are not counted by the host: a caller that replays inserts must admit
+ *     them against mk_graph_stats itself.
  *   - Vertex ids and weights are uint32.  Ids >= 0xFFFFFFFD are reserved sentinels
  *     (EMPTY = 0xFFFFFFFE and TOMBSTONE = 0xFFFFFFFD, as in section 2; 0xFFFFFFFF is
  *     INVALID) and are rejected.  Weights must be >= 1 for shortest paths.
  *   - Errors are returned as mk_status; nothing aborts or throws across the ABI.  On any
  *     error other than MK_ERR_HIP the graph is unchanged.  A graph is not thread-safe:
  *     use one stream per graph.
+ *   - Second line of defence: an insert lane that finds its pool empty all the same (the
+ *     pre-check above makes this unreachable unless pool memory was damaged) stores nothing,
+ *     reports status 2 for its arc and raises a device-side overflow bit.  Once the host has
+ *     seen that bit (at the next synchronizing call, or from a completed pool snapshot), the
+ *     graph may have lost arcs and every later call on it returns MK_ERR_OUT_OF_SLABS.
  */
 #ifndef MEERKAT_MI355X_H
 #define MEERKAT_MI355X_H
@@ -37,7 +49,8 @@ typedef struct mk_graph mk_graph; /* opaque; host-side metadata + pointers into 
 typedef enum {
   MK_OK = 0,
   MK_ERR_INVALID_ARG = 1,  /* null/misaligned pointer, size out of range, bad config      */
-  MK_ERR_OUT_OF_SLABS = 2, /* the slab pool could not hold the batch; nothing was applied */
+  MK_ERR_OUT_OF_SLABS = 2, /* the slab pool could not hold the batch; nothing was applied
+                              (also: the graph overflowed a pool earlier and is unusable)  */
   MK_ERR_CAPACITY = 3,     /* arena too small, or a batch larger than the change log      */
   MK_ERR_STATE = 4,        /* the operation needs a view that the graph was built without */
   MK_ERR_HIP = 5           /* a HIP runtime call failed (the message is kept per graph)   */
@@ -93,7 +106,9 @@ size_t mk_arena_bytes(const mk_config* cfg, uint64_t n_edges_hint);
  *   d_src/d_dst/d_w     : m arcs (device, uint32 each); d_w may be NULL (weight 1).
  *                         Duplicates keep one copy; invalid arcs are skipped.
  *   out                 : receives the handle.  The call synchronizes `stream` once.
- */
+ * MK_ERR_OUT_OF_SLABS if an explicit pool_slabs ran out while the initial arcs were inserted
+ * (no handle).  Lanes racing to extend one chain may each hold a slab for a moment, so an
+ * explicit pool should have room for one slab per initial arc that a chain cannot take. */
 mk_status mk_graph_create(const mk_config* cfg, void* d_arena, size_t arena_bytes,
                           const uint32_t* d_src, const uint32_t* d_dst, const uint32_t* d_w,
                           uint64_t m, hipStream_t stream, mk_graph** out);
@@ -206,7 +221,7 @@ mk_status mk_sssp_distances(mk_graph* g, uint32_t source, void* d_ws, size_t ws_
  *   d_label : N uint32 (device): the smallest vertex id of the component. */
 mk_status mk_incr_wcc(mk_graph* g, uint32_t* d_label, mk_mode mode, hipStream_t stream);
 
-/* How incremental WCC finds the arcs to unite (the incremental-WCC schemes that section 5
+/* How incremental WCC finds the arcs to unite (the incremental-WCC schemes that section 6.4
  * compares in its table of speedups over the naive scheme).  Every scheme gives the same
  * labels; they differ only in the slabs they read. */
 typedef enum {
@@ -272,7 +287,8 @@ mk_status mk_compact(mk_graph* g, uint32_t min_tombstones, uint64_t* h_freed, hi
 mk_status mk_probe_cost(mk_graph* g, int op, int view, const uint32_t* d_src, const uint32_t* d_dst,
                         uint64_t n, uint64_t* h_slabs, hipStream_t stream);
 
-/* Occupancy and capacity figures (synchronizes). */
+/* Occupancy and capacity figures (synchronizes).  Fills *h_out and returns
+ * MK_ERR_OUT_OF_SLABS if the graph has overflowed a pool. */
 mk_status mk_graph_stats(mk_graph* g, mk_stats* h_out, hipStream_t stream);
 
 /* Structural self-check of every chain of every view: no duplicate keys in a vertex's

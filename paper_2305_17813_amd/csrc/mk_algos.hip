@@ -316,8 +316,10 @@ __global__ void __launch_bounds__(kBlock) k_pr_contrib(const float* __restrict__
   if (threadIdx.x == 0) dpart[blockIdx.x] = s;
 }
 
-// Sum of per-block partial sums in a fixed order (one block): every FP64 reduction of an
-// iteration is deterministic and takes no same-address atomics.
+// Sum of per-block partial sums in a fixed order (one block): the dangling mass and the L1
+// change of an iteration are deterministic and take no same-address atomics.  (The in-arc
+// sums of vertices split into bucket work items are the exception: their FP64 partials are
+// added by atomics, so the order, and the last bits of those ranks, can vary between runs.)
 __device__ inline double sum_parts(const double* part, uint32_t n, double* lds) {
   double v = 0;
   for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) v += part[i];
@@ -698,13 +700,14 @@ mk_status mk_incr_wcc(mk_graph* g, uint32_t* d_label, mk_mode mode, hipStream_t 
 mk_status mk_incr_wcc_scheme(mk_graph* g, uint32_t* d_label, mk_mode mode, mk_wcc_scheme scheme,
                              hipStream_t stream) {
   if (!g || !d_label || (uint32_t)scheme > (uint32_t)MK_WCC_UPDATE) return MK_ERR_INVALID_ARG;
+  if (mk_status gs = graph_guard(g); gs != MK_OK) return gs;
   const uint32_t N = g->n;
   Pending p = pending_for(g, g->wcc);
   const bool full = mode == MK_RECOMPUTE || !g->wcc.valid || p.lost || (p.kinds & 2);
   uint32_t* P = g->wcc_parent;
   const DView F = g->view[VF].d;
   auto all_arcs = [&]() {  // union over every arc (collecting the heavy vertices first)
-    uint32_t* nh = &g->ctr->pad0[1];
+    uint32_t* nh = &g->ctr->n_heavy_wcc;
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, nh, 1u);
     hipLaunchKernelGGL(k_collect_heavy, dim3(blocks_for(N)), dim3(kBlock), 0, stream,
                        g->view[VF].nbk, N, g->fq[2], nh);
@@ -724,8 +727,8 @@ mk_status mk_incr_wcc_scheme(mk_graph* g, uint32_t* d_label, mk_mode mode, mk_wc
     } else if (scheme == MK_WCC_NAIVE) {
       all_arcs();
     } else {
-      uint32_t* nl = &g->ctr->pad0[5];
-      uint32_t* nh = &g->ctr->pad0[6];
+      uint32_t* nl = &g->ctr->n_listed_light;
+      uint32_t* nh = &g->ctr->n_listed_heavy;
       hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, nl, 2u);
       uint64_t ops = 0;
       for (const BatchRec* b : p.list) {
@@ -756,6 +759,7 @@ mk_status mk_incr_pagerank(mk_graph* g, float damping, double tol_l1, uint32_t m
   if (!g->view[VR].on) return MK_ERR_STATE;
   const uint32_t N = g->n;
   Pending p = pending_for(g, g->pr);
+  if (mk_status gs = graph_guard(g); gs != MK_OK) return gs;
   const bool warm = mode != MK_RECOMPUTE && g->pr.valid && !p.lost;
   if (warm && p.list.empty()) {
     hipLaunchKernelGGL(k_pr_start, dim3(1), dim3(64), 0, stream, g->ctr);
@@ -766,7 +770,7 @@ mk_status mk_incr_pagerank(mk_graph* g, float damping, double tol_l1, uint32_t m
   }
   if (!warm)
     hipLaunchKernelGGL(k_pr_fill, dim3(blocks_for(N)), dim3(kBlock), 0, stream, g->pr_x, N, 1.f / N);
-  uint32_t* nh = &g->ctr->pad0[2];
+  uint32_t* nh = &g->ctr->n_heavy_pr;
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, nh, 1u);
   hipLaunchKernelGGL(k_collect_heavy, dim3(blocks_for(N)), dim3(kBlock), 0, stream, g->view[VR].nbk,
                      N, g->heavy_rev, nh);
@@ -826,11 +830,12 @@ mk_status mk_count_triangles(mk_graph* g, uint64_t* d_count, mk_mode mode, hipSt
   if (!g->view[VU].on) return MK_ERR_STATE;
   const uint32_t N = g->n;
   const DView U = g->view[VU].d;
+  if (mk_status gs = graph_guard(g); gs != MK_OK) return gs;
   Pending p = pending_for(g, g->tc);
   const bool full = mode == MK_RECOMPUTE || !g->tc.valid || p.lost || p.kinds == 3;
   unsigned long long* out = reinterpret_cast<unsigned long long*>(d_count);
   if (full) {
-    uint32_t* nh = &g->ctr->pad0[3];
+    uint32_t* nh = &g->ctr->n_heavy_tc;
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, nh, 1u);
     hipLaunchKernelGGL(k_collect_heavy, dim3(blocks_for(N)), dim3(kBlock), 0, stream, U.nbk, N,
                        g->fq[2], nh);
@@ -858,7 +863,7 @@ mk_status mk_count_triangles(mk_graph* g, uint64_t* d_count, mk_mode mode, hipSt
     hipLaunchKernelGGL(k_tc_begin, dim3(1), dim3(64), 0, stream, g->ctr, false);
     // after the sort, tc_keys[0] is free: it holds the list of split arcs
     uint32_t* hl = reinterpret_cast<uint32_t*>(g->tc_keys[0]);
-    uint32_t* nhl = &g->ctr->pad0[4];
+    uint32_t* nhl = &g->ctr->n_split_tc;
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, nhl, 1u);
     // segment bounds per source vertex (scratch: two traversal queues, unused here)
     hipLaunchKernelGGL(k_tc_segs, dim3(blocks_for(nk)), dim3(kBlock), 0, stream, g->tc_keys[1], nk, N,

@@ -106,6 +106,7 @@ extern "C" mk_status mk_batch_features(mk_graph* g, int algo, const uint32_t* d_
                                        float* h_out, hipStream_t stream) {
   if (!g || !h_out || algo < 0 || algo > 4) return MK_ERR_INVALID_ARG;
   if ((n_ins && (!d_ins_src || !d_ins_dst)) || (n_del && (!d_del_src || !d_del_dst))) return MK_ERR_INVALID_ARG;
+  if (mk_status gs = graph_guard(g); gs != MK_OK) return gs;
   const DView F = g->view[VF].d;
   const uint32_t* indeg = g->view[VR].on ? g->view[VR].d.deg : nullptr;
   const uint32_t* undeg = g->view[VU].on ? g->view[VU].d.deg : nullptr;

@@ -41,13 +41,27 @@ void mark_seen(mk_graph* g, AlgoState& st) { st.seen_seq = g->next_seq - 1; }
 
 }  // namespace mk
 
+namespace {
+void poll_snapshots(mk_graph* g);
+}
+
+namespace mk {
+mk_status graph_guard(mk_graph* g, bool poll) {
+  if (poll && !g->overflowed.load(std::memory_order_relaxed)) poll_snapshots(g);
+  return g->overflowed.load(std::memory_order_relaxed) ? MK_ERR_OUT_OF_SLABS : MK_OK;
+}
+}  // namespace mk
+
 // ============================================================ device: updates
 namespace {
 
 // Insert <key, w> into u's table (one lane).  Returns 1 inserted, 0 already present,
-// 3 pool empty.  Progress never depends on a load being fresh: every failed CAS returns
-// the word's true value and `floor` (words of this slab known to be filled) only grows, so
-// a slab is retried at most 15 times.
+// kPoolEmpty when no slab could be taken (the host-side pool check makes this unreachable;
+// the caller raises the view's overflow bit).  Progress never depends on a load being
+// fresh: every failed CAS returns the word's true value and `floor` (words of this slab
+// known to be filled) only grows, so a slab is retried at most 15 times.
+constexpr int kPoolEmpty = 3;
+
 __device__ int insert_key_core(const DView& V, uint32_t u, uint32_t key, uint32_t w, uint32_t& spare) {
   Slab sl;
   int nd;
@@ -79,8 +93,9 @@ __device__ int insert_key_core(const DView& V, uint32_t u, uint32_t key, uint32_
     }
     // Full tail: put the key in word 0 of a fresh slab, then link the slab.  Pool slabs
     // were filled with EMPTY words and an INVALID link at creation, so word 0 is the only
-    // word to write; writing it with an atomic exchange (performed where the CASes are)
-    // and waiting for its result orders it before the link without an L2 write-back.
+    // word to write; writing it with a CAS from EMPTY (performed where the other CASes
+    // are) and waiting for its result orders it before the link without an L2 write-back.
+    // A spare kept from a lost link race already holds this key in word 0.
     if (spare == kInvalid) {
       // the bump pointer first (one counter atomic for the lanes of the wave that need a
       // slab now), reclaimed slabs once it is exhausted; both hand out EMPTY slabs
@@ -96,12 +111,17 @@ __device__ int insert_key_core(const DView& V, uint32_t u, uint32_t key, uint32_
         leader = __builtin_ctzll(m);
         if (lane64() == leader) base = atomicAdd(V.pool_ctr + 2, (uint32_t)__popcll(m));
         const uint32_t idx = __shfl(base, leader) + lanes_below(m);
-        if ((int32_t)(V.pool_ctr[1] - idx) <= 0) return 3;
+        if ((int32_t)(V.pool_ctr[1] - idx) <= 0) return kPoolEmpty;
         spare = V.free_ids[idx % V.pool_cap];
       }
     }
-    const uint64_t prev = atomicExch((unsigned long long*)slab_ptr(V, spare), (unsigned long long)mine);
-    if (prev != kEmptyWord && prev != mine) return 3;  // a pool slab is fresh or our own spare
+    const uint64_t prev = cas64(slab_ptr(V, spare), kEmptyWord, mine);
+    if (prev != kEmptyWord && prev != mine) {
+      // not a fresh slab (the free list handed out a slab in use): leave it alone and
+      // report the pool as broken rather than list it as a spare
+      spare = kInvalid;
+      return kPoolEmpty;
+    }
     // the link word keeps its meta half (the bucket count of a primary slab)
     const uint64_t old = cas64(sp + 15, link, (link & 0xFFFFFFFF00000000ull) | spare);
     if (old == link) {
@@ -147,6 +167,20 @@ __global__ void k_spare_merge(DView F, DView R, DView U, uint32_t views) {
   }
 }
 
+// Pool counters of every view and the overflow bits, gathered for one asynchronous copy.
+__global__ void k_pool_snapshot(const uint32_t* f, const uint32_t* r, const uint32_t* u,
+                                const uint32_t* overflow, uint32_t* out) {
+  const uint32_t t = threadIdx.x;
+  if (t < 12) {
+    const uint32_t* c = t < 4 ? f : (t < 8 ? r : u);
+    out[t] = (c && (t & 3) < 3) ? c[t & 3] : 0u;
+  } else if (t == 12) {
+    out[t] = *overflow;
+  } else if (t < 16) {
+    out[t] = 0u;
+  }
+}
+
 // Delete key from u's table (one lane).  Returns 1 deleted, 0 absent; *w_out gets the weight.
 __device__ int delete_key(const DView& V, uint32_t u, uint32_t key, uint32_t* w_out) {
   Slab sl;
@@ -185,7 +219,10 @@ __global__ void __launch_bounds__(kBlock) k_insert_fwd(DView F, const uint32_t* 
   int st = 2;
   if (!bad_arc(s, d, nv)) st = insert_key(F, s, d, wt);
   if (st == 1) atomicAdd(F.deg + s, 1u);
-  if (st == 3) atomicOr(overflow, 1u);
+  if (st == kPoolEmpty) {  // not stored: reported as not applied, the graph is flagged
+    atomicOr(overflow, 1u);
+    st = 2;
+  }
   if (status) status[op] = (uint8_t)st;
   log.s[op] = s;
   log.d[op] = d;
@@ -221,7 +258,10 @@ __global__ void __launch_bounds__(kBlock) k_insert_all(DView F, DView R, DView U
     int st = 2;
     if (!bad) st = insert_key(F, s, d, wt);
     if (st == 1) atomicAdd(F.deg + s, 1u);
-    if (st == 3) atomicOr(overflow, 1u);
+    if (st == kPoolEmpty) {
+      atomicOr(overflow, 1u);
+      st = 2;
+    }
     if (status) status[op] = (uint8_t)st;
     log.s[op] = s;
     log.d[op] = d;
@@ -245,7 +285,7 @@ __global__ void __launch_bounds__(kBlock) k_insert_all(DView F, DView R, DView U
     if (r == 1) atomicAdd(U.deg + a, 1u);
     if (task == 2) log.uf[op] = r == 1;
   }
-  if (r == 3) atomicOr(overflow, task == 1 ? 2u : 4u);
+  if (r == kPoolEmpty) atomicOr(overflow, task == 1 ? 2u : 4u);
 }
 
 __global__ void __launch_bounds__(kBlock) k_delete_fwd(DView F, const uint32_t* __restrict__ src,
@@ -788,40 +828,107 @@ uint32_t default_band(uint64_t m, uint32_t n, double mean_w) {
   return (uint32_t)std::min(b, (double)(1u << 30));
 }
 
-// Pool slabs in use = bump high-water mark minus the free-list entries not yet taken.
+// Pool slabs in use from one view's counters: bump high-water mark minus the free-list
+// entries not yet taken.
+uint64_t used_from(const ViewHost& vh, const uint32_t* c) {
+  const int32_t avail = std::max<int32_t>(0, (int32_t)(c[1] - c[2]));
+  const uint64_t hw = std::min<uint64_t>(c[0], vh.pool_cap);
+  return hw - std::min<uint64_t>((uint64_t)avail, hw);
+}
+
+// Exact pool figures and the overflow bits (synchronizes the stream).
 mk_status refresh_pool(mk_graph* g, hipStream_t stream) {
   for (int v = 0; v < 3; ++v)
     if (g->view[v].on)
       MK_HIP(g, hipMemcpyAsync(g->h_pin + 2 * v, g->view[v].d.pool_ctr, 3 * sizeof(uint32_t),
                                hipMemcpyDeviceToHost, stream));
+  MK_HIP(g, hipMemcpyAsync(g->h_pin + 7, &g->ctr->overflow, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
   MK_HIP(g, hipStreamSynchronize(stream));
+  g->overflowed.fetch_or(*reinterpret_cast<const uint32_t*>(g->h_pin + 7));
   for (int v = 0; v < 3; ++v) {
     ViewHost& vh = g->view[v];
     if (!vh.on) continue;
     const uint32_t* c = reinterpret_cast<const uint32_t*>(g->h_pin + 2 * v);
-    const int32_t avail = std::max<int32_t>(0, (int32_t)(c[1] - c[2]));
     vh.pool_hw = std::min<uint64_t>(c[0], vh.pool_cap);
-    vh.pool_used_est = vh.pool_hw - std::min<uint64_t>((uint64_t)avail, vh.pool_hw);
+    vh.pool_used_est = used_from(vh, c);
   }
+  // every snapshot still in flight is older than these figures
+  for (auto& sn : g->snap) sn.pending = false;
   return MK_OK;
 }
 
-// Make sure every enabled view's pool can take `n` more inserts (at most one new slab per
-// arc and view; two for the undirected view).
+bool stream_capturing(hipStream_t stream) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+}
+
+// Use the newest completed snapshot, if any: slabs in use then, plus the bound of every
+// insert enqueued after it, bound the slabs in use now.  Never waits.
+void poll_snapshots(mk_graph* g) {
+  int best = -1;
+  for (int i = 0; i < kSnaps; ++i) {
+    PoolSnap& sn = g->snap[i];
+    if (!sn.pending || hipEventQuery(sn.ev) != hipSuccess) continue;
+    if (best < 0 || sn.added_at[VF] > g->snap[best].added_at[VF]) best = i;
+  }
+  if (best < 0) return;
+  const PoolSnap& b = g->snap[best];
+  g->overflowed.fetch_or(b.pin[12]);
+  for (int v = 0; v < 3; ++v) {
+    ViewHost& vh = g->view[v];
+    if (!vh.on) continue;
+    const uint64_t bound = used_from(vh, b.pin + 4 * v) + (vh.added - b.added_at[v]);
+    vh.pool_used_est = std::min(vh.pool_used_est, bound);
+  }
+  // this one and every older completed snapshot are consumed
+  for (auto& sn : g->snap)
+    if (sn.pending && sn.added_at[VF] <= b.added_at[VF] && hipEventQuery(sn.ev) == hipSuccess)
+      sn.pending = false;
+}
+
+// Enqueue a snapshot of the pool counters behind the work already on the stream.
+void enqueue_snapshot(mk_graph* g, hipStream_t stream) {
+  PoolSnap& sn = g->snap[g->snap_next];
+  if (sn.pending && hipEventQuery(sn.ev) != hipSuccess) return;  // ring slot still in flight
+  const auto ctr_of = [&](int v) -> const uint32_t* { return g->view[v].on ? g->view[v].d.pool_ctr : nullptr; };
+  hipLaunchKernelGGL(k_pool_snapshot, dim3(1), dim3(64), 0, stream, ctr_of(VF), ctr_of(VR), ctr_of(VU),
+                     &g->ctr->overflow, g->ctr->snap);
+  if (hipMemcpyAsync(sn.pin, g->ctr->snap, 16 * sizeof(uint32_t), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipEventRecord(sn.ev, stream) != hipSuccess) {
+    (void)hipGetLastError();
+    sn.pending = false;
+    return;
+  }
+  for (int v = 0; v < 3; ++v) sn.added_at[v] = g->view[v].added;
+  sn.pending = true;
+  g->snap_next = (g->snap_next + 1) % kSnaps;
+}
+
+// Slabs one insert call may take per view: one per arc (two for the undirected view).
+uint64_t insert_need(int v, uint64_t n) { return v == VU ? 2 * n : n; }
+
+bool pool_fits(const mk_graph* g, uint64_t n) {
+  for (int v = 0; v < 3; ++v) {
+    const ViewHost& vh = g->view[v];
+    if (vh.on && vh.pool_used_est + insert_need(v, n) > vh.pool_cap) return false;
+  }
+  return true;
+}
+
+// Make sure every enabled view's pool can take `n` more inserts.  The host keeps an upper
+// bound of the slabs in use; when it runs short, a completed snapshot tightens it, and only
+// when that is not enough either is the stream synchronized for the exact figures (never
+// under stream capture: the call is then refused).
 mk_status ensure_pool(mk_graph* g, uint64_t n, hipStream_t stream) {
-  auto fits = [&]() {
-    for (int v = 0; v < 3; ++v) {
-      const ViewHost& vh = g->view[v];
-      if (!vh.on) continue;
-      const uint64_t need = v == VU ? 2 * n : n;
-      if (vh.pool_used_est + need > vh.pool_cap) return false;
-    }
-    return true;
-  };
-  if (fits()) return MK_OK;
+  if (pool_fits(g, n)) return MK_OK;
+  poll_snapshots(g);
+  if (g->overflowed.load()) return MK_ERR_OUT_OF_SLABS;
+  if (pool_fits(g, n)) return MK_OK;
+  if (stream_capturing(stream)) return MK_ERR_OUT_OF_SLABS;
   mk_status st = refresh_pool(g, stream);
   if (st != MK_OK) return st;
-  return fits() ? MK_OK : MK_ERR_OUT_OF_SLABS;
+  if (g->overflowed.load()) return MK_ERR_OUT_OF_SLABS;
+  return pool_fits(g, n) ? MK_OK : MK_ERR_OUT_OF_SLABS;
 }
 
 // Reserve n log entries for a new batch, dropping the oldest batches it overwrites.
@@ -857,10 +964,10 @@ void launch_insert(mk_graph* g, const uint32_t* s, const uint32_t* d, const uint
                    uint8_t* status, const Log& lg, hipStream_t stream) {
   if (g->view[VR].on || g->view[VU].on)
     hipLaunchKernelGGL(k_insert_all, dim3(grid_for_lanes(4 * n)), dim3(kBlock), 0, stream, dv(g, VF), dv(g, VR),
-                       dv(g, VU), g->cfg.views, s, d, w, n, g->n, status, lg, &g->ctr->pad0[0]);
+                       dv(g, VU), g->cfg.views, s, d, w, n, g->n, status, lg, &g->ctr->overflow);
   else
     hipLaunchKernelGGL(k_insert_fwd, dim3(grid_for_lanes(n)), dim3(kBlock), 0, stream, dv(g, VF), s, d, w,
-                       n, g->n, status, lg, &g->ctr->pad0[0]);
+                       n, g->n, status, lg, &g->ctr->overflow);
   hipLaunchKernelGGL(k_spare_merge, dim3(3), dim3(kBlock), 0, stream, dv(g, VF), dv(g, VR), dv(g, VU),
                      g->cfg.views | MK_VIEW_FWD);
 }
@@ -895,12 +1002,18 @@ mk_status mk_graph_create(const mk_config* cfg, void* d_arena, size_t arena_byte
   g->arena_bytes = arena_bytes;
   layout(&g->cfg, m, g->arena, g, &g->used);
   auto fail = [&](mk_status s) {
-    if (g->h_pin) (void)hipHostFree(g->h_pin);
-    delete g;
+    mk_graph_destroy(g);
     return s;
   };
   if (hipHostMalloc((void**)&g->h_pin, 64 * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess)
     return fail(MK_ERR_HIP);
+  uint32_t* snap_pin = nullptr;
+  if (hipHostMalloc((void**)&snap_pin, kSnaps * 16 * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess)
+    return fail(MK_ERR_HIP);
+  for (int i = 0; i < kSnaps; ++i) {
+    g->snap[i].pin = snap_pin + 16 * i;
+    if (hipEventCreateWithFlags(&g->snap[i].ev, hipEventDisableTiming) != hipSuccess) return fail(MK_ERR_HIP);
+  }
   const uint32_t N = g->n;
   const uint32_t nb_blocks = grid_stride_blocks(N);
   for (int v = 0; v < 3; ++v) {
@@ -971,6 +1084,8 @@ mk_status mk_graph_create(const mk_config* cfg, void* d_arena, size_t arena_byte
   }
   if (hipGetLastError() != hipSuccess) return fail(MK_ERR_HIP);
   if (refresh_pool(g, stream) != MK_OK) return fail(MK_ERR_HIP);
+  // the initial arcs did not fit the pool (only an explicit, too small pool_slabs can do this)
+  if (g->overflowed.load()) return fail(MK_ERR_OUT_OF_SLABS);
   *out = g;
   return MK_OK;
 }
@@ -980,6 +1095,9 @@ mk_status mk_graph_destroy(mk_graph* g) {
   if (g->h_pin) (void)hipHostFree(g->h_pin);
   for (auto* p : g->slot_pin)
     if (p) (void)hipHostFree(p);
+  for (auto& sn : g->snap)
+    if (sn.ev) (void)hipEventDestroy(sn.ev);
+  if (g->snap[0].pin) (void)hipHostFree(g->snap[0].pin);
   delete g;
   return MK_OK;
 }
@@ -990,13 +1108,21 @@ mk_status mk_insert_edges(mk_graph* g, const uint32_t* d_src, const uint32_t* d_
   if (n == 0) return MK_OK;
   if (!d_src || !d_dst) return MK_ERR_INVALID_ARG;
   if (n > g->log_cap) return MK_ERR_CAPACITY;
-  mk_status st = ensure_pool(g, n, stream);
+  mk_status st = graph_guard(g, true);
+  if (st != MK_OK) return st;
+  st = ensure_pool(g, n, stream);
   if (st != MK_OK) return st;
   const uint64_t off = reserve_log(g, n);
   launch_insert(g, d_src, d_dst, d_w, n, d_status, log_at(g, off), stream);
   MK_LAUNCH(g, "k_insert");
   for (int v = 0; v < 3; ++v)
-    if (g->view[v].on) g->view[v].pool_used_est += v == VU ? 2 * n : n;
+    if (g->view[v].on) {
+      g->view[v].pool_used_est += insert_need(v, n);
+      g->view[v].added += insert_need(v, n);
+    }
+  // the bound would not admit two more batches of this size: have exact figures on the way,
+  // so that they are usually there before the bound runs out
+  if (!pool_fits(g, 2 * n) && !stream_capturing(stream)) enqueue_snapshot(g, stream);
   g->batches.push_back(BatchRec{kInsertBatch, off, n, g->next_seq++});
   g->log_tail = off + n;
   g->batches_applied++;
@@ -1009,6 +1135,8 @@ mk_status mk_delete_edges(mk_graph* g, const uint32_t* d_src, const uint32_t* d_
   if (n == 0) return MK_OK;
   if (!d_src || !d_dst) return MK_ERR_INVALID_ARG;
   if (n > g->log_cap) return MK_ERR_CAPACITY;
+  mk_status st = graph_guard(g, true);
+  if (st != MK_OK) return st;
   const uint64_t off = reserve_log(g, n);
   const Log lg = log_at(g, off);
   hipLaunchKernelGGL(k_delete_fwd, dim3(grid_for_lanes(n)), dim3(kBlock), 0, stream, dv(g, VF),
@@ -1031,6 +1159,8 @@ mk_status mk_query_edges(mk_graph* g, const uint32_t* d_src, const uint32_t* d_d
   if (!g) return MK_ERR_INVALID_ARG;
   if (n == 0) return MK_OK;
   if (!d_src || !d_dst || !d_found) return MK_ERR_INVALID_ARG;
+  mk_status st = graph_guard(g);
+  if (st != MK_OK) return st;
   hipLaunchKernelGGL(k_query, dim3(grid_for_lanes(n)), dim3(kBlock), 0, stream, dv(g, VF), d_src,
                      d_dst, n, g->n, d_found, d_w);
   MK_LAUNCH(g, "k_query");
@@ -1040,6 +1170,7 @@ mk_status mk_query_edges(mk_graph* g, const uint32_t* d_src, const uint32_t* d_d
 mk_status mk_graph_export(mk_graph* g, uint32_t* d_src, uint32_t* d_dst, uint32_t* d_w,
                           uint64_t cap, uint64_t* h_count, hipStream_t stream) {
   if (!g || !h_count || (cap && (!d_src || !d_dst))) return MK_ERR_INVALID_ARG;
+  if (mk_status gs = graph_guard(g); gs != MK_OK) return gs;
   unsigned long long* cnt = &g->ctr->u64tmp[3];
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, stream, (uint32_t*)cnt, 2, 0u);
   hipLaunchKernelGGL(k_export, dim3(grid_for_groups(std::min<uint64_t>(g->n, 1u << 20))),
@@ -1076,7 +1207,7 @@ mk_status mk_graph_stats(mk_graph* g, mk_stats* h_out, hipStream_t stream) {
   }
   h_out->arena_bytes_used = g->used;
   h_out->batches_applied = g->batches_applied;
-  return MK_OK;
+  return g->overflowed.load() ? MK_ERR_OUT_OF_SLABS : MK_OK;
 }
 
 mk_status mk_graph_check(mk_graph* g, uint64_t* h_bad, hipStream_t stream) {
@@ -1095,11 +1226,12 @@ mk_status mk_graph_check(mk_graph* g, uint64_t* h_bad, hipStream_t stream) {
   MK_HIP(g, hipMemcpyAsync(g->h_pin, bad, 8, hipMemcpyDeviceToHost, stream));
   MK_HIP(g, hipStreamSynchronize(stream));
   *h_bad = g->h_pin[0];
-  return MK_OK;
+  return g->overflowed.load() ? MK_ERR_OUT_OF_SLABS : MK_OK;
 }
 
 mk_status mk_compact(mk_graph* g, uint32_t min_tombstones, uint64_t* h_freed, hipStream_t stream) {
   if (!g || !h_freed) return MK_ERR_INVALID_ARG;
+  if (mk_status gs = graph_guard(g); gs != MK_OK) return gs;
   unsigned long long* freed = &g->ctr->u64tmp[2];
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, stream, (uint32_t*)freed, 2, 0u);
   for (int v = 0; v < 3; ++v) {
@@ -1122,6 +1254,7 @@ mk_status mk_probe_cost(mk_graph* g, int op, int view, const uint32_t* d_src, co
                         uint64_t n, uint64_t* h_slabs, hipStream_t stream) {
   if (!g || !h_slabs || view < 0 || view > 2 || op < 0 || op > 1) return MK_ERR_INVALID_ARG;
   if (!g->view[view].on) return MK_ERR_STATE;
+  if (mk_status gs = graph_guard(g); gs != MK_OK) return gs;
   *h_slabs = 0;
   if (n == 0) return MK_OK;
   if (!d_src || !d_dst) return MK_ERR_INVALID_ARG;

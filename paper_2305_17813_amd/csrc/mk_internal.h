@@ -1,5 +1,6 @@
 // Host-side graph object shared by the library's translation units.
 #pragma once
+#include <atomic>
 #include <deque>
 #include <string>
 #include <vector>
@@ -36,6 +37,8 @@ struct ViewHost {
   uint64_t pool_cap = 0;       // chained slabs
   uint64_t pool_used_est = 0;  // host-side upper bound of the pool slabs in use
   uint64_t pool_hw = 0;        // bump-pointer high-water mark read back last
+  uint64_t added = 0;          // slabs the inserts so far may have taken (running sum of
+                               // the per-call bounds; snapshots are placed against it)
 };
 
 struct AlgoState {
@@ -49,7 +52,13 @@ struct Counters {          // device-side scalars, one 4 KiB block
                            // queues), [9..10] far-pile sizes, [11..12] band thresholds,
                            // [13] smallest far distance
   uint32_t inval;          // invalidated-vertex list size
-  uint32_t pad0[7];
+  uint32_t overflow;       // bit per view (1 fwd, 2 rev, 4 und): an insert found its pool empty
+  uint32_t n_heavy_wcc;    // vertices of more than 16 buckets, all-arc WCC walk
+  uint32_t n_heavy_pr;     // the same for the PageRank pull (reverse view)
+  uint32_t n_heavy_tc;     // the same for the static triangle count (undirected view)
+  uint32_t n_split_tc;     // batch arcs whose intersections are split over many groups
+  uint32_t n_listed_light; // vertices listed for an incremental WCC pass: up to 16 buckets,
+  uint32_t n_listed_heavy; //   and more (these two are cleared together)
   unsigned long long tc_s[3];  // S1, S2, S3 of the triangle batch identity
   unsigned long long tc_total; // current triangle count
   unsigned long long u64tmp[4];
@@ -59,6 +68,19 @@ struct Counters {          // device-side scalars, one 4 KiB block
   double pr_best;          // smallest L1 change seen
   double feat[6];          // batch-feature sums
   uint32_t feat_max[2];    // batch-feature maxima
+  uint32_t snap[16];       // pool snapshot staging: view v's bump, free-end and free-take
+                           // counters at [4v, 4v+3), the overflow bits at [12]
+};
+
+// Asynchronous pool snapshots: after an insert that leaves the host-side bound short of
+// another batch, the pool counters are copied to pinned memory behind an event, so that a
+// later call can tighten the bound without synchronizing the stream.
+constexpr int kSnaps = 4;
+struct PoolSnap {
+  hipEvent_t ev = nullptr;
+  uint32_t* pin = nullptr;       // 16 pinned words (layout of Counters::snap)
+  uint64_t added_at[3] = {};     // ViewHost::added when the snapshot was enqueued
+  bool pending = false;          // enqueued and not yet consumed
 };
 
 }  // namespace mk
@@ -113,6 +135,10 @@ struct mk_graph {
   size_t scan_tmp_bytes = 0;
 
   uint64_t* h_pin = nullptr;  // pinned host words for read-backs
+  mk::PoolSnap snap[mk::kSnaps];
+  uint32_t snap_next = 0;     // ring position of the next snapshot
+  std::atomic<uint32_t> overflowed{0};  // overflow bits seen on the host: the graph may have
+                                        // lost arcs (read by concurrent read-only calls)
   uint64_t* slot_pin[mk::kSlots] = {};  // pinned words of one-off traversals, per slot
   uint64_t batches_applied = 0;
   std::string last_err;
@@ -120,6 +146,11 @@ struct mk_graph {
 
 namespace mk {
 mk_status hip_fail(mk_graph* g, hipError_t e, const char* what);
+// MK_ERR_OUT_OF_SLABS once an insert has overflowed a pool (the graph may have lost arcs).
+// With `poll` (update calls only, which never overlap other calls on the graph) it first
+// looks at completed pool snapshots, without waiting for the stream; read-only calls,
+// which may overlap each other, only read the flag.
+mk_status graph_guard(mk_graph* g, bool poll = false);
 #define MK_HIP(g, call)                                  \
   do {                                                   \
     hipError_t _e = (call);                              \

@@ -774,6 +774,7 @@ mk_status mk_bfs_levels(mk_graph* g, uint32_t source, uint32_t flags, void* d_ws
   if (!g || !d_ws || !d_level || source >= g->n || slot >= kSlots || (flags & ~MK_BFS_TOP_DOWN_ONLY))
     return MK_ERR_INVALID_ARG;
   if (ws_bytes < levels_ws_bytes(g)) return MK_ERR_CAPACITY;
+  if (mk_status gs = graph_guard(g); gs != MK_OK) return gs;
   if (!g->slot_pin[slot]) {
     if (hipHostMalloc((void**)&g->slot_pin[slot], 64 * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess)
       return MK_ERR_HIP;
@@ -801,6 +802,7 @@ mk_status mk_sssp_distances(mk_graph* g, uint32_t source, void* d_ws, size_t ws_
                             uint32_t* d_dist, hipStream_t stream) {
   if (!g || !d_ws || !d_dist || source >= g->n || slot >= kSlots) return MK_ERR_INVALID_ARG;
   if (ws_bytes < dist_ws_bytes(g)) return MK_ERR_CAPACITY;
+  if (mk_status gs = graph_guard(g); gs != MK_OK) return gs;
   if (!g->slot_pin[slot]) {
     if (hipHostMalloc((void**)&g->slot_pin[slot], 64 * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess)
       return MK_ERR_HIP;

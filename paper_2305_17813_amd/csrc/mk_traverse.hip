@@ -863,12 +863,14 @@ extern "C" {
 mk_status mk_incr_bfs(mk_graph* g, uint32_t source, uint32_t* d_level, uint32_t* d_parent,
                       mk_mode mode, hipStream_t stream) {
   if (!g) return MK_ERR_INVALID_ARG;
+  if (mk_status gs = graph_guard(g); gs != MK_OK) return gs;
   return traverse<true>(g, g->bfs, g->bfs_D, source, d_level, d_parent, mode, stream);
 }
 
 mk_status mk_incr_sssp(mk_graph* g, uint32_t source, uint32_t* d_dist, uint32_t* d_parent,
                        mk_mode mode, hipStream_t stream) {
   if (!g) return MK_ERR_INVALID_ARG;
+  if (mk_status gs = graph_guard(g); gs != MK_OK) return gs;
   return traverse<false>(g, g->sssp, g->sssp_D, source, d_dist, d_parent, mode, stream);
 }
 
@@ -878,6 +880,7 @@ mk_status mk_traverse_from(mk_graph* g, uint32_t source, int weighted, void* d_w
                            uint32_t slot, uint32_t* d_dist, uint32_t* d_parent, hipStream_t stream) {
   if (!g || !d_ws || !d_dist || source >= g->n || slot >= kSlots) return MK_ERR_INVALID_ARG;
   if (ws_bytes < ws_bytes_for(g->n)) return MK_ERR_CAPACITY;
+  if (mk_status gs = graph_guard(g); gs != MK_OK) return gs;
   if (!g->slot_pin[slot]) {
     if (hipHostMalloc((void**)&g->slot_pin[slot], 64 * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess)
       return MK_ERR_HIP;

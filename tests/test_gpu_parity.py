@@ -146,6 +146,53 @@ def test_out_of_slabs_is_clean():
     p.check_structure()  # still equal to the oracle, which saw nothing
 
 
+def test_initial_arcs_that_overflow_an_explicit_pool_are_refused():
+    """With hashing off every vertex has one chain; a star of 199 arcs needs 13 chained
+    slabs, more than an explicit pool of 2 holds.  The insert lanes that find the pool empty
+    raise the overflow bit, and creation returns MK_ERR_OUT_OF_SLABS instead of a graph that
+    silently lost arcs.  A pool with a slab per arc (lanes racing on the tail may each take
+    one before the losers return theirs) builds the same star exactly."""
+    say("case: initial arcs overflow an explicit pool")
+    n = 200
+    src = np.zeros(n - 1, np.int64)
+    dst = np.arange(1, n)
+    with pytest.raises(native.MkError) as e:
+        native.Graph(n, src, dst, np.ones(n - 1), views=native.VIEW_FWD, load_factor=0.0, pool_slabs=2)
+    assert e.value.status == 2
+    p = Pair(n, src, dst, np.ones(n - 1), views=native.VIEW_FWD, load_factor=0.0, pool_slabs=256)
+    p.check_structure()
+
+
+def test_steady_state_inserts_do_not_wait_for_the_stream():
+    """Inserts whose host-side slab bound runs short use the pool snapshots that earlier
+    inserts left behind events instead of synchronizing: with a long kernel queued ahead
+    of each insert, the stream is still busy when the insert call returns.  The graph then
+    still equals the oracle."""
+    say("case: inserts without stream synchronization")
+    g = I.rmat_s(14)
+    probe = native.Graph(g.n, g.src, g.dst, g.w)
+    used = max(probe.stats()["pool_used"])
+    del probe
+    p = make_pair(g, pool_slabs=used + 200_000)
+    wl = I.Workload(g, 12)
+    batches = [tuple(native.as_u32(x, DEV) for x in wl.insert_batch(20_000)) for _ in range(30)]
+    stream = p.g.stream
+    waited = 0
+    for s, d, w in batches:
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            torch.cuda._sleep(20_000_000)  # about 10 ms of spinning ahead of the insert
+        st = p.g.insert_edges(s, d, w)
+        waited += int(stream.query())
+        so = p.o.insert(u32(s), u32(d), u32(w))
+        assert np.array_equal(u32(st), so.astype(np.uint32))
+    torch.cuda.synchronize()
+    say(f"  inserts that found the stream drained: {waited} of {len(batches)}")
+    assert waited <= 1
+    p.check_structure()
+    p.check_all()
+
+
 def test_hashing_off_single_bucket():
     say("case: hashing off")
     g = I.rmat_s(10)
