@@ -1,6 +1,7 @@
 """GPU tests of the cost model: the HIP MLP kernels against the FP64 oracle, the batch
-features against values computed from the oracle's degrees, and the trained policy's
-regret against the always-incremental rule on held-out graph states."""
+features of all five algorithms against values built from the oracle's degrees, trees and
+labels, and the trained policy's regret against the always-incremental rule on held-out
+graph states."""
 import numpy as np
 import pytest
 import torch
@@ -61,25 +62,91 @@ def test_adam_matches_oracle_over_steps():
         assert np.abs(net.params.cpu().numpy() - po).max() <= 1e-5
 
 
-def test_batch_features_from_oracle_degrees():
-    say("case: batch features")
+INF = 0xFFFFFFFF
+
+
+def _expected_features(p, algo, ins, dels, tree=None, labels=None, pending=0):
+    """The twelve features of mk_batch_features, built in FP64 from the oracle's state:
+    out-degrees, in-degrees (from its arcs), undirected degrees, the BFS/SSSP tree of the
+    algorithm's last run (`tree` = (dist, parent)) and the WCC labels of its last run."""
+    n_v = p.n
+    out = p.o.out_degree().astype(np.float64)
+    s_all, d_all, _ = p.o.export()
+    indeg = np.bincount(d_all, minlength=n_v).astype(np.float64)
+    und = p.o.undirected_degree().astype(np.float64)
+    isrc, idst = u32(ins[0]), u32(ins[1])
+    iw = u32(ins[2]) if len(ins) > 2 else np.ones_like(isrc)
+    dsrc, ddst = u32(dels[0]), u32(dels[1])
+    srcs = np.concatenate([isrc, dsrc])
+    dsts = np.concatenate([idst, ddst])
+    n = srcs.size
+    if algo in (0, 1):
+        if tree is None:
+            aff, depth = 0.0, 0.0
+        else:
+            dist, par = (x.astype(np.uint64) for x in tree)
+            w = np.ones_like(iw, dtype=np.uint64) if algo == 0 else iw.astype(np.uint64)
+            relax = (dist[isrc] != INF) & (dist[isrc] + w < dist[idst])
+            tree_arc = (dist[ddst] != INF) & (par[ddst] == dsrc)
+            aff = (relax.sum() + tree_arc.sum()) / n
+            fin = dist[dist != INF]
+            depth = np.log2(1 + fin.max()) / 32
+    elif algo == 2:
+        joins = 0 if labels is None else (labels[isrc] != labels[idst]).sum()
+        aff = (joins + dsrc.size) / n
+        depth = 0.0
+    elif algo == 3:
+        aff = np.mean(1 / (1 + out[srcs]))
+        depth = 0.0
+    else:
+        aff = np.mean(np.log2(1 + np.minimum(und[srcs], und[dsts]))) / 32
+        depth = 0.0
+    return np.asarray([np.log2(1 + n) / 32, isrc.size / n, dsrc.size / n, np.log2(n_v) / 32,
+                       np.log2(1 + out.sum()) / 32, np.mean(np.log2(1 + out[srcs])) / 32,
+                       np.log2(1 + out[srcs].max()) / 32, np.mean(np.log2(1 + indeg[dsts])) / 32,
+                       aff, depth, np.log2(1 + pending) / 32, algo / 4], np.float32)
+
+
+@pytest.mark.parametrize("algo", [0, 1, 2, 3, 4])
+def test_batch_features_match_values_from_the_oracle(algo):
+    """Every feature of every algorithm: sizes and mix, degrees of the touched vertices
+    (out-, in- and undirected), the affected fraction (BFS/SSSP: inserts that would relax plus
+    deleted tree arcs, from the oracle's tree; WCC: inserts joining two of the oracle's
+    components plus deletions; PageRank: mean 1/(1+out-degree); triangles: mean log2 of the
+    smaller undirected degree) and the tree depth from the oracle's distances."""
+    say(f"case: batch features, algo {algo}")
     g = I.rmat_s(11)
     p = Pair(g.n, g.src, g.dst, g.w, source=I.max_out_degree_vertex(g))
-    wl = I.Workload(g, 6)
+    wl = I.Workload(g, 6 + algo)
+    # a first batch, then the algorithm runs: its state is what the features read
+    s, d, w = wl.insert_batch(200)
+    p.insert(s, d, w)
+    tree = labels = None
+    if algo == 0:
+        p.g.bfs(p.source)
+        tree = p.o.bfs(p.source)
+    elif algo == 1:
+        p.g.sssp(p.source)
+        tree = p.o.sssp(p.source)
+    elif algo == 2:
+        p.g.wcc()
+        labels = p.o.wcc()
+    elif algo == 3:
+        p.g.pagerank()
+    else:
+        p.g.triangles()
     ins = wl.insert_batch(300)
     dels = wl.delete_batch(100)
-    f = p.g.batch_features(native.VIEW_FWD * 0 + 3, ins, dels)  # PageRank features
-    out = p.o.out_degree().astype(np.float64)
-    # in-degrees from the oracle's arcs
-    s, d, _ = p.o.export()
-    indeg = np.bincount(d, minlength=g.n).astype(np.float64)
-    srcs = np.concatenate([u32(ins[0]), u32(dels[0])])
-    dsts = np.concatenate([u32(ins[1]), u32(dels[1])])
-    n = srcs.size
-    exp = [np.log2(1 + n) / 32, 300 / n, 100 / n, np.log2(g.n) / 32, np.log2(1 + out.sum()) / 32,
-           np.mean(np.log2(1 + out[srcs])) / 32, np.log2(1 + out[srcs].max()) / 32,
-           np.mean(np.log2(1 + indeg[dsts])) / 32, np.mean(1 / (1 + out[srcs])), 0.0, 0.0, 3 / 4]
-    assert np.allclose(f, np.asarray(exp, np.float32), rtol=1e-5, atol=1e-6), (f, exp)
+    f = p.g.batch_features(algo, ins, dels)
+    exp = _expected_features(p, algo, ins, dels, tree, labels)
+    assert np.allclose(f, exp, rtol=1e-5, atol=1e-6), (algo, f, exp)
+    # pending batches are counted, and the tree / labels stay those of the last run
+    p.insert(*ins)
+    p.delete(*dels)
+    ins2 = wl.insert_batch(150)
+    f2 = p.g.batch_features(algo, ins2, (torch.empty(0, dtype=torch.int32),) * 2)
+    exp2 = _expected_features(p, algo, ins2, (np.empty(0, np.uint32),) * 2, tree, labels, pending=2)
+    assert np.allclose(f2, exp2, rtol=1e-5, atol=1e-6), (algo, f2, exp2)
 
 
 def test_trained_policy_beats_always_incremental():

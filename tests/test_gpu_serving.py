@@ -1,6 +1,7 @@
 """GPU tests of the serving loop: captured query graphs replay correctly, and every result
-of a concurrent, continuously batched run equals the same request run alone in sequence
-order (integers exact, PageRank within 1e-6 in L1)."""
+of a concurrent, continuously batched run equals the oracle's answer on the graph after all
+earlier-sequenced updates, and the same request run alone in sequence order (integers
+exact, PageRank within 1e-6 in L1)."""
 import numpy as np
 import pytest
 import torch
@@ -53,16 +54,51 @@ def _compare(reqs, alone):
             assert torch.equal(r.result[0], a[0]) and torch.equal(r.result[1], a[1]), r.kind
 
 
-def _serve(cost_model, realtime, seed):
-    g = I.rmat_s(12)
+def _compare_with_oracle(g, reqs, tracked):
+    """Replay the admitted requests in sequence order on the oracle: every update is applied
+    to it, and every read must equal the oracle's answer on the graph after all updates
+    with smaller sequence numbers (statuses, found flags, weights, levels, distances and
+    parents exact; PageRank within 1e-6 in L1 of the oracle's fixed point)."""
+    import oracle
+    O = oracle.OracleGraph(g.n, u32(g.src), u32(g.dst), u32(g.w))
+    counts = {}
+    for r in sorted(reqs, key=lambda r: r.seq):
+        counts[r.kind] = counts.get(r.kind, 0) + 1
+        if r.kind == "insert":
+            if r.rejected:
+                continue
+            so = O.insert(u32(r.src), u32(r.dst), u32(r.w)).astype(np.uint32)
+            assert np.array_equal(u32(r.result), so), f"insert statuses differ (request {r.rid})"
+        elif r.kind == "delete":
+            so = O.delete(u32(r.src), u32(r.dst)).astype(np.uint32)
+            assert np.array_equal(u32(r.result), so), f"delete statuses differ (request {r.rid})"
+        elif r.kind == "query":
+            fo, wo = O.query(u32(r.src), u32(r.dst))
+            assert np.array_equal(u32(r.result[0]), fo.astype(np.uint32)), f"query {r.rid}"
+            assert np.array_equal(u32(r.result[1]), wo), f"query weights {r.rid}"
+        elif r.kind == "pagerank":
+            ro, _ = O.pagerank()
+            l1 = float(np.abs(r.result[0].double().cpu().numpy() - ro).sum())
+            assert l1 <= PR_L1_TOL, (r.rid, l1)
+        else:
+            do, po = O.bfs(r.source) if r.kind == "bfs" else O.sssp(r.source)
+            assert np.array_equal(u32(r.result[0]), do), f"{r.kind} {r.rid} from {r.source}"
+            if r.result[1] is not None:
+                assert np.array_equal(u32(r.result[1]), po), f"{r.kind} parents {r.rid}"
+    say(f"  every served result equals the oracle's: {counts}")
+
+
+def _serve(cost_model, realtime, seed, scale=12, n_req=160):
+    g = I.rmat_s(scale)
     tracked = I.max_out_degree_vertex(g)
     G = native.Graph(g.n, g.src, g.dst, g.w)
-    reqs = S.make_requests(g, I.Workload(g, seed), 160, rate=4000.0, seed=seed, tracked=tracked,
+    reqs = S.make_requests(g, I.Workload(g, seed), n_req, rate=4000.0, seed=seed, tracked=tracked,
                            upd_median=300, upd_clip=(20, 4000), q_median=2000, q_clip=(10, 20000))
     srv = S.Server(G, tracked, n_slots=4, cost_model=cost_model, keep_results=True)
     st = srv.run(reqs, realtime=realtime)
     srv.close()
     say(f"  served {len(reqs)}: {st.summary()}")
+    _compare_with_oracle(g, reqs, tracked)
     G2 = native.Graph(g.n, g.src, g.dst, g.w)
     alone = S.run_alone(G2, reqs, tracked)
     _compare(reqs, alone)
@@ -72,6 +108,14 @@ def _serve(cost_model, realtime, seed):
 def test_mixed_run_equals_alone_burst():
     say("case: serving, burst arrivals")
     st = _serve(None, realtime=False, seed=31)
+    assert st.merged_batches > 0
+
+
+def test_served_results_equal_the_oracle_at_scale_16():
+    """A larger resident graph (R-MAT scale 16, 65K vertices, 1M arcs) with the same stream
+    shape: every served result against the oracle, and against the same request alone."""
+    say("case: serving, burst arrivals, R-MAT scale 16")
+    st = _serve(None, realtime=False, seed=34, scale=16, n_req=120)
     assert st.merged_batches > 0
 
 
@@ -104,6 +148,7 @@ def test_mixed_run_compacts_when_the_pool_runs_low():
     srv.close()
     say(f"  compactions {srv.compactions}, rejected {st.rejected}: {st.summary()['p99_ms']}")
     assert srv.compactions >= 1
+    _compare_with_oracle(g, reqs, tracked)
     G2 = native.Graph(g.n, g.src, g.dst, g.w)
     alone = S.run_alone(G2, reqs, tracked)
     _compare(reqs, alone)
