@@ -208,22 +208,32 @@ def main():
     torch.cuda.synchronize()
     log("[bench] warmup done")
 
-    # byte model of the first timed step's kernels, on the graph as the step will find it
-    s, d, w, ds, dd, qs, qd = steps[args.warmup]
-    slabs = {
-        "i_fwd": G.probe_cost(1, 0, s, d), "i_rev": G.probe_cost(1, 1, s, d),
-        "i_und": G.probe_cost(1, 2, s, d), "d_fwd": G.probe_cost(0, 0, ds, dd),
-        "d_rev": G.probe_cost(0, 1, ds, dd), "d_und": G.probe_cost(0, 2, ds, dd),
-        "d_chk": G.probe_cost(0, 0, dd, ds),
-        "q_fwd": G.probe_cost(0, 0, qs, qd),
-    }
-    evs = []
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
+    def byte_model(k):
+        """Slabs each batched kernel of step k will walk, on the graph as the step finds it
+        (read-only probes, run before the step and outside its timing)."""
+        s, d, w, ds, dd, qs, qd = steps[k]
+        return {
+            "i_fwd": G.probe_cost(1, 0, s, d), "i_rev": G.probe_cost(1, 1, s, d),
+            "i_und": G.probe_cost(1, 2, s, d), "d_fwd": G.probe_cost(0, 0, ds, dd),
+            "d_rev": G.probe_cost(0, 1, ds, dd), "d_und": G.probe_cost(0, 2, ds, dd),
+            "d_chk": G.probe_cost(0, 0, dd, ds),
+            "q_fwd": G.probe_cost(0, 0, qs, qd),
+        }
+
+    # the deletes change the graph before the step's queries run: their slabs are modelled
+    # on the graph the queries meet, by a second probe after the step (also untimed)
+    evs, slab_steps, walls = [], [], []
     for k in range(args.warmup, args.warmup + args.steps):
+        sl = byte_model(k)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         evs.append(run_step(k, True))
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+        _, _, _, _, _, qs, qd = steps[k]
+        sl["q_fwd"] = G.probe_cost(0, 0, qs, qd)
+        slab_steps.append(sl)
+    wall = sum(walls)
     for ev, its in evs:
         for i, p in enumerate(phases):
             times[p].append(ev[i].elapsed_time(ev[i + 1]))
@@ -238,40 +248,44 @@ def main():
     updates_per_s = 2 * B * K / (t_ins + t_del)
     queries_per_s = Q * K / t_q
     med = lambda xs: float(np.median(xs))
+    slabs = {key: sum(sl[key] for sl in slab_steps) for key in slab_steps[0]}
 
     # per op: read the op (8 or 12 B), the walked slabs (128 B each; the head slab carries the
     # bucket count, so there is no directory read), the CAS / tombstone word (8 B per view),
-    # degree counters (4 B per view), the status byte and the change-log record (14 B)
-    q_bytes = Q * (8 + 1 + 4) + 128 * slabs["q_fwd"]
+    # degree counters (4 B per view), the status byte and the change-log record (14 B).
+    # Summed over the K timed steps, each step's slabs probed on the graph it ran on.
+    q_bytes = K * Q * (8 + 1 + 4) + 128 * slabs["q_fwd"]
     # (the four lanes of an op, one per view probe, read the op once between them)
-    i_bytes = B * (12 + 1 + 14 + 4 * (8 + 4)) + 128 * (slabs["i_fwd"] + slabs["i_rev"] + slabs["i_und"])
+    i_bytes = K * B * (12 + 1 + 14 + 4 * (8 + 4)) + 128 * (slabs["i_fwd"] + slabs["i_rev"] + slabs["i_und"])
     # a delete also leaves the undirected view only when the reverse arc is gone, which one
     # forward probe per arc decides (its slabs)
-    d_bytes = B * (8 + 1 + 14 + 2 * (8 + 4)) + 128 * (slabs["d_fwd"] + slabs["d_rev"]) \
-        + B * (8 + 2 * (8 + 4)) + 128 * slabs["d_und"] + 128 * slabs["d_chk"]
-    ins_ms = med(times["insert"])
-    q_ms = med(times["query"])
-    del_ms = med(times["delete"])
+    d_bytes = K * B * (8 + 1 + 14 + 2 * (8 + 4)) + 128 * (slabs["d_fwd"] + slabs["d_rev"]) \
+        + K * B * (8 + 2 * (8 + 4)) + 128 * slabs["d_und"] + 128 * slabs["d_chk"]
+    ins_ms = t_ins * 1e3 / K  # mean event time of one insert call
+    q_ms = t_q * 1e3 / K
+    del_ms = t_del * 1e3 / K
     roof = {
-        "kernel": "insert call = k_insert_all (fwd, rev, und views; four lanes per arc)",
+        "kernel": "insert call = k_insert_all (fwd, rev, und views; four lanes per arc) + k_spare_merge",
         "bound": "hbm",
-        "achieved": i_bytes / (ins_ms / 1e3) / 1e9,
+        "achieved": i_bytes / K / (ins_ms / 1e3) / 1e9,
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "traffic": counter_traffic(["k_insert_all"]),
-        "bytes_per_launch": i_bytes,
+        "bytes_per_launch": i_bytes / K,
         "launch_ms": ins_ms,
+        "launch_ms_median": med(times["insert"]),
     }
     roof["frac"] = roof["achieved"] / roof["peak"]
     rooflines = {
-        "k_query": {"achieved": q_bytes / (q_ms / 1e3) / 1e9, "bytes_per_launch": q_bytes, "launch_ms": q_ms,
-                    "slabs_per_op": slabs["q_fwd"] / Q, "traffic": counter_traffic(["k_query"])},
-        "k_delete_fwd+k_delete_aux": {"achieved": d_bytes / (del_ms / 1e3) / 1e9, "bytes_per_launch": d_bytes,
-                                      "launch_ms": del_ms,
+        "k_query": {"achieved": q_bytes / K / (q_ms / 1e3) / 1e9, "bytes_per_launch": q_bytes / K,
+                    "launch_ms": q_ms, "slabs_per_op": slabs["q_fwd"] / (K * Q),
+                    "traffic": counter_traffic(["k_query"])},
+        "k_delete_fwd+k_delete_aux": {"achieved": d_bytes / K / (del_ms / 1e3) / 1e9,
+                                      "bytes_per_launch": d_bytes / K, "launch_ms": del_ms,
                                       "traffic": counter_traffic(["k_delete_fwd", "k_delete_aux"])},
-        "k_insert_all": {"achieved": roof["achieved"], "bytes_per_launch": i_bytes, "launch_ms": ins_ms,
-                                      "traffic": roof["traffic"],
-                     "slabs_per_op": {k: slabs[k] / B for k in ("i_fwd", "i_rev", "i_und")}},
+        "k_insert_all": {"achieved": roof["achieved"], "bytes_per_launch": i_bytes / K, "launch_ms": ins_ms,
+                         "traffic": roof["traffic"],
+                         "slabs_per_op": {k: slabs[k] / (K * B) for k in ("i_fwd", "i_rev", "i_und")}},
     }
     # PageRank: one pull iteration reads the reverse view's slabs (128 B each; vertices
     # without in-arcs are skipped, so this over-counts), gathers a 4 B contribution per arc
