@@ -57,7 +57,8 @@ typedef enum {
 } mk_status;
 
 typedef enum {
-  MK_AUTO = 0,      /* incremental when the pending batches allow it, else recompute      */
+  MK_AUTO = 0,      /* incremental when the pending batches allow it, else recompute; with
+                       a cost model set (mk_set_cost_model) the model decides between them  */
   MK_INCR = 1,      /* incremental if at all possible (falls back to recompute if not)    */
   MK_RECOMPUTE = 2  /* recompute from scratch on the current graph                        */
 } mk_mode;
@@ -244,6 +245,19 @@ typedef enum {
 mk_status mk_incr_wcc_scheme(mk_graph* g, uint32_t* d_label, mk_mode mode, mk_wcc_scheme scheme,
                              hipStream_t stream);
 
+/* How all-vertex walks are scheduled (section 3.4, IterationScheme1 and IterationScheme2).
+ * SCHEME1 (the default) gives each vertex to one worker: a lane for a single-bucket vertex,
+ * a 16-lane group for up to 16 buckets, work items of a few buckets for larger ones.
+ * SCHEME2 gives each bucket chain <v, i> to a 16-lane group in a grid-stride loop over the
+ * list of all <vertex, bucket> pairs (built once from one exclusive scan of the bucket
+ * counts, which never change after creation); a per-vertex pass then adds the buckets'
+ * partial results in bucket order.  The scheme applies to the PageRank pull over the
+ * reverse view and to the union over every arc of a static (or naive incremental) WCC.
+ * Results are the same under either scheme (PageRank within its tolerance).
+ * MK_ERR_INVALID_ARG for an unknown scheme. */
+typedef enum { MK_ITER_SCHEME1 = 1, MK_ITER_SCHEME2 = 2 } mk_iter_scheme;
+mk_status mk_set_iteration_scheme(mk_graph* g, mk_iter_scheme scheme);
+
 /* PageRank (section 4.1): PR'(v) = (1-d)/N + d * (sum over in-arcs u->v of PR(u)/out(u)
  * + sum over zero-out-degree z of PR(z)/N), iterated from 1/N (first call, RECOMPUTE) or
  * from the previous vector (incremental and decremental batches) until the L1 change of
@@ -326,6 +340,16 @@ enum { MK_ALGO_BFS = 0, MK_ALGO_SSSP = 1, MK_ALGO_WCC = 2, MK_ALGO_PAGERANK = 3,
 mk_status mk_batch_features(mk_graph* g, int algo, const uint32_t* d_ins_src, const uint32_t* d_ins_dst,
                             const uint32_t* d_ins_w, uint64_t n_ins, const uint32_t* d_del_src,
                             const uint32_t* d_del_dst, uint64_t n_del, float* h_out, hipStream_t stream);
+
+/* Hand the cost model to the graph.  d_params: MK_MLP_PARAMS floats on the device (the
+ * caller's; they are read at every MK_AUTO decision, so they must stay valid until cleared
+ * or the graph is destroyed), or NULL to clear.  With a model set, an algorithm called with
+ * MK_AUTO on pending batches that it could apply incrementally computes the features of
+ * those batches (as mk_batch_features, over the change log, with every pending batch taken
+ * as applied) and runs the MLP forward kernel: it recomputes when the predicted recompute
+ * time is below the predicted incremental time.  That decision synchronizes the stream.
+ * Without a model MK_AUTO applies the batches incrementally whenever it can. */
+mk_status mk_set_cost_model(mk_graph* g, const float* d_params);
 
 /* Bytes of device workspace mk_mlp_grad needs for a minibatch of n samples. */
 size_t mk_mlp_workspace_bytes(uint32_t n);

@@ -21,6 +21,7 @@ constexpr uint32_t kWalkBlocks = 4096;
 constexpr uint32_t kPrContribBlocks = 2048, kPrFinalBlocks = 512;
 static_assert(kPrContribBlocks + kWalkBlocks + kPrFinalBlocks <= kPrParts, "PageRank partial sums");
 constexpr uint32_t kPrChunk = 4;  // buckets per heavy-vertex work item
+constexpr uint32_t kPrBatch = 8;  // head slabs a group loads at once in the PageRank pull
 constexpr int kPrSyncEvery = 4;
 
 inline uint32_t blocks_for(uint64_t n, uint32_t cap = 4096) {
@@ -124,6 +125,38 @@ __global__ void __launch_bounds__(kBlock) k_wcc_all(DView F, uint32_t* P, uint32
     const uint32_t u = heavy[j];
     const uint32_t ru = uf_find(P, u);
     for_each_slab_strided(F, u, gib, kGroupsPerBlock, [&](uint64_t x, bool data) { body(u, ru, x, data); });
+  }
+}
+
+// IterationScheme2 (section 3.4): one 16-lane group per bucket chain <v, i>, in a
+// grid-stride loop over the pair list.  Bucket i > 0 of v is the extra head slab
+// N + off[v] - v + i - 1 = N + k - v - 1 (the extra head slabs were laid out by the same
+// scan); bucket 0 is v's primary slab, with 14 data words when v has several buckets.
+template <class F>
+__device__ inline void walk_pair(const DView& V, const uint32_t* pv, const uint32_t* pi, uint32_t nv,
+                                 uint32_t k, uint32_t& v, F&& f) {
+  v = pv[k];
+  const uint32_t i = pi[k];
+  const uint32_t h = i == 0 ? v : nv + k - v - 1;
+  const uint64_t x = ld_word(slab_ptr(V, h) + glane());
+  int nd = kKeysPerSlab;
+  if (i == 0 && (uint32_t)(gbcast64(x, 15) >> 32) > 1) nd = kKeysPerSlab - 1;
+  walk_chain(V, h, x, nd, f);
+}
+
+// Static WCC under IterationScheme2: union over the arcs of every bucket chain.
+__global__ void __launch_bounds__(kBlock) k_wcc_pairs(DView F, uint32_t* P, const uint32_t* pv,
+                                                      const uint32_t* pi, uint32_t np, uint32_t nv) {
+  const uint32_t g0 = (blockIdx.x * kBlock + threadIdx.x) / kGroup;
+  const uint32_t ng = gridDim.x * kGroupsPerBlock;
+  for (uint32_t k = g0; k < np; k += ng) {
+    const uint32_t u = pv[k];
+    const uint32_t ru = uf_find(P, u);
+    uint32_t vv;
+    walk_pair(F, pv, pi, nv, k, vv, [&](uint64_t x, bool data) {
+      const uint32_t v = (uint32_t)x;
+      if (data && valid_key(v) && ld_u32(P + v) != ru) uf_union(P, u, v);
+    });
   }
 }
 
@@ -370,17 +403,42 @@ __global__ void __launch_bounds__(kBlock) k_pr_gather(DView R, const float* __re
     y[v] = nvl;
     local += fabs((double)nvl - (double)x[v]);
   }
-  // vertices with 2 .. kHeavyBuckets buckets: one 16-lane group per vertex
+  // vertices with 2 .. kHeavyBuckets buckets: one 16-lane group per vertex.  The group
+  // issues the loads of all its head slabs at once, then all their contribution gathers,
+  // and only then follows the (rare) chains, rather than one dependent slab at a time.
   const uint32_t g0 = (blockIdx.x * kBlock + threadIdx.x) / kGroup;
   const uint32_t ng = gridDim.x * kGroupsPerBlock;
+  const int gl = glane();
   for (uint32_t v = g0; v < nv; v += ng) {
     const uint32_t nb = R.nbk[v];
     if (nb == 1 || nb > kHeavyBuckets) continue;
+    const uint64_t x0 = ld_word(slab_ptr(R, v) + gl);
+    const uint32_t xb = gbcast((uint32_t)x0, 14);
     double s = 0;
-    for_each_slab(R, v, [&](uint64_t w, bool data) {
-      const uint32_t u = (uint32_t)w;
-      if (data && valid_key(u)) s += (double)c[u];
-    });
+    for (uint32_t b0 = 0; b0 < nb; b0 += kPrBatch) {
+      uint64_t hw[kPrBatch];
+#pragma unroll
+      for (uint32_t j = 0; j < kPrBatch; ++j) {
+        const uint32_t b = b0 + j;
+        hw[j] = b == 0 ? x0 : (b < nb ? ld_word(slab_ptr(R, xb + b - 1) + gl) : kEmptyWord);
+      }
+#pragma unroll
+      for (uint32_t j = 0; j < kPrBatch; ++j) {
+        const uint32_t u = (uint32_t)hw[j];
+        const bool data = gl < (b0 + j == 0 ? kKeysPerSlab - 1 : kKeysPerSlab);
+        if (data && valid_key(u)) s += (double)c[u];
+      }
+#pragma unroll
+      for (uint32_t j = 0; j < kPrBatch; ++j) {  // chained slabs after a full head slab
+        if (b0 + j >= nb) break;
+        const uint32_t next = gbcast((uint32_t)hw[j], 15);
+        if (next == kInvalid) continue;
+        walk_chain(R, next, ld_word(slab_ptr(R, next) + gl), kKeysPerSlab, [&](uint64_t w, bool data) {
+          const uint32_t u = (uint32_t)w;
+          if (data && valid_key(u)) s += (double)c[u];
+        });
+      }
+    }
     s = gsum(s);
     if (glane() == 0) {
       const float nvl = (float)(base + (double)damping * s);
@@ -410,6 +468,48 @@ __global__ void __launch_bounds__(kBlock) k_pr_gather(DView R, const float* __re
       s = gsum(s);
       if (glane() == 0 && s != 0.0) atomicAdd(hacc + lo, s);
     }
+  }
+  const double s = block_sum(local, lds);
+  if (threadIdx.x == 0) delta[blockIdx.x] = s;
+}
+
+// PageRank pull under IterationScheme2: the FP64 in-arc sum of every reverse-view bucket
+// chain into pp[k]; k_pr_final_s2 adds a vertex's buckets in bucket order.
+__global__ void __launch_bounds__(kBlock) k_pr_gather_s2(DView R, const float* __restrict__ c,
+                                                         const uint32_t* pv, const uint32_t* pi, uint32_t np,
+                                                         uint32_t nv, double* __restrict__ pp,
+                                                         const uint32_t* state) {
+  if (state[0]) return;
+  const uint32_t g0 = (blockIdx.x * kBlock + threadIdx.x) / kGroup;
+  const uint32_t ng = gridDim.x * kGroupsPerBlock;
+  for (uint32_t k = g0; k < np; k += ng) {
+    double s = 0;
+    uint32_t v;
+    walk_pair(R, pv, pi, nv, k, v, [&](uint64_t w, bool data) {
+      const uint32_t u = (uint32_t)w;
+      if (data && valid_key(u)) s += (double)c[u];
+    });
+    s = gsum(s);
+    if (glane() == 0) pp[k] = s;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_pr_final_s2(const uint32_t* __restrict__ nbk,
+                                                        const uint32_t* __restrict__ off,
+                                                        const double* __restrict__ pp, const float* __restrict__ x,
+                                                        float* __restrict__ y, uint32_t nv, float damping,
+                                                        const double* dang, double* delta, const uint32_t* state) {
+  __shared__ double lds[kBlock / 64];
+  if (state[0]) return;
+  const double base = (1.0 - (double)damping) / nv + (double)damping * (*dang) / nv;
+  double local = 0;
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
+    const uint32_t o = off[v], nb = nbk[v];
+    double s = 0;
+    for (uint32_t i = 0; i < nb; ++i) s += pp[o + i];
+    const float nvl = (float)(base + (double)damping * s);
+    y[v] = nvl;
+    local += fabs((double)nvl - (double)x[v]);
   }
   const double s = block_sum(local, lds);
   if (threadIdx.x == 0) delta[blockIdx.x] = s;
@@ -689,6 +789,48 @@ Log log_at(const mk_graph* g, uint64_t off) {
   return l;
 }
 
+// PageRank iterations under IterationScheme2 from the ranks in g->pr_x (the caller has
+// initialized or kept them): contributions, one group per reverse-view bucket chain, then
+// the per-vertex sums in bucket order.
+mk_status pagerank_scheme2(mk_graph* g, float damping, double tol_l1, uint32_t max_iter, float* d_rank,
+                           uint32_t* d_iters, hipStream_t stream) {
+  const uint32_t N = g->n;
+  if (mk_status st = ensure_pairs(g, VR, stream); st != MK_OK) return st;
+  const ViewHost& vh = g->view[VR];
+  hipLaunchKernelGGL(k_pr_start, dim3(1), dim3(64), 0, stream, g->ctr);
+  float* buf[2] = {g->pr_x, g->pr_y};
+  const uint32_t cb = blocks_for(N, kPrContribBlocks);
+  double* dpart = g->pr_part + kPrContribBlocks;
+  uint32_t it = 0;
+  while (true) {
+    for (int k = 0; k < kPrSyncEvery; ++k, ++it) {
+      const int slot = it & 3;
+      const float* x = buf[it & 1];
+      float* y = buf[(it + 1) & 1];
+      double* dang = &g->ctr->pr_acc[2 * slot];
+      hipLaunchKernelGGL(k_pr_contrib, dim3(cb), dim3(kBlock), 0, stream, x, g->view[VF].d.deg, g->pr_c,
+                         N, g->pr_part, g->ctr->pr_state);
+      hipLaunchKernelGGL(k_pr_sum, dim3(1), dim3(kBlock), 0, stream, g->pr_part, cb, dang, g->ctr->pr_state);
+      hipLaunchKernelGGL(k_pr_gather_s2, dim3(kWalkBlocks), dim3(kBlock), 0, stream, vh.d, g->pr_c,
+                         vh.pair_v, vh.pair_i, (uint32_t)vh.n_head, N, g->pr_pair, g->ctr->pr_state);
+      hipLaunchKernelGGL(k_pr_final_s2, dim3(kWalkBlocks), dim3(kBlock), 0, stream, vh.nbk, vh.pair_off,
+                         g->pr_pair, x, y, N, damping, dang, dpart, g->ctr->pr_state);
+      hipLaunchKernelGGL(k_pr_check, dim3(1), dim3(kBlock), 0, stream, g->ctr, slot, tol_l1, max_iter, dpart,
+                         kWalkBlocks);
+      MK_LAUNCH(g, "pagerank iteration (scheme 2)");
+    }
+    MK_HIP(g, hipMemcpyAsync(g->h_pin, g->ctr->pr_state, 8, hipMemcpyDeviceToHost, stream));
+    MK_HIP(g, hipStreamSynchronize(stream));
+    if (reinterpret_cast<const uint32_t*>(g->h_pin)[0]) break;
+  }
+  hipLaunchKernelGGL(k_pr_final, dim3(blocks_for(N)), dim3(kBlock), 0, stream, g->ctr, g->pr_x,
+                     g->pr_y, g->pr_x, d_rank, N, d_iters);
+  MK_LAUNCH(g, "pagerank final");
+  g->pr.valid = true;
+  mark_seen(g, g->pr);
+  return MK_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -703,19 +845,30 @@ mk_status mk_incr_wcc_scheme(mk_graph* g, uint32_t* d_label, mk_mode mode, mk_wc
   if (mk_status gs = graph_guard(g); gs != MK_OK) return gs;
   const uint32_t N = g->n;
   Pending p = pending_for(g, g->wcc);
-  const bool full = mode == MK_RECOMPUTE || !g->wcc.valid || p.lost || (p.kinds & 2);
+  bool full = mode == MK_RECOMPUTE || !g->wcc.valid || p.lost || (p.kinds & 2);
+  if (!full && mode == MK_AUTO)
+    if (mk_status s = auto_prefers_recompute(g, MK_ALGO_WCC, p, stream, &full); s != MK_OK) return s;
   uint32_t* P = g->wcc_parent;
   const DView F = g->view[VF].d;
-  auto all_arcs = [&]() {  // union over every arc (collecting the heavy vertices first)
+  auto all_arcs = [&]() -> mk_status {  // union over every arc
+    if (g->iter_scheme == MK_ITER_SCHEME2) {  // one group per bucket chain
+      if (mk_status st = ensure_pairs(g, VF, stream); st != MK_OK) return st;
+      const ViewHost& vh = g->view[VF];
+      hipLaunchKernelGGL(k_wcc_pairs, dim3(kWalkBlocks), dim3(kBlock), 0, stream, F, P, vh.pair_v, vh.pair_i,
+                         (uint32_t)vh.n_head, N);
+      return MK_OK;
+    }
+    // IterationScheme1, collecting the heavy vertices first
     uint32_t* nh = &g->ctr->n_heavy_wcc;
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, nh, 1u);
     hipLaunchKernelGGL(k_collect_heavy, dim3(blocks_for(N)), dim3(kBlock), 0, stream,
                        g->view[VF].nbk, N, g->fq[2], nh);
     hipLaunchKernelGGL(k_wcc_all, dim3(kWalkBlocks), dim3(kBlock), 0, stream, F, P, N, g->fq[2], nh);
+    return MK_OK;
   };
   if (full) {
     hipLaunchKernelGGL(k_wcc_init, dim3(blocks_for(N)), dim3(kBlock), 0, stream, P, N);
-    all_arcs();
+    if (mk_status st = all_arcs(); st != MK_OK) return st;
     if (scheme == MK_WCC_UPDATE)
       hipLaunchKernelGGL(k_mark_all, dim3(grid_for_groups(std::min<uint64_t>(g->view[VF].n_head, 1u << 20))),
                          dim3(kBlock), 0, stream, F, g->upd_mark, g->view[VF].n_head, N);
@@ -725,7 +878,7 @@ mk_status mk_incr_wcc_scheme(mk_graph* g, uint32_t* d_label, mk_mode mode, mk_wc
         hipLaunchKernelGGL(k_wcc_batch, dim3(blocks_for(b->n)), dim3(kBlock), 0, stream, P,
                            log_at(g, b->off), b->n);
     } else if (scheme == MK_WCC_NAIVE) {
-      all_arcs();
+      if (mk_status st = all_arcs(); st != MK_OK) return st;
     } else {
       uint32_t* nl = &g->ctr->n_listed_light;
       uint32_t* nh = &g->ctr->n_listed_heavy;
@@ -760,7 +913,12 @@ mk_status mk_incr_pagerank(mk_graph* g, float damping, double tol_l1, uint32_t m
   const uint32_t N = g->n;
   Pending p = pending_for(g, g->pr);
   if (mk_status gs = graph_guard(g); gs != MK_OK) return gs;
-  const bool warm = mode != MK_RECOMPUTE && g->pr.valid && !p.lost;
+  bool warm = mode != MK_RECOMPUTE && g->pr.valid && !p.lost;
+  if (warm && mode == MK_AUTO) {
+    bool rec = false;
+    if (mk_status s = auto_prefers_recompute(g, MK_ALGO_PAGERANK, p, stream, &rec); s != MK_OK) return s;
+    warm = !rec;
+  }
   if (warm && p.list.empty()) {
     hipLaunchKernelGGL(k_pr_start, dim3(1), dim3(64), 0, stream, g->ctr);
     hipLaunchKernelGGL(k_pr_final, dim3(blocks_for(N)), dim3(kBlock), 0, stream, g->ctr, g->pr_x,
@@ -770,6 +928,7 @@ mk_status mk_incr_pagerank(mk_graph* g, float damping, double tol_l1, uint32_t m
   }
   if (!warm)
     hipLaunchKernelGGL(k_pr_fill, dim3(blocks_for(N)), dim3(kBlock), 0, stream, g->pr_x, N, 1.f / N);
+  if (g->iter_scheme == MK_ITER_SCHEME2) return pagerank_scheme2(g, damping, tol_l1, max_iter, d_rank, d_iters, stream);
   uint32_t* nh = &g->ctr->n_heavy_pr;
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, nh, 1u);
   hipLaunchKernelGGL(k_collect_heavy, dim3(blocks_for(N)), dim3(kBlock), 0, stream, g->view[VR].nbk,
@@ -832,7 +991,9 @@ mk_status mk_count_triangles(mk_graph* g, uint64_t* d_count, mk_mode mode, hipSt
   const DView U = g->view[VU].d;
   if (mk_status gs = graph_guard(g); gs != MK_OK) return gs;
   Pending p = pending_for(g, g->tc);
-  const bool full = mode == MK_RECOMPUTE || !g->tc.valid || p.lost || p.kinds == 3;
+  bool full = mode == MK_RECOMPUTE || !g->tc.valid || p.lost || p.kinds == 3;
+  if (!full && mode == MK_AUTO)
+    if (mk_status s = auto_prefers_recompute(g, MK_ALGO_TC, p, stream, &full); s != MK_OK) return s;
   unsigned long long* out = reinterpret_cast<unsigned long long*>(d_count);
   if (full) {
     uint32_t* nh = &g->ctr->n_heavy_tc;

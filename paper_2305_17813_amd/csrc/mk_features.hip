@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "mk_internal.h"
 
@@ -100,13 +101,10 @@ inline uint32_t blocks_for(uint64_t n, uint32_t cap = 2048) {
 
 }  // namespace
 
-extern "C" mk_status mk_batch_features(mk_graph* g, int algo, const uint32_t* d_ins_src,
-                                       const uint32_t* d_ins_dst, const uint32_t* d_ins_w, uint64_t n_ins,
-                                       const uint32_t* d_del_src, const uint32_t* d_del_dst, uint64_t n_del,
-                                       float* h_out, hipStream_t stream) {
-  if (!g || !h_out || algo < 0 || algo > 4) return MK_ERR_INVALID_ARG;
-  if ((n_ins && (!d_ins_src || !d_ins_dst)) || (n_del && (!d_del_src || !d_del_dst))) return MK_ERR_INVALID_ARG;
-  if (mk_status gs = graph_guard(g); gs != MK_OK) return gs;
+namespace mk {
+
+mk_status batch_features(mk_graph* g, int algo, const FeatPart* parts, int n_parts, float* h_out,
+                         hipStream_t stream) {
   const DView F = g->view[VF].d;
   const uint32_t* indeg = g->view[VR].on ? g->view[VR].d.deg : nullptr;
   const uint32_t* undeg = g->view[VU].on ? g->view[VU].d.deg : nullptr;
@@ -115,12 +113,14 @@ extern "C" mk_status mk_batch_features(mk_graph* g, int algo, const uint32_t* d_
   if (algo == MK_ALGO_SSSP && g->sssp.valid) D = g->sssp_D;
   const uint32_t* labels = (algo == MK_ALGO_WCC && g->wcc.valid) ? g->wcc_parent : nullptr;
   hipLaunchKernelGGL(k_feat_reset, dim3(1), dim3(64), 0, stream, g->ctr);
-  if (n_ins)
-    hipLaunchKernelGGL(k_feat_ops, dim3(blocks_for(n_ins)), dim3(kBlock), 0, stream, F, indeg, undeg, D, labels,
-                       algo, false, d_ins_src, d_ins_dst, d_ins_w, n_ins, g->n, g->ctr);
-  if (n_del)
-    hipLaunchKernelGGL(k_feat_ops, dim3(blocks_for(n_del)), dim3(kBlock), 0, stream, F, indeg, undeg, D, labels,
-                       algo, true, d_del_src, d_del_dst, (const uint32_t*)nullptr, n_del, g->n, g->ctr);
+  uint64_t n_ins = 0, n_del = 0;
+  for (int i = 0; i < n_parts; ++i) {
+    const FeatPart& q = parts[i];
+    if (!q.n) continue;
+    (q.del ? n_del : n_ins) += q.n;
+    hipLaunchKernelGGL(k_feat_ops, dim3(blocks_for(q.n)), dim3(kBlock), 0, stream, F, indeg, undeg, D, labels,
+                       algo, q.del, q.src, q.dst, q.del ? (const uint32_t*)nullptr : q.w, q.n, g->n, g->ctr);
+  }
   hipLaunchKernelGGL(k_feat_graph, dim3(blocks_for(g->n)), dim3(kBlock), 0, stream, D, F.deg, g->n, g->ctr);
   MK_LAUNCH(g, "k_feat");
   double host[6];
@@ -147,5 +147,47 @@ extern "C" mk_status mk_batch_features(mk_graph* g, int algo, const uint32_t* d_
   h_out[9] = (float)(std::log2(1.0 + (D ? hmax[1] : 0u)) / 32.0);
   h_out[10] = (float)(std::log2(1.0 + pending) / 32.0);
   h_out[11] = (float)algo / 4.f;
+  return MK_OK;
+}
+
+mk_status auto_prefers_recompute(mk_graph* g, int algo, const Pending& p, hipStream_t stream, bool* out) {
+  *out = false;
+  if (!g->cm_params || p.list.empty()) return MK_OK;
+  std::vector<FeatPart> parts;
+  for (const BatchRec* b : p.list)
+    parts.push_back(FeatPart{g->log.s + b->off, g->log.d + b->off, g->log.w + b->off, b->n,
+                             b->kind == kDeleteBatch});
+  float x[MK_MLP_IN];
+  if (mk_status st = batch_features(g, algo, parts.data(), (int)parts.size(), x, stream); st != MK_OK) return st;
+  // features through pinned memory to the device, the forward pass, the outputs back
+  float* hx = reinterpret_cast<float*>(g->h_pin + 16);
+  float* hy = reinterpret_cast<float*>(g->h_pin + 32);
+  std::memcpy(hx, x, sizeof(x));
+  MK_HIP(g, hipMemcpyAsync(g->ctr->mlp_x, hx, sizeof(x), hipMemcpyHostToDevice, stream));
+  mlp_forward_launch(g->cm_params, g->ctr->mlp_x, 1, g->ctr->mlp_y, stream);
+  MK_LAUNCH(g, "cost model forward");
+  MK_HIP(g, hipMemcpyAsync(hy, g->ctr->mlp_y, MK_MLP_OUT * sizeof(float), hipMemcpyDeviceToHost, stream));
+  MK_HIP(g, hipStreamSynchronize(stream));
+  *out = hy[1] < hy[0];  // predicted log ms: recompute below incremental
+  return MK_OK;
+}
+
+}  // namespace mk
+
+extern "C" mk_status mk_batch_features(mk_graph* g, int algo, const uint32_t* d_ins_src,
+                                       const uint32_t* d_ins_dst, const uint32_t* d_ins_w, uint64_t n_ins,
+                                       const uint32_t* d_del_src, const uint32_t* d_del_dst, uint64_t n_del,
+                                       float* h_out, hipStream_t stream) {
+  if (!g || !h_out || algo < 0 || algo > 4) return MK_ERR_INVALID_ARG;
+  if ((n_ins && (!d_ins_src || !d_ins_dst)) || (n_del && (!d_del_src || !d_del_dst))) return MK_ERR_INVALID_ARG;
+  if (mk_status gs = graph_guard(g); gs != MK_OK) return gs;
+  const FeatPart parts[2] = {{d_ins_src, d_ins_dst, d_ins_w, n_ins, false},
+                             {d_del_src, d_del_dst, nullptr, n_del, true}};
+  return batch_features(g, algo, parts, 2, h_out, stream);
+}
+
+extern "C" mk_status mk_set_cost_model(mk_graph* g, const float* d_params) {
+  if (!g || ((uintptr_t)d_params & 3)) return MK_ERR_INVALID_ARG;
+  g->cm_params = d_params;
   return MK_OK;
 }

@@ -410,6 +410,17 @@ __global__ void k_extra_total(const uint32_t* nb, const uint32_t* xrel, uint32_t
   if (threadIdx.x == 0) *total = (unsigned long long)xrel[nv - 1] + nb[nv - 1] - 1;
 }
 
+// IterationScheme2 pairs: bucket k = off[v] + i of vertex v becomes <v, i>.
+__global__ void k_pairs_build(const uint32_t* nbk, const uint32_t* off, uint32_t nv, uint32_t* pv, uint32_t* pi) {
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
+    const uint32_t o = off[v], nb = nbk[v];
+    for (uint32_t i = 0; i < nb; ++i) {
+      pv[o + i] = v;
+      pi[o + i] = i;
+    }
+  }
+}
+
 // ============================================================ device: export / stats / check
 __global__ void __launch_bounds__(kBlock) k_export(DView F, uint32_t nv, uint32_t* os, uint32_t* od,
                                                    uint32_t* ow, unsigned long long cap,
@@ -699,7 +710,7 @@ bool layout(const mk_config* c, uint64_t m, char* base, mk_graph* g, size_t* tot
   Carver cv{base};
   const uint32_t N = c->n_vertices;
   const uint32_t views = c->views | MK_VIEW_FWD;
-  uint64_t hb_fwd = 0;
+  uint64_t hb_fwd = 0, hb_rev = 0;
   for (int v = 0; v < 3; ++v) {
     const bool on = views & (1u << v);
     if (!on) continue;
@@ -713,6 +724,13 @@ bool layout(const mk_config* c, uint64_t m, char* base, mk_graph* g, size_t* tot
     uint32_t* pctr = cv.take<uint32_t>(64);
     uint32_t* free_ids = cv.take<uint32_t>(pc);
     uint32_t* spare_ids = cv.take<uint32_t>(pc);
+    uint32_t *pair_v = nullptr, *pair_i = nullptr, *pair_off = nullptr;
+    if (v != VU) {  // IterationScheme2 work lists: one entry per head slab
+      pair_v = cv.take<uint32_t>(hb);
+      pair_i = cv.take<uint32_t>(hb);
+      pair_off = cv.take<uint32_t>(N);
+    }
+    if (v == VR) hb_rev = hb;
     if (g) {
       ViewHost& vh = g->view[v];
       vh.on = true;
@@ -726,6 +744,9 @@ bool layout(const mk_config* c, uint64_t m, char* base, mk_graph* g, size_t* tot
       vh.d.free_ids = free_ids;
       vh.d.spare_ids = spare_ids;
       vh.d.pool_cap = (uint32_t)pc;
+      vh.pair_v = pair_v;
+      vh.pair_i = pair_i;
+      vh.pair_off = pair_off;
     }
   }
   const uint64_t L = log_default(c, m);
@@ -752,6 +773,7 @@ bool layout(const mk_config* c, uint64_t m, char* base, mk_graph* g, size_t* tot
   uint32_t* hv = cv.take<uint32_t>(N);
   double* hacc = cv.take<double>(N);
   double* prp = cv.take<double>(kPrParts);
+  double* prpair = hb_rev ? cv.take<double>(hb_rev) : nullptr;
   uint64_t* umark = cv.take<uint64_t>(hb_fwd);
   uint32_t* wflag = cv.take<uint32_t>(N);
   char* lvc = cv.take<char>(256);
@@ -792,6 +814,7 @@ bool layout(const mk_config* c, uint64_t m, char* base, mk_graph* g, size_t* tot
     g->heavy_rev = hv;
     g->pr_hacc = hacc;
     g->pr_part = prp;
+    g->pr_pair = prpair;
     g->upd_mark = umark;
     g->wcc_flag = wflag;
     g->lv_cnt = lvc;
@@ -973,6 +996,24 @@ void launch_insert(mk_graph* g, const uint32_t* s, const uint32_t* d, const uint
 }
 
 }  // namespace
+
+namespace mk {
+mk_status ensure_pairs(mk_graph* g, int v, hipStream_t stream) {
+  ViewHost& vh = g->view[v];
+  if (!vh.on || !vh.pair_v) return MK_ERR_STATE;
+  if (vh.pairs_ok) return MK_OK;
+  size_t tb = g->scan_tmp_bytes;
+  if (rocprim::exclusive_scan(g->scan_tmp, tb, vh.nbk, vh.pair_off, 0u, (size_t)g->n, rocprim::plus<uint32_t>(),
+                              stream) != hipSuccess)
+    return MK_ERR_HIP;
+  hipLaunchKernelGGL(k_pairs_build, dim3(grid_stride_blocks(g->n)), dim3(kBlock), 0, stream, vh.nbk,
+                     vh.pair_off, g->n, vh.pair_v, vh.pair_i);
+  MK_LAUNCH(g, "k_pairs_build");
+  vh.pairs_ok = true;
+  return MK_OK;
+}
+
+}  // namespace mk
 
 // ============================================================ C-ABI
 extern "C" {
@@ -1266,6 +1307,12 @@ mk_status mk_probe_cost(mk_graph* g, int op, int view, const uint32_t* d_src, co
   MK_HIP(g, hipMemcpyAsync(g->h_pin, acc, 8, hipMemcpyDeviceToHost, stream));
   MK_HIP(g, hipStreamSynchronize(stream));
   *h_slabs = g->h_pin[0];
+  return MK_OK;
+}
+
+mk_status mk_set_iteration_scheme(mk_graph* g, mk_iter_scheme scheme) {
+  if (!g || (scheme != MK_ITER_SCHEME1 && scheme != MK_ITER_SCHEME2)) return MK_ERR_INVALID_ARG;
+  g->iter_scheme = scheme;
   return MK_OK;
 }
 

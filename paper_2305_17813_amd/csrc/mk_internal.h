@@ -39,6 +39,13 @@ struct ViewHost {
   uint64_t pool_hw = 0;        // bump-pointer high-water mark read back last
   uint64_t added = 0;          // slabs the inserts so far may have taken (running sum of
                                // the per-call bounds; snapshots are placed against it)
+  // IterationScheme2 work list (fwd and rev views): bucket k = off[v] + i of vertex v is the
+  // pair <pair_v[k], pair_i[k]> = <v, i>, with off the exclusive scan of the bucket counts.
+  // Bucket counts never change after creation, so the list is built once, when first used.
+  uint32_t* pair_v = nullptr;
+  uint32_t* pair_i = nullptr;
+  uint32_t* pair_off = nullptr;
+  bool pairs_ok = false;
 };
 
 struct AlgoState {
@@ -70,6 +77,8 @@ struct Counters {          // device-side scalars, one 4 KiB block
   uint32_t feat_max[2];    // batch-feature maxima
   uint32_t snap[16];       // pool snapshot staging: view v's bump, free-end and free-take
                            // counters at [4v, 4v+3), the overflow bits at [12]
+  float mlp_x[16];         // features of an MK_AUTO decision (MK_MLP_IN used)
+  float mlp_y[4];          // the cost model's outputs for them (MK_MLP_OUT used)
 };
 
 // Asynchronous pool snapshots: after an insert that leaves the host-side bound short of
@@ -125,6 +134,9 @@ struct mk_graph {
   uint32_t* heavy_rev = nullptr;  // rev-view vertices split into bucket work items
   double* pr_hacc = nullptr;      // FP64 partial sums of the heavy vertices
   double* pr_part = nullptr;      // FP64 per-block partial sums of one iteration (kPrParts)
+  double* pr_pair = nullptr;      // FP64 in-arc sum per reverse-view bucket (IterationScheme2)
+  int iter_scheme = MK_ITER_SCHEME1;  // how all-vertex walks are scheduled
+  const float* cm_params = nullptr;   // cost-model parameters for MK_AUTO (device, caller's)
   uint32_t n_heavy_rev = 0;
   bool heavy_rev_ok = false;
 
@@ -175,6 +187,25 @@ struct Pending {
 };
 Pending pending_for(const mk_graph* g, const AlgoState& st);
 void mark_seen(mk_graph* g, AlgoState& st);
+
+// One stretch of update ops for the batch features: n ops at src/dst/w (w may be null),
+// deletions or insertions.
+struct FeatPart {
+  const uint32_t *src, *dst, *w;
+  uint64_t n;
+  bool del;
+};
+// The MK_MLP_IN features of mk_batch_features over any number of parts (synchronizes).
+mk_status batch_features(mk_graph* g, int algo, const FeatPart* parts, int n_parts, float* h_out,
+                         hipStream_t stream);
+// The MLP forward pass (one thread per sample; mk_mlp_forward without argument checks).
+void mlp_forward_launch(const float* params, const float* x, uint32_t n, float* y, hipStream_t stream);
+// MK_AUTO with a cost model set: true when the model predicts a recompute of `algo` to be
+// faster than applying the pending batches `p` incrementally (synchronizes).
+mk_status auto_prefers_recompute(mk_graph* g, int algo, const Pending& p, hipStream_t stream, bool* out);
+
+// IterationScheme2 work list of view v (built on first use; see ViewHost::pair_v).
+mk_status ensure_pairs(mk_graph* g, int v, hipStream_t stream);
 
 // Buffers of one level-synchronous BFS (mk_levels.hip): a 256-byte counter block, two
 // frontier queues of N entries and two work-item arrays of levels_multi_cap(g) entries.

@@ -187,29 +187,11 @@ __global__ void k_mlp_adam(float* __restrict__ params, const float* __restrict__
 
 inline bool aligned4(const void* p) { return ((uintptr_t)p & 3) == 0; }
 
-}  // namespace
+size_t grad_ws_bytes(uint32_t n) { return (size_t)n * (4 * kHid + kOut) * sizeof(float) + 512; }
 
-extern "C" {
-
-size_t mk_mlp_workspace_bytes(uint32_t n) {
-  return (size_t)n * (4 * kHid + kOut) * sizeof(float) + 512;
-}
-
-mk_status mk_mlp_forward(const float* d_params, const float* d_x, uint32_t n, float* d_y,
-                         hipStream_t stream) {
-  if (!d_params || (n && (!d_x || !d_y)) || !aligned4(d_params)) return MK_ERR_INVALID_ARG;
-  if (n == 0) return MK_OK;
-  hipLaunchKernelGGL(k_mlp_forward, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, stream, d_params,
-                     d_x, n, d_y);
-  return hipGetLastError() == hipSuccess ? MK_OK : MK_ERR_HIP;
-}
-
-mk_status mk_mlp_grad(const float* d_params, const float* d_x, const float* d_t, const float* d_mask,
-                      uint32_t n, float* d_grad, void* d_ws, size_t ws_bytes, double* d_loss,
-                      hipStream_t stream) {
-  if (!d_params || !d_grad || !d_loss || n == 0 || !d_x || !d_t || !d_mask || !d_ws)
-    return MK_ERR_INVALID_ARG;
-  if (ws_bytes < mk_mlp_workspace_bytes(n)) return MK_ERR_CAPACITY;
+// The gradient's kernels with the workspace at d_ws (at least grad_ws_bytes(n) bytes).
+mk_status grad_launch(const float* d_params, const float* d_x, const float* d_t, const float* d_mask,
+                      uint32_t n, float* d_grad, void* d_ws, double* d_loss, hipStream_t stream) {
   float* ws = reinterpret_cast<float*>(((uintptr_t)d_ws + 255) & ~uintptr_t(255));
   float* H1 = ws;
   float* H2 = H1 + (size_t)n * kHid;
@@ -226,6 +208,36 @@ mk_status mk_mlp_grad(const float* d_params, const float* d_x, const float* d_t,
   hipLaunchKernelGGL(k_mlp_loss_mean, dim3(1), dim3(64), 0, stream, cnt, d_loss);
   return hipGetLastError() == hipSuccess ? MK_OK : MK_ERR_HIP;
 }
+
+}  // namespace
+
+namespace mk {
+void mlp_forward_launch(const float* params, const float* x, uint32_t n, float* y, hipStream_t stream) {
+  hipLaunchKernelGGL(k_mlp_forward, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, stream, params, x, n, y);
+}
+}  // namespace mk
+
+extern "C" {
+
+size_t mk_mlp_workspace_bytes(uint32_t n) { return grad_ws_bytes(n); }
+
+mk_status mk_mlp_forward(const float* d_params, const float* d_x, uint32_t n, float* d_y,
+                         hipStream_t stream) {
+  if (!d_params || (n && (!d_x || !d_y)) || !aligned4(d_params)) return MK_ERR_INVALID_ARG;
+  if (n == 0) return MK_OK;
+  mlp_forward_launch(d_params, d_x, n, d_y, stream);
+  return hipGetLastError() == hipSuccess ? MK_OK : MK_ERR_HIP;
+}
+
+mk_status mk_mlp_grad(const float* d_params, const float* d_x, const float* d_t, const float* d_mask,
+                      uint32_t n, float* d_grad, void* d_ws, size_t ws_bytes, double* d_loss,
+                      hipStream_t stream) {
+  if (!d_params || !d_grad || !d_loss || n == 0 || !d_x || !d_t || !d_mask || !d_ws)
+    return MK_ERR_INVALID_ARG;
+  if (ws_bytes < grad_ws_bytes(n)) return MK_ERR_CAPACITY;
+  return grad_launch(d_params, d_x, d_t, d_mask, n, d_grad, d_ws, d_loss, stream);
+}
+
 
 mk_status mk_mlp_adam(float* d_params, const float* d_grad, float* d_m, float* d_v, uint32_t n_params,
                       float lr, float beta1, float beta2, float eps, uint32_t step, hipStream_t stream) {

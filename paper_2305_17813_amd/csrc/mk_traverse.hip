@@ -795,8 +795,12 @@ mk_status traverse(mk_graph* g, AlgoState& st, uint64_t* D, uint32_t source, uin
   const TravCtx c = graph_ctx(g, D);
   Pending p = pending_for(g, st);
   const bool can_dec = g->view[VR].on;
-  const bool full = mode == MK_RECOMPUTE || !st.valid || st.source != source || p.lost ||
-                    p.kinds == 3 || (p.kinds == 2 && !can_dec);
+  bool full = mode == MK_RECOMPUTE || !st.valid || st.source != source || p.lost ||
+              p.kinds == 3 || (p.kinds == 2 && !can_dec);
+  if (!full && mode == MK_AUTO) {  // the cost model, when one is set, may prefer a recompute
+    mk_status s = auto_prefers_recompute(g, kUnit ? MK_ALGO_BFS : MK_ALGO_SSSP, p, stream, &full);
+    if (s != MK_OK) return s;
+  }
   if (full) {
     // A graph with the reverse view and a mean out-degree of at least 8: distances first
     // (direction-optimizing BFS levels, or the distance-only SSSP), then every vertex's

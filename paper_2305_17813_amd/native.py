@@ -22,6 +22,8 @@ VIEW_FWD, VIEW_REV, VIEW_UND = 1, 2, 4
 AUTO, INCR, RECOMPUTE = 0, 1, 2
 # incremental-WCC schemes (mk_wcc_scheme)
 WCC_LOG, WCC_NAIVE, WCC_SLAB, WCC_UPDATE = 0, 1, 2, 3
+# iteration schemes of all-vertex walks (mk_iter_scheme)
+ITER_SCHEME1, ITER_SCHEME2 = 1, 2
 STATUS_NAMES = {0: "MK_OK", 1: "MK_ERR_INVALID_ARG", 2: "MK_ERR_OUT_OF_SLABS", 3: "MK_ERR_CAPACITY",
                 4: "MK_ERR_STATE", 5: "MK_ERR_HIP"}
 
@@ -97,6 +99,8 @@ def load():
         "mk_bfs_levels": [vp, u32, u32, vp, ctypes.c_size_t, u32, vp, ctypes.POINTER(u32), vp],
         "mk_sssp_distances": [vp, u32, vp, ctypes.c_size_t, u32, vp, vp],
         "mk_mlp_grad": [vp, vp, vp, vp, u32, vp, vp, ctypes.c_size_t, vp, vp],
+        "mk_set_iteration_scheme": [vp, i32],
+        "mk_set_cost_model": [vp, vp],
         "mk_mlp_adam": [vp, vp, vp, vp, u32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                         ctypes.c_float, u32, vp],
     }
@@ -290,6 +294,20 @@ class Graph:
             _check(self.lib.mk_incr_wcc_scheme(self.h, _ptr(lab), mode, int(scheme), self._s(stream)),
                    "mk_incr_wcc_scheme")
         return lab
+
+    def set_cost_model(self, params: Optional[torch.Tensor]):
+        """MLP parameters (MK_MLP_PARAMS float32 on this device) that MK_AUTO consults to pick
+        incremental or recompute; None clears.  The tensor is kept alive here."""
+        if params is not None:
+            params = params.to(self.device, torch.float32).contiguous()
+            assert params.numel() == 5187
+        _check(self.lib.mk_set_cost_model(self.h, _ptr(params)), "mk_set_cost_model")
+        self._cm_params = params
+
+    def set_iteration_scheme(self, scheme: int):
+        """ITER_SCHEME1 (a worker per vertex) or ITER_SCHEME2 (a group per bucket chain) for
+        the PageRank pull and the all-arc WCC walk."""
+        _check(self.lib.mk_set_iteration_scheme(self.h, int(scheme)), "mk_set_iteration_scheme")
 
     def pagerank(self, damping: float = 0.85, tol: float = 5e-8, max_iter: int = 500,
                  mode: int = AUTO, stream=None):

@@ -45,6 +45,8 @@ def test_null_arguments_rejected_without_gpu(lib_path):
     assert lib.mk_graph_destroy(None) == 0
     assert lib.mk_insert_edges(None, None, None, None, 1, None, None) == 1
     assert lib.mk_query_edges(None, None, None, 1, None, None, None) == 1
+    assert lib.mk_set_iteration_scheme(None, 2) == 1
+    assert lib.mk_set_cost_model(None, None) == 1
     cfg = native.MkConfig(0, 1, 0.7, 1, 0, 0)
     h = ctypes.c_void_p()
     assert lib.mk_graph_create(ctypes.byref(cfg), None, 0, None, None, None, 0, None, ctypes.byref(h)) == 1

@@ -614,3 +614,65 @@ def test_distance_only_entry_points_reject_bad_arguments():
     di = G.sssp_distances(0, ws=ws)
     torch.cuda.synchronize()
     assert int(lv[0].item()) == 0 and int(di[0].item()) == 0
+
+
+@pytest.mark.parametrize("lf", [0.7, 0.0])
+def test_iteration_scheme2_agrees_with_the_oracle(lf):
+    """IterationScheme2 (a 16-lane group per <vertex, bucket> chain, grid-stride over the pair
+    list) for the PageRank pull and the static WCC: labels exact and PageRank within 1e-6 in
+    L1, from scratch and warm after insert and delete batches, with hashing on and off (one
+    bucket per vertex); switching back to IterationScheme1 gives the same results."""
+    say(f"case: IterationScheme2, load factor {lf}")
+    g = I.rmat_s(12)
+    p = make_pair(g, source=I.max_out_degree_vertex(g), load_factor=lf)
+    p.g.set_iteration_scheme(native.ITER_SCHEME2)
+    p.check_wcc(native.RECOMPUTE)
+    p.check_pr(native.RECOMPUTE)
+    wl = I.Workload(g, 77)
+    p.insert(*wl.insert_batch(2000))
+    p.check_pr()
+    p.check_wcc(native.RECOMPUTE)
+    p.delete(*wl.delete_batch(2000))
+    p.check_pr()
+    p.check_wcc()  # a delete forces the recompute, here through scheme 2
+    lab2 = p.g.wcc(native.RECOMPUTE)
+    p.g.set_iteration_scheme(native.ITER_SCHEME1)
+    assert torch.equal(p.g.wcc(native.RECOMPUTE), lab2)
+    p.check_pr(native.RECOMPUTE)
+    with pytest.raises(native.MkError):
+        p.g.set_iteration_scheme(3)
+
+
+def test_cost_model_on_the_graph_decides_auto_mode():
+    """mk_set_cost_model: with parameters whose network always predicts a recompute faster
+    (all weights zero, output biases log-incremental 1 > log-recompute 0), MK_AUTO recomputes
+    (PageRank starts cold: as many iterations as an explicit recompute); with the biases
+    swapped it applies the batch incrementally (a warm start, far fewer iterations).  Every
+    result still equals the oracle's."""
+    say("case: cost model set on the graph")
+    g = I.rmat_s(12)
+    p = make_pair(g, source=I.max_out_degree_vertex(g))
+    p.check_all()
+    wl = I.Workload(g, 91)
+    prefer_rec = torch.zeros(5187)
+    prefer_rec[5184:5187] = torch.tensor([1.0, 0.0, 0.0])
+    prefer_inc = torch.zeros(5187)
+    prefer_inc[5184:5187] = torch.tensor([0.0, 1.0, 0.0])
+    iters = {}
+    for name, params in (("recompute", prefer_rec), ("incremental", prefer_inc)):
+        p.g.set_cost_model(params)
+        p.insert(*wl.insert_batch(300))
+        _, it = p.g.pagerank()
+        iters[name] = int(it.item())
+        p.check_pr()
+        p.check_all(algos=("bfs", "sssp", "wcc", "tc"))
+        p.delete(*wl.delete_batch(300))
+        p.check_all()
+    _, it_cold = p.g.pagerank(mode=native.RECOMPUTE)
+    it_cold = int(it_cold.item())
+    say(f"  PageRank iterations: chosen recompute {iters['recompute']}, chosen incremental "
+        f"{iters['incremental']}, explicit recompute {it_cold}")
+    assert abs(iters["recompute"] - it_cold) <= 1
+    assert iters["incremental"] < it_cold - 2
+    p.g.set_cost_model(None)
+    assert p.g.lib.mk_set_cost_model(p.g.h, ctypes.c_void_p(2)) == 1  # misaligned: refused
