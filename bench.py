@@ -91,6 +91,12 @@ def parse():
     ap.add_argument("--schemes", action="store_true",
                     help="iteration-scheme comparison (IterationScheme1 vs IterationScheme2) for the "
                          "static WCC and PageRank at R-MAT scale 22, hashing on and off")
+    ap.add_argument("--costmodel", action="store_true",
+                    help="generate cost-model records on R-MAT scale 22 and the 4096^2 grid (batch sizes "
+                         "log-uniform in [100, 4M]), train the MLP on the GPU and report held-out regret")
+    ap.add_argument("--cm-seconds", type=float, default=120.0, help="record generation time per graph")
+    ap.add_argument("--cm-epochs", type=int, default=200)
+    ap.add_argument("--cm-out", default="", help="npz file for the records and the trained parameters")
     ap.add_argument("--serve-requests", type=int, default=600)
     ap.add_argument("--serve-rate", type=float, default=150.0, help="requests per second")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -122,6 +128,8 @@ def main():
         return wcc_scheme_bench(args)
     if args.schemes:
         return iteration_scheme_bench(args)
+    if args.costmodel:
+        return costmodel_bench(args)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if args.calibrate_copy:
@@ -464,6 +472,70 @@ def ablation_bench(args):
     print(json.dumps({"metric": "hashing / load-factor ablation", "unit": "ms",
                       "config": {"workload": f"R-MAT scale {args.scale}, fwd + rev views, batches of {B}"},
                       "rows": rows}))
+
+
+def costmodel_bench(args):
+    """Cost-model records at the configured scale: batches with sizes log-uniform in
+    [100, 4M] and delete fractions uniform in [0, 1] applied to the R-MAT scale-22 graph (all
+    five algorithms) and to the 4096 x 4096 road-like grid (BFS, SSSP, WCC), each part timed
+    incrementally and against a recompute on the same state (the recompute re-measured every
+    few parts).  Record generation stops at a time budget per graph.  The MLP is trained by the
+    HIP kernels on the older graph states and judged on the newest 20 %: total time of its
+    choices against always-incremental and against the best choice, per algorithm."""
+    import numpy as np
+    import torch
+
+    from paper_2305_17813_amd import costmodel as CM
+    from paper_2305_17813_amd import inputs as I
+    from paper_2305_17813_amd import native
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    rec = CM.Records()
+    plan = [("R-MAT scale 22", lambda: I.rmat_graph(22, 16, args.seed, device=dev), 7, CM.ALGOS, 25),
+            ("grid 4096x4096", lambda: I.grid_graph(4096, 0x4D45524B + 2, device=dev),
+             native.VIEW_FWD | native.VIEW_REV, ["bfs", "sssp", "wcc"], 10)]
+    gen = {}
+    for k, (name, make, views, algos, every) in enumerate(plan):
+        g = make()
+        src = I.max_out_degree_vertex(g) if k == 0 else 0
+        G = native.Graph(g.n, g.src, g.dst, g.w, views=views, load_factor=0.7, log_capacity=1 << 23,
+                         device=dev)
+        wl = I.Workload(g, args.seed + 90 + k)
+        t0 = time.time()
+        n0 = len(rec.X)
+        b = 0
+        while time.time() - t0 < args.cm_seconds:
+            CM.generate_records(G, wl, src, 1, 100, 4_000_000, seed=args.seed + 1000 * k + b, rec=rec,
+                                state_base=100_000 * k + b, algos=algos, recompute_every=every)
+            b += 1
+            if b % 20 == 0:
+                log(f"[costmodel] {name}: {b} batches, {len(rec.X) - n0} records, {time.time() - t0:.0f}s")
+        gen[name] = {"batches": b, "records": len(rec.X) - n0, "seconds": time.time() - t0}
+        del G, g, wl
+        torch.cuda.empty_cache()
+    # interleave the graphs' states so both appear on each side of the split
+    rec.state = [st % 100_000 for st in rec.state]
+    t0 = time.time()
+    cm, hist, r = CM.fit(rec, epochs=args.cm_epochs)
+    X, T, M, ti, tr, algo, state = rec.arrays()
+    cut = np.quantile(state, 0.8)
+    per_algo = {}
+    for a, name in enumerate(CM.ALGOS):
+        sel = (state >= cut) & (algo == a)
+        if sel.any():
+            per_algo[name] = CM.regret(ti[sel], tr[sel], cm.choose(X[sel]))
+    out = {"metric": "cost-model regret on held-out graph states", "unit": "ms", "higher_is_better": False,
+           "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": "batches of size log-uniform in [100, 4M], delete fraction U[0,1], on "
+                                  "R-MAT scale 22 (all five algorithms) and the 4096^2 grid (BFS, SSSP, WCC); "
+                                  "MLP 12-64-64-3 trained by the HIP kernels on the older 80 % of graph states"},
+           "generation": gen, "records": len(rec.X), "train_seconds": time.time() - t0,
+           "loss_first_last": [hist[0], hist[-1]], "held_out": r, "held_out_by_algo": per_algo}
+    if args.cm_out:
+        np.savez(args.cm_out, X=X, T=T, M=M, t_incr=ti, t_rec=tr, algo=algo, state=state,
+                 params=cm.mlp.params.cpu().numpy())
+    print(json.dumps(out))
 
 
 def iteration_scheme_bench(args):

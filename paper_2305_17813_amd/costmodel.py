@@ -157,39 +157,65 @@ def run_algo(G, algo: str, mode: int, source: int):
 
 def generate_records(G, wl, source: int, n_batches: int, bmin: int, bmax: int, seed: int,
                      rec: Optional[Records] = None, state_base: int = 0, algos=ALGOS,
-                     slab_scale: float = float("nan")) -> Records:
-    """Apply `n_batches` seeded mixed batches to G (and its workload `wl`) and record, per
-    algorithm, the features, the incremental time and the recompute time."""
+                     slab_scale: float = float("nan"), recompute_every: int = 1,
+                     max_part: Optional[int] = None) -> Records:
+    """Apply `n_batches` seeded mixed batches to G (and its workload `wl`): a size log-uniform
+    in [bmin, bmax] and a delete fraction uniform in [0, 1] split each batch into an insert
+    part and a delete part, applied in turn.  After each part, per algorithm, one record: the
+    features of the part as MK_AUTO computes them (the part applied and pending for the
+    algorithm), the time of the incremental update, and the time of a recompute on the same
+    graph state.  The recompute time depends on the graph, not on the part, so it is measured
+    every `recompute_every` parts per algorithm and reused in between.  A part larger than
+    `max_part` is applied in slices of at most that size (one pending batch each).  An insert
+    the slab pool refuses is retried once after compaction."""
     rec = rec or Records()
     rng = np.random.default_rng(seed)
     stream = G.stream
     for a in algos:  # every algorithm starts from a valid state
         run_algo(G, a, native.RECOMPUTE, source)
+    t_rec_last = {}
+    n_parts = 0
+
+    def apply(kind, arrays):
+        if kind == "insert":
+            try:
+                G.insert_edges(*arrays, status=False)
+            except native.MkError as e:
+                if e.status != 2:
+                    raise
+                G.compact()
+                G.insert_edges(*arrays, status=False)
+        else:
+            G.delete_edges(*arrays, status=False)
+
     for b in range(n_batches):
         size = int(round(math.exp(rng.uniform(math.log(bmin), math.log(bmax)))))
         fdel = float(rng.uniform(0.0, 1.0))
         n_del = int(round(size * fdel))
         n_ins = size - n_del
-        ins = wl.insert_batch(n_ins) if n_ins else None
-        dels = wl.delete_batch(n_del) if n_del else None
-        feats = {a: G.batch_features(ALGOS.index(a), ins, dels) for a in algos}
-        t_inc = {a: 0.0 for a in algos}
-        if ins is not None:
-            G.insert_edges(*ins, status=False)
+        parts = []
+        if n_ins:
+            parts.append(("insert", wl.insert_batch(n_ins)))
+        if n_del:
+            parts.append(("delete", wl.delete_batch(n_del)))
+        for kind, arrays in parts:
+            k = arrays[0].numel()
+            step = max_part or k
+            for lo in range(0, k, step):
+                apply(kind, tuple(x[lo:lo + step] for x in arrays))
+            feats = {a: G.batch_features(ALGOS.index(a), arrays if kind == "insert" else None,
+                                         arrays if kind == "delete" else None) for a in algos}
             for a in algos:
-                t_inc[a] += _time_call(lambda: run_algo(G, a, native.INCR, source), stream)
-        if dels is not None:
-            G.delete_edges(*dels, status=False)
-            for a in algos:
-                t_inc[a] += _time_call(lambda: run_algo(G, a, native.INCR, source), stream)
-        for a in algos:
-            t_r = _time_call(lambda: run_algo(G, a, native.RECOMPUTE, source), stream)
-            rec.X.append(feats[a])
-            rec.t_incr.append(max(t_inc[a], 1e-3))
-            rec.t_rec.append(max(t_r, 1e-3))
-            rec.algo.append(ALGOS.index(a))
-            rec.state.append(state_base + b)
-            rec.slab_scale.append(slab_scale)
+                t_i = _time_call(lambda: run_algo(G, a, native.INCR, source), stream)
+                if a not in t_rec_last or n_parts % recompute_every == 0:
+                    t_rec_last[a] = _time_call(lambda: run_algo(G, a, native.RECOMPUTE, source), stream)
+                rec.X.append(feats[a])
+                rec.t_incr.append(max(t_i, 1e-3))
+                rec.t_rec.append(max(t_rec_last[a], 1e-3))
+                rec.algo.append(ALGOS.index(a))
+                rec.state.append(state_base + b)
+                rec.slab_scale.append(slab_scale)
+            n_parts += 1
     return rec
 
 
