@@ -366,6 +366,21 @@ mk_status mk_mlp_grad(const float* d_params, const float* d_x, const float* d_t,
                       uint32_t n, float* d_grad, void* d_ws, size_t ws_bytes, double* d_loss,
                       hipStream_t stream);
 
+/* mk_mlp_grad without a workspace argument, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  The
+ * workspace is a file-scope device array of mk_mlp_workspace_bytes(MK_MLP_GRAD_STATIC_MAX)
+ * bytes (about 16 MiB), one copy per GPU, held by each GPU the library runs on until the
+ * process ends; its address is looked up on the first call on a device.  Runs on the
+ * current device (the pointers and the stream must belong to it) and allocates nothing.
+ * Every call on one GPU shares that array and it keeps the last call's contents: calls that
+ * overlap on one GPU (on other streams or from other threads) race and must be ordered by
+ * the caller.
+ *   n : 1 .. MK_MLP_GRAD_STATIC_MAX, else MK_ERR_CAPACITY (nothing launched).
+ * Other arguments, results and determinism as for mk_mlp_grad. */
+#define MK_MLP_GRAD_STATIC_MAX 16384
+mk_status mk_mlp_grad_static(const float* d_params, const float* d_x, const float* d_t, const float* d_mask,
+                             uint32_t n, float* d_grad, double* d_loss, hipStream_t stream);
+
 /* One Adam step (Kingma and Ba, with bias correction; `step` counts from 1) on n_params
  * parameters with first and second moment buffers d_m, d_v (device, FP32). */
 mk_status mk_mlp_adam(float* d_params, const float* d_grad, float* d_m, float* d_v, uint32_t n_params,

@@ -7,6 +7,7 @@
 // without atomics (one thread per weight sums over the minibatch), so a training step is
 // deterministic.  Adam follows Kingma and Ba (ICLR 2015) with bias correction.
 #include <algorithm>
+#include <mutex>
 
 #include "mk_internal.h"
 
@@ -187,7 +188,31 @@ __global__ void k_mlp_adam(float* __restrict__ params, const float* __restrict__
 
 inline bool aligned4(const void* p) { return ((uintptr_t)p & 3) == 0; }
 
-size_t grad_ws_bytes(uint32_t n) { return (size_t)n * (4 * kHid + kOut) * sizeof(float) + 512; }
+constexpr size_t grad_ws_bytes(uint32_t n) { return (size_t)n * (4 * kHid + kOut) * sizeof(float) + 512; }
+
+// Workspace of mk_mlp_grad_static: one copy per GPU, held until the process ends.  In host
+// code `scratch` names a host-side stand-in, never the device array: the device address
+// comes from hipGetSymbolAddress, once per device, and only that address is passed on.
+constexpr size_t kStaticGradBytes = grad_ws_bytes(MK_MLP_GRAD_STATIC_MAX);
+static __device__ __align__(256) unsigned char scratch[kStaticGradBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void* scratch_dev[kMaxDevices] = {};
+
+// Device address of the current device's copy of `scratch` (looked up on its first use).
+mk_status scratch_address(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return MK_ERR_HIP;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_dev[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return MK_ERR_HIP;
+    scratch_dev[dev] = p;
+  }
+  *out = scratch_dev[dev];
+  return MK_OK;
+}
 
 // The gradient's kernels with the workspace at d_ws (at least grad_ws_bytes(n) bytes).
 mk_status grad_launch(const float* d_params, const float* d_x, const float* d_t, const float* d_mask,
@@ -236,6 +261,17 @@ mk_status mk_mlp_grad(const float* d_params, const float* d_x, const float* d_t,
     return MK_ERR_INVALID_ARG;
   if (ws_bytes < grad_ws_bytes(n)) return MK_ERR_CAPACITY;
   return grad_launch(d_params, d_x, d_t, d_mask, n, d_grad, d_ws, d_loss, stream);
+}
+
+mk_status mk_mlp_grad_static(const float* d_params, const float* d_x, const float* d_t, const float* d_mask,
+                             uint32_t n, float* d_grad, double* d_loss, hipStream_t stream) {
+  if (!d_params || !d_grad || !d_loss || n == 0 || !d_x || !d_t || !d_mask) return MK_ERR_INVALID_ARG;
+  if (n > MK_MLP_GRAD_STATIC_MAX) return MK_ERR_CAPACITY;
+  void* ws = nullptr;
+  if (mk_status st = scratch_address(&ws); st != MK_OK) return st;
+  // every word the kernels read back (activations, error terms, the mask count) is written
+  // first in the same call, so the array needs no clearing between calls
+  return grad_launch(d_params, d_x, d_t, d_mask, n, d_grad, ws, d_loss, stream);
 }
 
 

@@ -99,6 +99,7 @@ def load():
         "mk_bfs_levels": [vp, u32, u32, vp, ctypes.c_size_t, u32, vp, ctypes.POINTER(u32), vp],
         "mk_sssp_distances": [vp, u32, vp, ctypes.c_size_t, u32, vp, vp],
         "mk_mlp_grad": [vp, vp, vp, vp, u32, vp, vp, ctypes.c_size_t, vp, vp],
+        "mk_mlp_grad_static": [vp, vp, vp, vp, u32, vp, vp, vp],
         "mk_set_iteration_scheme": [vp, i32],
         "mk_set_cost_model": [vp, vp],
         "mk_mlp_adam": [vp, vp, vp, vp, u32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
