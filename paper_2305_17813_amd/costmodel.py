@@ -36,6 +36,8 @@ N_IN, N_HID, N_OUT, N_PARAMS = 12, 64, 3, 5187
 ALGOS = ["bfs", "sssp", "wcc", "pagerank", "tc"]
 BASE_LOAD_FACTOR = 0.7
 SLAB_SCALES = (0.5, 1.0, 2.0)  # head-slab count multipliers tried by slab_scale_records
+RECOMPUTE_MARGIN = 1.25  # predicted incremental / recompute time ratio a recompute needs
+SCALE_GAIN = 0.9  # a slab scale other than 1 is the label only when it takes < 90 % of the time
 
 
 def load_factor_for(scale: float) -> float:
@@ -225,7 +227,8 @@ def slab_scale_records(graphs, seed: int, rec: Optional[Records] = None, state_b
     the forward and reverse views, at every scale of SLAB_SCALES and timed on the same work:
     one insert batch and one delete batch of m/16 arcs, as many queries, a static BFS and a
     static PageRank from the vertex of largest out-degree.  The record holds the insert
-    batch's features (taken on the default-scale graph) and log2 of the fastest scale."""
+    batch's features (taken on the default-scale graph) and log2 of the fastest scale, or 0
+    (the default) when no scale beats the default by SCALE_GAIN."""
     from . import inputs as I
     rec = rec or Records()
     for k, g in enumerate(graphs):
@@ -253,12 +256,18 @@ def slab_scale_records(graphs, seed: int, rec: Optional[Records] = None, state_b
         rec.t_rec.append(float("nan"))
         rec.algo.append(-1)
         rec.state.append(state_base + k)
-        rec.slab_scale.append(math.log2(SLAB_SCALES[int(np.argmin(ms))]))
+        # the default scale keeps the label unless another is clearly faster (timing noise
+        # alone must not teach the model to move away from it)
+        best = int(np.argmin(ms))
+        if ms[best] > SCALE_GAIN * ms[SLAB_SCALES.index(1.0)]:
+            best = SLAB_SCALES.index(1.0)
+        rec.slab_scale.append(math.log2(SLAB_SCALES[best]))
     return rec
 
 
 class CostModel:
-    """Trained MLP + the decision rule (incremental iff predicted incremental < recompute)."""
+    """Trained MLP + the decision rule (recompute iff predicted incremental time exceeds the
+    predicted recompute time by RECOMPUTE_MARGIN; near ties keep the incremental path)."""
 
     def __init__(self, mlp: MLP):
         self.mlp = mlp
@@ -267,9 +276,10 @@ class CostModel:
         return self.mlp.forward(torch.as_tensor(np.atleast_2d(X))).cpu().numpy()
 
     def choose(self, X: np.ndarray) -> np.ndarray:
-        """MK_INCR (1) or MK_RECOMPUTE (2) per feature row."""
+        """MK_INCR (1) or MK_RECOMPUTE (2) per feature row: a recompute only when it is
+        predicted at least RECOMPUTE_MARGIN faster (the rule MK_AUTO applies in the library)."""
         y = self.predict(X)
-        return np.where(y[:, 0] <= y[:, 1], native.INCR, native.RECOMPUTE)
+        return np.where(y[:, 1] < y[:, 0] - math.log(RECOMPUTE_MARGIN), native.RECOMPUTE, native.INCR)
 
     def mode_for(self, G, algo: str, ins=None, dels=None) -> int:
         return int(self.choose(G.batch_features(ALGOS.index(algo), ins, dels)[None, :])[0])

@@ -150,6 +150,9 @@ mk_status batch_features(mk_graph* g, int algo, const FeatPart* parts, int n_par
   return MK_OK;
 }
 
+// log(1.25): the predicted gain a recompute needs before MK_AUTO takes it.
+constexpr float kRecomputeMargin = 0.22314355f;
+
 mk_status auto_prefers_recompute(mk_graph* g, int algo, const Pending& p, hipStream_t stream, bool* out) {
   *out = false;
   if (!g->cm_params || p.list.empty()) return MK_OK;
@@ -168,7 +171,9 @@ mk_status auto_prefers_recompute(mk_graph* g, int algo, const Pending& p, hipStr
   MK_LAUNCH(g, "cost model forward");
   MK_HIP(g, hipMemcpyAsync(hy, g->ctr->mlp_y, MK_MLP_OUT * sizeof(float), hipMemcpyDeviceToHost, stream));
   MK_HIP(g, hipStreamSynchronize(stream));
-  *out = hy[1] < hy[0];  // predicted log ms: recompute below incremental
+  // predicted log ms: a recompute only when it is predicted at least a quarter faster, so
+  // that near ties (where the prediction error decides) keep the incremental path
+  *out = hy[1] < hy[0] - kRecomputeMargin;
   return MK_OK;
 }
 
