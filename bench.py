@@ -559,7 +559,8 @@ def iteration_scheme_bench(args):
                          device=dev)
         stream = G.stream
         rows = {}
-        for name, scheme in (("scheme1", native.ITER_SCHEME1), ("scheme2", native.ITER_SCHEME2)):
+        for name, scheme in (("scheme1", native.ITER_SCHEME1), ("scheme2", native.ITER_SCHEME2),
+                             ("packed", native.ITER_PACKED)):
             G.set_iteration_scheme(scheme)
 
             def timed(fn):

@@ -246,16 +246,21 @@ mk_status mk_incr_wcc_scheme(mk_graph* g, uint32_t* d_label, mk_mode mode, mk_wc
                              hipStream_t stream);
 
 /* How all-vertex walks are scheduled (section 3.4, IterationScheme1 and IterationScheme2).
- * SCHEME1 (the default) gives each vertex to one worker: a lane for a single-bucket vertex,
- * a 16-lane group for up to 16 buckets, work items of a few buckets for larger ones.
+ * SCHEME1 gives each vertex to one worker: a lane for a single-bucket vertex, a 16-lane
+ * group for up to 16 buckets, work items of a few buckets for larger ones.
  * SCHEME2 gives each bucket chain <v, i> to a 16-lane group in a grid-stride loop over the
  * list of all <vertex, bucket> pairs (built once from one exclusive scan of the bucket
  * counts, which never change after creation); a per-vertex pass then adds the buckets'
- * partial results in bucket order.  The scheme applies to the PageRank pull over the
- * reverse view and to the union over every arc of a static (or naive incremental) WCC.
- * Results are the same under either scheme (PageRank within its tolerance).
- * MK_ERR_INVALID_ARG for an unknown scheme. */
-typedef enum { MK_ITER_SCHEME1 = 1, MK_ITER_SCHEME2 = 2 } mk_iter_scheme;
+ * partial results in bucket order.
+ * PACKED (the default; not in the paper) is SCHEME1 for WCC.  For PageRank its first
+ * iteration of a call walks the slabs as SCHEME1 does and also packs every vertex's in-arc
+ * keys into one array (segments at the exclusive scan of the in-degrees, room for every
+ * data word of the reverse view in the arena); the call's later iterations read those 4-byte
+ * keys instead of 128-byte slabs.
+ * The scheme applies to the PageRank pull over the reverse view and to the union over every
+ * arc of a static (or naive incremental) WCC.  Results are the same under every scheme
+ * (PageRank within its tolerance).  MK_ERR_INVALID_ARG for an unknown scheme. */
+typedef enum { MK_ITER_SCHEME1 = 1, MK_ITER_SCHEME2 = 2, MK_ITER_PACKED = 3 } mk_iter_scheme;
 mk_status mk_set_iteration_scheme(mk_graph* g, mk_iter_scheme scheme);
 
 /* PageRank (section 4.1): PR'(v) = (1-d)/N + d * (sum over in-arcs u->v of PR(u)/out(u)

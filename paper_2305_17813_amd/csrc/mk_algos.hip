@@ -369,13 +369,20 @@ __global__ void __launch_bounds__(kBlock) k_pr_sum(const double* part, uint32_t 
 
 // Pull over in-arcs (reverse view): PR'[v] = (1-d)/N + d * (sum C[u] + dangling/N),
 // and the FP64 L1 change sum |PR'[v] - PR[v]|.
+// With `list`, the pull also packs every vertex's in-arc sources, as their ranks in the
+// hot-first order (rank[u]), into list[off[v] .. off[v] + deg[v]) for the packed iterations
+// (k_pr_pull): single-bucket and 2..16-bucket vertices in slab order, heavy vertices in the
+// order their work items reserve room at cur[j] (so their keys' order, and the last bits of
+// their FP64 sums, can vary between runs).
 __global__ void __launch_bounds__(kBlock) k_pr_gather(DView R, const float* __restrict__ c,
                                                       const float* __restrict__ x,
                                                       float* __restrict__ y, uint32_t nv, float damping,
                                                       const double* dang, double* delta,
                                                       const uint32_t* heavy, const uint32_t* nheavy,
                                                       const uint32_t* hcnt, const uint32_t* hoff,
-                                                      double* hacc, const uint32_t* state) {
+                                                      double* hacc, const uint32_t* state,
+                                                      uint32_t* __restrict__ list, const uint32_t* __restrict__ off,
+                                                      uint32_t* cur, const uint32_t* __restrict__ rank) {
   __shared__ double lds[kBlock / 64];
   if (state[0]) return;
   const double base = (1.0 - (double)damping) / nv + (double)damping * (*dang) / nv;
@@ -385,15 +392,22 @@ __global__ void __launch_bounds__(kBlock) k_pr_gather(DView R, const float* __re
   for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
     if (R.nbk[v] != 1) continue;
     double s = 0;
-    if (R.deg[v] != 0) {  // vertices without in-arcs need no slab read
+    const uint32_t dv = R.deg[v];
+    if (dv != 0) {  // vertices without in-arcs need no slab read
       Slab sl;
       uint32_t t = v;
+      uint32_t* out = list ? list + off[v] : nullptr;
+      uint32_t n = 0;
       while (true) {
         load_slab(R, t, sl);
 #pragma unroll
         for (int j = 0; j < kKeysPerSlab; ++j) {
           const uint32_t u = (uint32_t)sl.w[j];
-          if (valid_key(u)) s += (double)c[u];
+          if (valid_key(u)) {
+            s += (double)c[u];
+            if (out && n < dv) out[n] = rank[u];
+            ++n;
+          }
         }
         t = (uint32_t)sl.w[15];
         if (t == kInvalid) break;
@@ -415,6 +429,15 @@ __global__ void __launch_bounds__(kBlock) k_pr_gather(DView R, const float* __re
     const uint64_t x0 = ld_word(slab_ptr(R, v) + gl);
     const uint32_t xb = gbcast((uint32_t)x0, 14);
     double s = 0;
+    uint32_t* out = list ? list + off[v] : nullptr;
+    const uint32_t dv = list ? R.deg[v] : 0u;
+    uint32_t n = 0;  // keys packed so far (the same in every lane of the group)
+    auto pack = [&](bool valid, uint32_t u) {
+      const uint32_t m = gballot(valid);
+      const uint32_t at = n + (uint32_t)__popc(m & ((1u << gl) - 1u));
+      if (valid && at < dv) out[at] = rank[u];
+      n += (uint32_t)__popc(m);
+    };
     for (uint32_t b0 = 0; b0 < nb; b0 += kPrBatch) {
       uint64_t hw[kPrBatch];
 #pragma unroll
@@ -427,6 +450,7 @@ __global__ void __launch_bounds__(kBlock) k_pr_gather(DView R, const float* __re
         const uint32_t u = (uint32_t)hw[j];
         const bool data = gl < (b0 + j == 0 ? kKeysPerSlab - 1 : kKeysPerSlab);
         if (data && valid_key(u)) s += (double)c[u];
+        if (out) pack(data && valid_key(u), u);
       }
 #pragma unroll
       for (uint32_t j = 0; j < kPrBatch; ++j) {  // chained slabs after a full head slab
@@ -436,6 +460,7 @@ __global__ void __launch_bounds__(kBlock) k_pr_gather(DView R, const float* __re
         walk_chain(R, next, ld_word(slab_ptr(R, next) + gl), kKeysPerSlab, [&](uint64_t w, bool data) {
           const uint32_t u = (uint32_t)w;
           if (data && valid_key(u)) s += (double)c[u];
+          if (out) pack(data && valid_key(u), u);
         });
       }
     }
@@ -461,12 +486,154 @@ __global__ void __launch_bounds__(kBlock) k_pr_gather(DView R, const float* __re
       const uint32_t v = heavy[lo];
       const uint32_t b0 = (it - hoff[lo]) * kPrChunk;
       double s = 0;
+      const uint32_t end = list ? off[v] + R.deg[v] : 0u;
       for_each_bucket_range(R, v, b0, b0 + kPrChunk, [&](uint64_t w, bool data) {
         const uint32_t u = (uint32_t)w;
-        if (data && valid_key(u)) s += (double)c[u];
+        const bool valid = data && valid_key(u);
+        if (valid) s += (double)c[u];
+        if (list) {  // room for this slab's keys in v's segment, one reservation per slab
+          const uint32_t m = gballot(valid);
+          uint32_t at = 0;
+          if (glane() == 0 && m) at = atomicAdd(cur + lo, (uint32_t)__popc(m));
+          at = gbcast(at, 0) + (uint32_t)__popc(m & ((1u << glane()) - 1u));
+          if (valid && at < end) list[at] = rank[u];
+        }
       });
       s = gsum(s);
       if (glane() == 0 && s != 0.0) atomicAdd(hacc + lo, s);
+    }
+  }
+  const double s = block_sum(local, lds);
+  if (threadIdx.x == 0) delta[blockIdx.x] = s;
+}
+
+// PageRank pull over the packed in-arc lists (iterations after the packing one): the same
+// sums as k_pr_gather, reading 4 bytes per in-arc instead of whole slabs.  Each lane issues
+// kPullRound list loads, then their contribution gathers, before it adds them (in list
+// order), so that many gathers are in flight.  Single-bucket vertices take a lane,
+// 2..16-bucket ones a 16-lane group, heavy ones work items of kPullItem in-arcs (partial sums
+// into hacc, as in k_pr_gather).
+constexpr uint32_t kPullRound = 16;
+constexpr uint32_t kPullItem = kGroup * kPullRound * 4;
+
+__global__ void k_pull_items(const uint32_t* deg, const uint32_t* heavy, const uint32_t* nheavy,
+                             const uint32_t* off, uint32_t* cnt, uint32_t* cur) {
+  const uint32_t nh = *nheavy;
+  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < nh; j += gridDim.x * blockDim.x) {
+    const uint32_t v = heavy[j];
+    cnt[j] = (deg[v] + kPullItem - 1) / kPullItem;
+    cur[j] = off[v];
+  }
+}
+
+// off[nv] = off[nv - 1] + deg[nv - 1]: the end of the last segment.
+__global__ void k_pull_end(const uint32_t* deg, uint32_t* off, uint32_t nv) {
+  if (threadIdx.x == 0) off[nv] = off[nv - 1] + deg[nv - 1];
+}
+
+// Hot-first order of the sources for the packed iterations: a stable sort by out-degree class
+// (largest first) puts the sources of most in-arcs in a few MB of the contribution vector,
+// which the L2 of each XCD keeps.  Keys 31 - floor(log2(out + 1)), values the vertex ids.
+__global__ void k_pr_class(const uint32_t* __restrict__ outdeg, uint32_t nv, uint32_t* key, uint32_t* idx) {
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
+    key[v] = (uint32_t)__clz(outdeg[v] + 1u);  // 31 - floor(log2(out + 1)), in [0, 31]
+    idx[v] = v;
+  }
+}
+__global__ void k_pr_rank(const uint32_t* __restrict__ perm, uint32_t nv, uint32_t* __restrict__ rank) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += gridDim.x * blockDim.x) rank[perm[i]] = i;
+}
+
+// k_pr_contrib in the hot-first order: cp[i] = PR[perm[i]] / out[perm[i]], and the FP64 sum of
+// the ranks of zero-out-degree vertices.
+__global__ void __launch_bounds__(kBlock) k_pr_contrib_perm(const float* __restrict__ x,
+                                                            const uint32_t* __restrict__ outdeg,
+                                                            const uint32_t* __restrict__ perm,
+                                                            float* __restrict__ cp, uint32_t nv, double* dpart,
+                                                            const uint32_t* state) {
+  __shared__ double lds[kBlock / 64];
+  if (state[0]) return;
+  double local = 0;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += gridDim.x * blockDim.x) {
+    const uint32_t v = perm[i];
+    const uint32_t o = outdeg[v];
+    const float xv = x[v];
+    cp[i] = o ? xv / (float)o : 0.f;
+    if (!o) local += xv;
+  }
+  const double s = block_sum(local, lds);
+  if (threadIdx.x == 0) dpart[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(kBlock) k_pr_pull(const uint32_t* __restrict__ nbk,
+                                                    const uint32_t* __restrict__ deg,
+                                                    const uint32_t* __restrict__ off,
+                                                    const uint32_t* __restrict__ list,
+                                                    const float* __restrict__ c, const float* __restrict__ x,
+                                                    float* __restrict__ y, uint32_t nv, float damping,
+                                                    const double* dang, double* delta, const uint32_t* heavy,
+                                                    const uint32_t* nheavy, const uint32_t* pcnt,
+                                                    const uint32_t* poff, double* hacc, const uint32_t* state) {
+  __shared__ double lds[kBlock / 64];
+  if (state[0]) return;
+  const double base = (1.0 - (double)damping) / nv + (double)damping * (*dang) / nv;
+  double local = 0;
+  // in-arcs [a + first + k * stride, for k < kPullRound) below a + n (n >= 1), summed in
+  // order.  Every load is unconditional (indexes clamped into the segment and the vertex
+  // range, out-of-range terms masked afterwards), so a lane has all its loads in flight.
+  auto round = [&](uint32_t a, uint32_t n, uint32_t first, uint32_t stride, double& s) {
+    uint32_t u[kPullRound];
+#pragma unroll
+    for (uint32_t k = 0; k < kPullRound; ++k) u[k] = list[a + min(first + k * stride, n - 1)];
+    float cv[kPullRound];
+#pragma unroll
+    for (uint32_t k = 0; k < kPullRound; ++k) cv[k] = c[min(u[k], nv - 1)];
+#pragma unroll
+    for (uint32_t k = 0; k < kPullRound; ++k)
+      if (first + k * stride < n && u[k] < nv) s += (double)cv[k];
+  };
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
+    if (nbk[v] != 1) continue;
+    const uint32_t a = off[v], n = deg[v];
+    double s = 0;
+    for (uint32_t j0 = 0; j0 < n; j0 += kPullRound) round(a + j0, n - j0, 0, 1, s);
+    const float nvl = (float)(base + (double)damping * s);
+    y[v] = nvl;
+    local += fabs((double)nvl - (double)x[v]);
+  }
+  const uint32_t g0 = (blockIdx.x * kBlock + threadIdx.x) / kGroup;
+  const uint32_t ng = gridDim.x * kGroupsPerBlock;
+  const uint32_t gl = (uint32_t)glane();
+  for (uint32_t v = g0; v < nv; v += ng) {
+    const uint32_t nb = nbk[v];
+    if (nb == 1 || nb > kHeavyBuckets) continue;
+    const uint32_t a = off[v], n = deg[v];
+    double s = 0;
+    for (uint32_t j0 = 0; j0 < n; j0 += kGroup * kPullRound) round(a + j0, n - j0, gl, kGroup, s);
+    s = gsum(s);
+    if (gl == 0) {
+      const float nvl = (float)(base + (double)damping * s);
+      y[v] = nvl;
+      local += fabs((double)nvl - (double)x[v]);
+    }
+  }
+  const uint32_t nh = *nheavy;
+  if (nh) {
+    const uint32_t items = poff[nh - 1] + pcnt[nh - 1];
+    for (uint32_t it = g0; it < items; it += ng) {
+      uint32_t lo = 0, hi = nh;  // last j with poff[j] <= it
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (poff[mid] <= it) lo = mid;
+        else hi = mid;
+      }
+      const uint32_t v = heavy[lo];
+      const uint32_t j0 = (it - poff[lo]) * kPullItem;
+      const uint32_t n = min(deg[v] - j0, kPullItem);
+      double s = 0;
+      for (uint32_t j = 0; j < n; j += kGroup * kPullRound) round(off[v] + j0 + j, n - j, gl, kGroup, s);
+      s = gsum(s);
+      if (gl == 0 && s != 0.0) atomicAdd(hacc + lo, s);
     }
   }
   const double s = block_sum(local, lds);
@@ -675,16 +842,32 @@ __global__ void k_tc_segs(const uint64_t* keys, uint64_t nk, uint32_t nv, uint32
   }
 }
 
+// Which end of a canonical batch edge {u, v} (u < v) is walked for S1: the end of smaller
+// live degree (ties: u).  The other end, b, is the one whose neighbourhood is looked up.
+__device__ inline bool tc_walk_u(const DView& U, uint32_t u, uint32_t v) { return U.deg[u] <= U.deg[v]; }
+// The walked end of the batch edge {x, y}, in either order.
+__device__ inline uint32_t tc_walked(const DView& U, uint32_t x, uint32_t y) {
+  const uint32_t u = min(x, y), v = max(x, y);
+  return tc_walk_u(U, u, v) ? u : v;
+}
+
+// A batch edge whose looked-up end b has more than kTcHubDeg neighbours and at least
+// kTcHubEdges batch edges is a hub edge: its S1 term is counted by k_tc_hub, which loads b's
+// neighbourhood into an LDS hash set once for all of them (a hub with fewer batch edges costs
+// less by probing).  Every other term is counted by k_tc_batch, one group per batch arc.
+constexpr uint32_t kTcHubDeg = 1024;
+constexpr uint32_t kTcHubEdges = 8;
+__device__ inline bool tc_is_hub(const DView& U, uint32_t b, uint32_t batch_deg) {
+  return U.deg[b] > kTcHubDeg && batch_deg >= kTcHubEdges;
+}
+
 // S1, S2 and S3 of the batch identity, one group per batch arc (u, v):
 //   S1 += |N_G(u) & N_G(v)|, S2 += |N_G(u) & N_B(v)|, S3 += |N_B(u) & N_B(v)|
-// with G the graph after the batch and B the graph of the batch alone.
+// with G the graph after the batch and B the graph of the batch alone (S1 and S3 on the
+// canonical direction u < v, counted twice).  S1 of hub edges is left to k_tc_hub.
 __global__ void __launch_bounds__(kBlock) k_tc_batch(DView U, const uint64_t* keys, uint64_t nk,
                                                      const uint32_t* seg_lo, const uint32_t* seg_hi,
-                                                     uint32_t nv, unsigned long long* S,
-                                                     uint32_t* heavy, uint32_t* nheavy) {
-  __shared__ Stage H[1];  // batch arcs left to k_tc_heavy_s1
-  stage_open(H[0], heavy, nheavy);
-  __syncthreads();
+                                                     uint32_t nv, unsigned long long* S) {
   const uint64_t g0 = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kGroup;
   const uint64_t ng = (uint64_t)gridDim.x * kGroupsPerBlock;
   uint64_t s1 = 0, s2 = 0, s3 = 0;
@@ -693,18 +876,11 @@ __global__ void __launch_bounds__(kBlock) k_tc_batch(DView U, const uint64_t* ke
     const uint64_t key = keys[i];
     const uint32_t u = (uint32_t)(key >> 32), v = (uint32_t)key;
     if (u >= nv) break;  // sentinels sort last
-    // S1 and S3 are symmetric in (u, v): count them once, on the canonical direction
     const bool canon = u < v;
+    const uint32_t a = tc_walked(U, u, v), b = a == u ? v : u;
+    const bool hub = tc_is_hub(U, b, seg_hi[b] - seg_lo[b]);
     uint64_t c1 = 0;
-    bool split = false;
-    if (canon) {
-      const bool u_small = U.deg[u] <= U.deg[v];  // walk the smaller side, probe the other
-      const uint32_t a = u_small ? u : v;
-      // a large smaller side (two hubs) is counted by k_tc_heavy_s1 over many groups
-      split = U.nbk[a] > kHeavyBuckets;
-      if (!split) c1 = 2 * group_intersect(U, a, u_small ? v : u);
-    }
-    stage_push(H[0], split && gl == 0, (uint32_t)i);
+    if (canon && !hub) c1 = 2 * group_intersect(U, a, b);  // walk the smaller side, probe the other
     // batch neighbourhoods: the segments of v and u in the sorted key list
     const uint64_t vlo = seg_lo[v], vhi = seg_hi[v];
     const uint64_t ulo = seg_lo[u], uhi = seg_hi[u];
@@ -733,33 +909,225 @@ __global__ void __launch_bounds__(kBlock) k_tc_batch(DView U, const uint64_t* ke
     if (s2) atomicAdd(S + 1, (unsigned long long)s2);
     if (s3) atomicAdd(S + 2, (unsigned long long)s3);
   }
-  stage_close(H);
 }
 
-// S1 of the batch arcs whose smaller side has many buckets: kTcSplit groups per arc, each
-// walking every kTcSplit-th bucket of the smaller neighbourhood.
-constexpr uint32_t kTcSplit = 64;
-__global__ void __launch_bounds__(kBlock) k_tc_heavy_s1(DView U, const uint64_t* keys, const uint32_t* heavy,
-                                                        const uint32_t* nheavy, unsigned long long* S) {
-  const uint32_t nh = *nheavy;
-  const uint64_t g0 = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kGroup;
-  const uint64_t ng = (uint64_t)gridDim.x * kGroupsPerBlock;
-  uint64_t acc = 0;
-  for (uint64_t it = g0; it < (uint64_t)nh * kTcSplit; it += ng) {
-    const uint64_t key = keys[heavy[it / kTcSplit]];
-    const uint32_t u = (uint32_t)(key >> 32), v = (uint32_t)key;
-    const bool u_small = U.deg[u] <= U.deg[v];
-    const uint32_t a = u_small ? u : v, b = u_small ? v : u;
-    const Table tb = group_table(U, b);
-    uint64_t c = 0;
-    for_each_slab_strided(U, a, (uint32_t)(it % kTcSplit), kTcSplit, [&](uint64_t x, bool data) {
-      const uint32_t k = (uint32_t)x;
-      if (data && valid_key(k) && k != b) c += lane_has(U, tb, k);
-    });
-    c = gsum_u64(c);
-    if (glane() == 0) acc += 2 * c;
+// ---------------------------------------------------------------- hub edges through LDS sets
+// A hub b (tc_is_hub, with its segment in the sorted batch keys) owns the batch edges {a, b}
+// whose walked end is a.  Its work is split into items <b, pass p, chunk c>: pass p keeps the
+// keys of N(b) whose partition hash is p (P_b passes, so that one pass fits the LDS set),
+// chunk c is a run of kTcHubChunk entries of b's segment.  An item loads its part of N(b) into
+// an LDS hash set, then walks N(a) of every partner a in its chunk (one bucket chain per lane,
+// spread over the whole block) and looks each key of the pass up.
+//
+// The set is bucketized: 4 slots (16 bytes, one LDS read) per bucket, linear probing over
+// buckets.  At the set's load factor a lookup mostly reads one bucket, so the lanes of a wave
+// rarely wait for each other's probe chains (one slot per probe step cost about twice as
+// much in the measurements).
+constexpr uint32_t kTcHubThreads = 1024;
+constexpr uint32_t kTcHubSlots = 32768;               // 128 KiB of u32 keys
+constexpr uint32_t kTcHubKeys = kTcHubSlots * 5 / 8;  // keys per pass (load factor <= 0.625)
+constexpr uint32_t kTcHubChunk = 128;                 // segment entries per item
+constexpr uint32_t kTcHubBlocks = 512;                // persistent blocks (one LDS set each)
+
+__device__ inline uint32_t tc_part(uint32_t k, uint32_t P) {
+  return (uint32_t)(((uint64_t)(k * 0x85EBCA6Bu) * P) >> 32);
+}
+__device__ inline uint32_t tc_bucket(uint32_t k, uint32_t bmask) { return (k * 0x9E3779B1u) >> 9 & bmask; }
+__device__ inline uint32_t tc_hub_passes(uint32_t deg) { return max(1u, (deg + kTcHubKeys - 1) / kTcHubKeys); }
+
+// Insert `key` into the bucketized LDS set of bmask + 1 buckets; false when the set is full.
+__device__ inline bool lds_insert(uint32_t* tab, uint32_t bmask, uint32_t key) {
+  uint32_t h = tc_bucket(key, bmask);
+  for (uint32_t n = 0; n <= bmask; ++n) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t old = atomicCAS(&tab[4 * h + i], kInvalid, key);
+      if (old == kInvalid || old == key) return true;
+    }
+    h = (h + 1) & bmask;
   }
-  if (glane() == 0 && acc) atomicAdd(S, (unsigned long long)acc);
+  return false;
+}
+__device__ inline bool lds_has(const uint32_t* tab, uint32_t bmask, uint32_t key) {
+  uint32_t h = tc_bucket(key, bmask);
+  for (uint32_t n = 0; n <= bmask; ++n) {
+    const uint4 q = reinterpret_cast<const uint4*>(tab)[h];
+    if (q.x == key || q.y == key || q.z == key || q.w == key) return true;
+    if (q.x == kInvalid || q.y == kInvalid || q.z == kInvalid || q.w == kInvalid) return false;
+    h = (h + 1) & bmask;
+  }
+  return false;
+}
+
+// The lookups of one slab's keys in b's slab table, when the pass overflowed its LDS set.
+// Out of line and not unrolled: it is the rare path, and the unrolled fast loop stays small.
+__device__ __attribute__((noinline)) uint64_t tc_slow_lookups(const DView& U, const Table& tb,
+                                                              const uint64_t* slab, int nd, uint32_t p,
+                                                              uint32_t P) {
+  uint64_t hits = 0;
+#pragma unroll 1
+  for (int i = 0; i < nd; ++i) {
+    const uint32_t key = (uint32_t)ld_word(slab + i);
+    if (valid_key(key) && key != tb.u && tc_part(key, P) == p) hits += lane_has(U, tb, key);
+  }
+  return hits;
+}
+
+// Work items per segment start: P_b * ceil(|segment| / kTcHubChunk) at the first key of a hub's
+// segment, 0 elsewhere (an exclusive scan of these numbers the items).
+__global__ void k_tc_hub_count(DView U, const uint64_t* keys, uint64_t nk, const uint32_t* seg_hi,
+                               uint32_t nv, uint32_t* cnt) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nk;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t b = (uint32_t)(keys[i] >> 32);
+    uint32_t c = 0;
+    if (b < nv && (i == 0 || (uint32_t)(keys[i - 1] >> 32) != b) && tc_is_hub(U, b, seg_hi[b] - (uint32_t)i)) {
+      const uint64_t len = seg_hi[b] - i;
+      c = tc_hub_passes(U.deg[b]) * (uint32_t)((len + kTcHubChunk - 1) / kTcHubChunk);
+    }
+    cnt[i] = c;
+  }
+}
+
+// Persistent blocks take items from a counter until none is left.
+__global__ void __launch_bounds__(kTcHubThreads) k_tc_hub(DView U, const uint64_t* keys, uint64_t nk,
+                                                         const uint32_t* seg_hi, const uint32_t* cnt,
+                                                         const uint32_t* off, uint32_t* next,
+                                                         unsigned long long* S) {
+  __shared__ uint4 tab4[kTcHubSlots / 4];
+  uint32_t* tab = reinterpret_cast<uint32_t*>(tab4);
+  __shared__ uint32_t px[kTcHubChunk], pxb[kTcHubChunk], pnb[kTcHubChunk], pre[kTcHubChunk + 1];
+  __shared__ uint32_t item_s[8];
+  __shared__ uint32_t full;  // a key found no free slot: this item looks keys up in b's slabs
+  __shared__ unsigned long long part[kTcHubThreads / 64];
+  const uint32_t total = nk ? off[nk - 1] + cnt[nk - 1] : 0u;
+  uint64_t hits = 0;
+  while (true) {
+    if (threadIdx.x == 0) {
+      const uint32_t t = atomicAdd(next, 1u);
+      item_s[0] = t;
+      if (t < total) {
+        // the segment start of item t: the last key position with off <= t
+        uint64_t lo = 0, hi = nk;
+        while (hi - lo > 1) {
+          const uint64_t mid = (lo + hi) >> 1;
+          if (off[mid] <= t) lo = mid;
+          else hi = mid;
+        }
+        const uint32_t b = (uint32_t)(keys[lo] >> 32);
+        const uint32_t P = tc_hub_passes(U.deg[b]);
+        const uint32_t C = cnt[lo] / P;
+        const uint32_t local = t - off[lo];
+        const uint64_t c0 = lo + (uint64_t)(local % C) * kTcHubChunk;
+        item_s[1] = b;
+        item_s[2] = P;
+        item_s[3] = local / C;
+        item_s[4] = (uint32_t)c0;
+        item_s[5] = (uint32_t)min<uint64_t>(c0 + kTcHubChunk, seg_hi[b]) - (uint32_t)c0;
+      }
+    }
+    __syncthreads();
+    if (item_s[0] >= total) break;  // every thread reads the same value
+    const uint32_t b = item_s[1], P = item_s[2], p = item_s[3], c0 = item_s[4], np = item_s[5];
+    // buckets: a power of two, at least 1.6 slots per key of the pass, within the LDS array
+    const uint32_t want = (U.deg[b] + P - 1) / P;
+    uint32_t slots = 64;
+    while (slots < kTcHubSlots && slots * 5 < want * 8) slots <<= 1;
+    const uint32_t bmask = slots / 4 - 1;
+    for (uint32_t i = threadIdx.x; i < slots; i += kTcHubThreads) tab[i] = kInvalid;
+    if (threadIdx.x == 0) full = 0;
+    // partners of this chunk: a is walked when tc_walked picks it over b
+    for (uint32_t j = threadIdx.x; j < np; j += kTcHubThreads) {
+      const uint32_t a = (uint32_t)keys[c0 + j];
+      const bool mine = tc_walked(U, a, b) == a;
+      uint32_t nb = 0, xb = 0;
+      if (mine && U.deg[a] > 0) {
+        const uint64_t* ps = slab_ptr(U, a);
+        nb = (uint32_t)(ld_word(ps + 15) >> 32);
+        xb = nb > 1 ? (uint32_t)ld_word(ps + 14) : 0u;
+      }
+      px[j] = a;
+      pnb[j] = nb;
+      pxb[j] = xb;
+    }
+    if (threadIdx.x == 64) {  // b's bucket count and first extra head slab
+      const uint64_t* ps = slab_ptr(U, b);
+      const uint32_t nbb0 = (uint32_t)(ld_word(ps + 15) >> 32);
+      item_s[6] = nbb0;
+      item_s[7] = nbb0 > 1 ? (uint32_t)ld_word(ps + 14) : 0u;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {  // bucket chains of the partners before each one
+      uint32_t acc = 0;
+      for (uint32_t j = 0; j < np; ++j) {
+        pre[j] = acc;
+        acc += pnb[j];
+      }
+      pre[np] = acc;
+    }
+    // this pass's keys of N(b), one bucket chain per lane (each lane reads whole slabs, so a
+    // wave keeps 64 slab reads in flight)
+    const uint32_t nbb = item_s[6], xbb = item_s[7];
+    for (uint32_t k = threadIdx.x; k < nbb; k += kTcHubThreads) {
+      uint32_t s = k == 0 ? b : xbb + k - 1;
+      int nd = (k == 0 && nbb > 1) ? kKeysPerSlab - 1 : kKeysPerSlab;
+      while (true) {
+        Slab sl;
+        load_slab(U, s, sl);
+#pragma unroll
+        for (int i = 0; i < kKeysPerSlab; ++i) {
+          const uint32_t key = (uint32_t)sl.w[i];
+          if (i >= nd || !valid_key(key) || tc_part(key, P) != p) continue;
+          if (!lds_insert(tab, bmask, key)) full = 1;
+        }
+        s = (uint32_t)sl.w[15];
+        if (s == kInvalid) break;
+        nd = kKeysPerSlab;
+      }
+    }
+    __syncthreads();
+    const bool in_lds = full == 0;
+    const Table tb{b, nbb, xbb};
+    // the partners' neighbourhoods, one bucket chain per lane, against this pass's keys of N(b)
+    const uint32_t tasks = pre[np];
+    for (uint32_t t = threadIdx.x; t < tasks; t += kTcHubThreads) {
+      uint32_t lo = 0, hi = np;  // the partner j with pre[j] <= t < pre[j + 1]
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (pre[mid] <= t) lo = mid;
+        else hi = mid;
+      }
+      const uint32_t a = px[lo], k = t - pre[lo], nba = pnb[lo];
+      uint32_t s = k == 0 ? a : pxb[lo] + k - 1;
+      int nd = (k == 0 && nba > 1) ? kKeysPerSlab - 1 : kKeysPerSlab;
+      while (true) {
+        Slab sl;
+        load_slab(U, s, sl);
+        if (in_lds) {
+#pragma unroll
+          for (int i = 0; i < kKeysPerSlab; ++i) {
+            const uint32_t key = (uint32_t)sl.w[i];
+            if (i < nd && valid_key(key) && key != b && tc_part(key, P) == p) hits += lds_has(tab, bmask, key);
+          }
+        } else {
+          hits += tc_slow_lookups(U, tb, slab_ptr(U, s), nd, p, P);
+        }
+        s = (uint32_t)sl.w[15];
+        if (s == kInvalid) break;
+        nd = kKeysPerSlab;
+      }
+    }
+    __syncthreads();  // the set and partner arrays are rebuilt by the next item
+  }
+  // every match counts twice (S1 adds both directions of an edge)
+  for (int o = 32; o > 0; o >>= 1) hits += __shfl_xor(hits, o);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = hits;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (uint32_t i = 0; i < kTcHubThreads / 64; ++i) t += part[i];
+    if (t) atomicAdd(S, 2 * t);
+  }
 }
 
 __global__ void k_tc_begin(Counters* C, bool reset_total) {
@@ -946,6 +1314,35 @@ mk_status mk_incr_pagerank(mk_graph* g, float damping, double tol_l1, uint32_t m
                                 stream) != hipSuccess)
       return MK_ERR_HIP;
   }
+  // packed iterations: the first one walks the slabs and packs the in-arc keys at the
+  // exclusive scan of the in-degrees; the heavy vertices' pull items and packing cursors
+  // use three more traversal queues
+  const bool packed = g->iter_scheme == MK_ITER_PACKED && g->pr_list;
+  const DView& Rd = g->view[VR].d;
+  uint32_t* pcnt = g->fq[2];
+  uint32_t* poff = g->fq[3];
+  uint32_t* pcur = g->fq[4];
+  if (packed) {
+    size_t tb = g->scan_tmp_bytes;
+    if (rocprim::exclusive_scan(g->scan_tmp, tb, Rd.deg, g->pr_off, 0u, (size_t)N, rocprim::plus<uint32_t>(),
+                                stream) != hipSuccess)
+      return MK_ERR_HIP;
+    // hot-first ranks of the sources (out-degrees change with every batch: once per call)
+    hipLaunchKernelGGL(k_pr_class, dim3(blocks_for(N)), dim3(kBlock), 0, stream, g->view[VF].d.deg, N,
+                       g->pr_skey[0], g->pr_sidx);
+    size_t sb = g->pr_sort_bytes;
+    if (rocprim::radix_sort_pairs(g->pr_sort_tmp, sb, g->pr_skey[0], g->pr_skey[1], g->pr_sidx, g->pr_perm,
+                                  (size_t)N, 0, 6, stream) != hipSuccess)
+      return MK_ERR_HIP;
+    hipLaunchKernelGGL(k_pr_rank, dim3(blocks_for(N)), dim3(kBlock), 0, stream, g->pr_perm, N, g->pr_rank);
+    hipLaunchKernelGGL(k_pull_end, dim3(1), dim3(64), 0, stream, Rd.deg, g->pr_off, N);
+    hipLaunchKernelGGL(k_pull_items, dim3(blocks_for(N)), dim3(kBlock), 0, stream, Rd.deg, g->heavy_rev, nh,
+                       g->pr_off, pcnt, pcur);
+    size_t tb2 = g->scan_tmp_bytes;
+    if (rocprim::exclusive_scan(g->scan_tmp, tb2, pcnt, poff, 0u, (size_t)N, rocprim::plus<uint32_t>(),
+                                stream) != hipSuccess)
+      return MK_ERR_HIP;
+  }
   hipLaunchKernelGGL(k_pr_start, dim3(1), dim3(64), 0, stream, g->ctr);
   MK_LAUNCH(g, "pagerank setup");
   float* buf[2] = {g->pr_x, g->pr_y};
@@ -960,12 +1357,21 @@ mk_status mk_incr_pagerank(mk_graph* g, float damping, double tol_l1, uint32_t m
       const float* x = buf[it & 1];
       float* y = buf[(it + 1) & 1];
       double* dang = &g->ctr->pr_acc[2 * slot];
-      hipLaunchKernelGGL(k_pr_contrib, dim3(cb), dim3(kBlock), 0, stream, x, g->view[VF].d.deg, g->pr_c,
-                         N, g->pr_part, g->ctr->pr_state);
+      if (packed && it > 0)
+        hipLaunchKernelGGL(k_pr_contrib_perm, dim3(cb), dim3(kBlock), 0, stream, x, g->view[VF].d.deg,
+                           g->pr_perm, g->pr_cp, N, g->pr_part, g->ctr->pr_state);
+      else
+        hipLaunchKernelGGL(k_pr_contrib, dim3(cb), dim3(kBlock), 0, stream, x, g->view[VF].d.deg, g->pr_c,
+                           N, g->pr_part, g->ctr->pr_state);
       hipLaunchKernelGGL(k_pr_sum, dim3(1), dim3(kBlock), 0, stream, g->pr_part, cb, dang, g->ctr->pr_state);
-      hipLaunchKernelGGL(k_pr_gather, dim3(kWalkBlocks), dim3(kBlock), 0, stream, g->view[VR].d,
-                         g->pr_c, x, y, N, damping, dang, dpart, g->heavy_rev, nh, hcnt, hoff, hacc,
-                         g->ctr->pr_state);
+      if (packed && it > 0)
+        hipLaunchKernelGGL(k_pr_pull, dim3(kWalkBlocks), dim3(kBlock), 0, stream, Rd.nbk, Rd.deg, g->pr_off,
+                           g->pr_list, g->pr_cp, x, y, N, damping, dang, dpart, g->heavy_rev, nh, pcnt, poff,
+                           hacc, g->ctr->pr_state);
+      else
+        hipLaunchKernelGGL(k_pr_gather, dim3(kWalkBlocks), dim3(kBlock), 0, stream, Rd, g->pr_c, x, y, N,
+                           damping, dang, dpart, g->heavy_rev, nh, hcnt, hoff, hacc, g->ctr->pr_state,
+                           packed ? g->pr_list : nullptr, g->pr_off, pcur, g->pr_rank);
       hipLaunchKernelGGL(k_pr_heavy_final, dim3(hb), dim3(kBlock), 0, stream, g->heavy_rev, nh, hacc, x, y,
                          N, damping, dang, dpart + kWalkBlocks, g->ctr->pr_state);
       hipLaunchKernelGGL(k_pr_check, dim3(1), dim3(kBlock), 0, stream, g->ctr, slot, tol_l1, max_iter, dpart,
@@ -1022,18 +1428,26 @@ mk_status mk_count_triangles(mk_graph* g, uint64_t* d_count, mk_mode mode, hipSt
                                  end_bit, stream) != hipSuccess)
       return MK_ERR_HIP;
     hipLaunchKernelGGL(k_tc_begin, dim3(1), dim3(64), 0, stream, g->ctr, false);
-    // after the sort, tc_keys[0] is free: it holds the list of split arcs
-    uint32_t* hl = reinterpret_cast<uint32_t*>(g->tc_keys[0]);
-    uint32_t* nhl = &g->ctr->n_split_tc;
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, nhl, 1u);
     // segment bounds per source vertex (scratch: two traversal queues, unused here)
     hipLaunchKernelGGL(k_tc_segs, dim3(blocks_for(nk)), dim3(kBlock), 0, stream, g->tc_keys[1], nk, N,
                        g->fq[4], g->fq[5]);
     hipLaunchKernelGGL(k_tc_batch, dim3(grid_for_groups(std::min<uint64_t>(nk, 1u << 20))),
-                       dim3(kBlock), 0, stream, U, g->tc_keys[1], nk, g->fq[4], g->fq[5], N, g->ctr->tc_s,
-                       hl, nhl);
-    hipLaunchKernelGGL(k_tc_heavy_s1, dim3(kWalkBlocks), dim3(kBlock), 0, stream, U, g->tc_keys[1], hl, nhl,
-                       g->ctr->tc_s);
+                       dim3(kBlock), 0, stream, U, g->tc_keys[1], nk, g->fq[4], g->fq[5], N, g->ctr->tc_s);
+    // hub edges: work items numbered by an exclusive scan over the key
+    // positions, in the sort's input buffer (free after the sort; 2 * nk u32 fit in it)
+    uint32_t* hcnt = reinterpret_cast<uint32_t*>(g->tc_keys[0]);
+    uint32_t* hoff = hcnt + nk;
+    hipLaunchKernelGGL(k_tc_hub_count, dim3(blocks_for(nk)), dim3(kBlock), 0, stream, U, g->tc_keys[1], nk,
+                       g->fq[5], N, hcnt);
+    {
+      size_t tb2 = g->scan_tmp_bytes;
+      if (rocprim::exclusive_scan(g->scan_tmp, tb2, hcnt, hoff, 0u, (size_t)nk, rocprim::plus<uint32_t>(),
+                                  stream) != hipSuccess)
+        return MK_ERR_HIP;
+    }
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, &g->ctr->tc_work, 1u);
+    hipLaunchKernelGGL(k_tc_hub, dim3(kTcHubBlocks), dim3(kTcHubThreads), 0, stream, U, g->tc_keys[1], nk,
+                       g->fq[5], hcnt, hoff, &g->ctr->tc_work, g->ctr->tc_s);
     hipLaunchKernelGGL(k_tc_finish, dim3(1), dim3(64), 0, stream, g->ctr,
                        p.kinds == 1 ? 0 : 1, out);
   }

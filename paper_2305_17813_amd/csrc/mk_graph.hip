@@ -774,6 +774,26 @@ bool layout(const mk_config* c, uint64_t m, char* base, mk_graph* g, size_t* tot
   double* hacc = cv.take<double>(N);
   double* prp = cv.take<double>(kPrParts);
   double* prpair = hb_rev ? cv.take<double>(hb_rev) : nullptr;
+  // packed in-arc lists: one u32 per data word of the reverse view's slabs
+  const uint64_t rev_words = hb_rev ? (hb_rev + pool_default(c, view_arcs(VR, m))) * kKeysPerSlab : 0;
+  uint32_t* prlist = hb_rev ? cv.take<uint32_t>(rev_words) : nullptr;
+  uint32_t* proff = hb_rev ? cv.take<uint32_t>((uint64_t)N + 1) : nullptr;
+  uint32_t *prperm = nullptr, *prrank = nullptr, *prk0 = nullptr, *prk1 = nullptr, *pridx = nullptr;
+  float* prcp = nullptr;
+  void* prsort = nullptr;
+  size_t prsort_bytes = 0;
+  if (hb_rev) {
+    prperm = cv.take<uint32_t>(N);
+    prrank = cv.take<uint32_t>(N);
+    prk0 = cv.take<uint32_t>(N);
+    prk1 = cv.take<uint32_t>(N);
+    pridx = cv.take<uint32_t>(N);
+    prcp = cv.take<float>(N);
+    if (rocprim::radix_sort_pairs(nullptr, prsort_bytes, (uint32_t*)nullptr, (uint32_t*)nullptr,
+                                  (uint32_t*)nullptr, (uint32_t*)nullptr, (size_t)N, 0, 6) != hipSuccess)
+      return false;
+    prsort = cv.take<char>(prsort_bytes + 256);
+  }
   uint64_t* umark = cv.take<uint64_t>(hb_fwd);
   uint32_t* wflag = cv.take<uint32_t>(N);
   char* lvc = cv.take<char>(256);
@@ -791,8 +811,9 @@ bool layout(const mk_config* c, uint64_t m, char* base, mk_graph* g, size_t* tot
       return false;
   }
   void* sort_tmp = cv.take<char>(sort_bytes + 256);
+  // scans over the vertices, and over the sorted batch keys of the triangle update (2 L)
   if (rocprim::exclusive_scan(nullptr, scan_bytes, (uint32_t*)nullptr, (uint32_t*)nullptr, 0u,
-                              (size_t)N, rocprim::plus<uint32_t>()) != hipSuccess)
+                              std::max<size_t>(N, 2 * L), rocprim::plus<uint32_t>()) != hipSuccess)
     return false;
   void* scan_tmp = cv.take<char>(scan_bytes + 256);
   if (g) {
@@ -815,6 +836,16 @@ bool layout(const mk_config* c, uint64_t m, char* base, mk_graph* g, size_t* tot
     g->pr_hacc = hacc;
     g->pr_part = prp;
     g->pr_pair = prpair;
+    g->pr_list = prlist;
+    g->pr_off = proff;
+    g->pr_perm = prperm;
+    g->pr_rank = prrank;
+    g->pr_skey[0] = prk0;
+    g->pr_skey[1] = prk1;
+    g->pr_sidx = pridx;
+    g->pr_cp = prcp;
+    g->pr_sort_tmp = prsort;
+    g->pr_sort_bytes = prsort_bytes;
     g->upd_mark = umark;
     g->wcc_flag = wflag;
     g->lv_cnt = lvc;
@@ -1311,7 +1342,8 @@ mk_status mk_probe_cost(mk_graph* g, int op, int view, const uint32_t* d_src, co
 }
 
 mk_status mk_set_iteration_scheme(mk_graph* g, mk_iter_scheme scheme) {
-  if (!g || (scheme != MK_ITER_SCHEME1 && scheme != MK_ITER_SCHEME2)) return MK_ERR_INVALID_ARG;
+  if (!g || (scheme != MK_ITER_SCHEME1 && scheme != MK_ITER_SCHEME2 && scheme != MK_ITER_PACKED))
+    return MK_ERR_INVALID_ARG;
   g->iter_scheme = scheme;
   return MK_OK;
 }

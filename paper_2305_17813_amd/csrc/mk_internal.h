@@ -63,7 +63,7 @@ struct Counters {          // device-side scalars, one 4 KiB block
   uint32_t n_heavy_wcc;    // vertices of more than 16 buckets, all-arc WCC walk
   uint32_t n_heavy_pr;     // the same for the PageRank pull (reverse view)
   uint32_t n_heavy_tc;     // the same for the static triangle count (undirected view)
-  uint32_t n_split_tc;     // batch arcs whose intersections are split over many groups
+  uint32_t tc_work;        // next hub work item of the triangle batch update
   uint32_t n_listed_light; // vertices listed for an incremental WCC pass: up to 16 buckets,
   uint32_t n_listed_heavy; //   and more (these two are cleared together)
   unsigned long long tc_s[3];  // S1, S2, S3 of the triangle batch identity
@@ -135,7 +135,19 @@ struct mk_graph {
   double* pr_hacc = nullptr;      // FP64 partial sums of the heavy vertices
   double* pr_part = nullptr;      // FP64 per-block partial sums of one iteration (kPrParts)
   double* pr_pair = nullptr;      // FP64 in-arc sum per reverse-view bucket (IterationScheme2)
-  int iter_scheme = MK_ITER_SCHEME1;  // how all-vertex walks are scheduled
+  uint32_t* pr_list = nullptr;    // packed in-arc keys of the reverse view (MK_ITER_PACKED),
+                                  // room for every data word of its slabs
+  uint32_t* pr_off = nullptr;     // N + 1 segment starts in pr_list (scan of the in-degrees)
+  // hot-first order of the packed iterations: perm[i] = the vertex of rank i (sources sorted
+  // by out-degree class, largest first), rank = its inverse, cp = contributions in rank order
+  uint32_t* pr_perm = nullptr;
+  uint32_t* pr_rank = nullptr;
+  uint32_t* pr_skey[2] = {};      // sort keys (out-degree classes) and their sorted copy
+  uint32_t* pr_sidx = nullptr;    // 0 .. N-1, the sort's values
+  float* pr_cp = nullptr;
+  void* pr_sort_tmp = nullptr;
+  size_t pr_sort_bytes = 0;
+  int iter_scheme = MK_ITER_PACKED;   // how all-vertex walks are scheduled
   const float* cm_params = nullptr;   // cost-model parameters for MK_AUTO (device, caller's)
   uint32_t n_heavy_rev = 0;
   bool heavy_rev_ok = false;

@@ -23,7 +23,7 @@ AUTO, INCR, RECOMPUTE = 0, 1, 2
 # incremental-WCC schemes (mk_wcc_scheme)
 WCC_LOG, WCC_NAIVE, WCC_SLAB, WCC_UPDATE = 0, 1, 2, 3
 # iteration schemes of all-vertex walks (mk_iter_scheme)
-ITER_SCHEME1, ITER_SCHEME2 = 1, 2
+ITER_SCHEME1, ITER_SCHEME2, ITER_PACKED = 1, 2, 3
 STATUS_NAMES = {0: "MK_OK", 1: "MK_ERR_INVALID_ARG", 2: "MK_ERR_OUT_OF_SLABS", 3: "MK_ERR_CAPACITY",
                 4: "MK_ERR_STATE", 5: "MK_ERR_HIP"}
 
@@ -306,8 +306,9 @@ class Graph:
         self._cm_params = params
 
     def set_iteration_scheme(self, scheme: int):
-        """ITER_SCHEME1 (a worker per vertex) or ITER_SCHEME2 (a group per bucket chain) for
-        the PageRank pull and the all-arc WCC walk."""
+        """ITER_SCHEME1 (a worker per vertex), ITER_SCHEME2 (a group per bucket chain) or
+        ITER_PACKED (the default: SCHEME1, with PageRank's later iterations of a call reading
+        packed in-arc keys) for the PageRank pull and the all-arc WCC walk."""
         _check(self.lib.mk_set_iteration_scheme(self.h, int(scheme)), "mk_set_iteration_scheme")
 
     def pagerank(self, damping: float = 0.85, tol: float = 5e-8, max_iter: int = 500,

@@ -640,7 +640,31 @@ def test_iteration_scheme2_agrees_with_the_oracle(lf):
     assert torch.equal(p.g.wcc(native.RECOMPUTE), lab2)
     p.check_pr(native.RECOMPUTE)
     with pytest.raises(native.MkError):
-        p.g.set_iteration_scheme(3)
+        p.g.set_iteration_scheme(4)
+
+
+@pytest.mark.parametrize("lf", [0.7, 0.0])
+def test_packed_pagerank_iterations_agree_with_the_oracle(lf):
+    """The packed PageRank iterations (the first one of a call walks the slabs and packs the
+    in-arc keys, the others read the packed lists): within 1e-6 in L1 of the oracle from
+    scratch and warm after insert and delete batches, hashing on and off, with vertices of
+    one bucket, of 2..16 buckets and heavier ones; scheme 1 gives the same ranks within the
+    tolerance."""
+    say(f"case: packed PageRank, load factor {lf}")
+    g = I.rmat_s(12)
+    p = make_pair(g, source=I.max_out_degree_vertex(g), load_factor=lf)
+    p.g.set_iteration_scheme(native.ITER_PACKED)
+    p.check_pr(native.RECOMPUTE)
+    wl = I.Workload(g, 78)
+    for b in (3000, 300):
+        p.insert(*wl.insert_batch(b))
+        p.check_pr()
+        p.delete(*wl.delete_batch(b))
+        p.check_pr()
+    r_packed, _ = p.g.pagerank(mode=native.RECOMPUTE)
+    p.g.set_iteration_scheme(native.ITER_SCHEME1)
+    r_s1, _ = p.g.pagerank(mode=native.RECOMPUTE)
+    assert float((r_packed.double() - r_s1.double()).abs().sum()) <= 2 * PR_L1_TOL
 
 
 def test_cost_model_on_the_graph_decides_auto_mode():
@@ -676,3 +700,40 @@ def test_cost_model_on_the_graph_decides_auto_mode():
     assert iters["incremental"] < it_cold - 2
     p.g.set_cost_model(None)
     assert p.g.lib.mk_set_cost_model(p.g.h, ctypes.c_void_p(2)) == 1  # misaligned: refused
+
+
+def test_triangle_updates_around_hubs():
+    """Triangle counts after batches whose edges touch hubs of 3,000, 24,000 and 49,999
+    neighbours: the batch-identity sum S1 of those edges runs through LDS hash sets of the hub
+    neighbourhoods, split into 1, 2 and 3 hash passes; every count equals the oracle's."""
+    say("case: triangle updates around hubs")
+    n = 50_000
+    rng = np.random.default_rng(17)
+    others = np.arange(1, n)
+    hub_s = np.concatenate([np.zeros(n - 1, np.int64), np.ones(24_000, np.int64), np.full(3_000, 2)])
+    hub_d = np.concatenate([others, rng.permutation(np.arange(2, n))[:24_000],
+                            rng.permutation(np.arange(3, n))[:3_000]])
+    flip = rng.random(hub_s.size) < 0.5  # both arc directions occur
+    s = np.where(flip, hub_d, hub_s)
+    d = np.where(flip, hub_s, hub_d)
+    bs = rng.integers(3, n, 150_000)
+    bd = rng.integers(3, n, 150_000)
+    keep = bs != bd
+    s = np.concatenate([s, bs[keep]])
+    d = np.concatenate([d, bd[keep]])
+    key = np.unique(s.astype(np.int64) * n + d)
+    s, d = key // n, key % n
+    p = Pair(n, s, d, rng.integers(1, 100, s.size), source=0)
+    p.check_tc()
+    arcs = np.stack([s, d], 1)
+    for b in (4_000, 20_000):
+        pick = arcs[rng.choice(len(arcs), b, replace=False)]  # hub-biased: most arcs touch a hub
+        p.delete(pick[:, 0], pick[:, 1])
+        p.check_tc()
+        ins_s = np.concatenate([np.zeros(b // 2, np.int64), rng.integers(3, n, b // 2)])
+        ins_d = rng.integers(1, n, b)
+        ik = np.unique(ins_s[ins_s != ins_d] * n + ins_d[ins_s != ins_d])  # no in-batch duplicates
+        p.insert(ik // n, ik % n, np.full(ik.size, 3))
+        p.check_tc()
+        p.insert(pick[:, 0], pick[:, 1], np.full(b, 5))  # the deleted arcs come back
+        p.check_tc()
