@@ -851,10 +851,11 @@ __device__ inline uint32_t tc_walked(const DView& U, uint32_t x, uint32_t y) {
   return tc_walk_u(U, u, v) ? u : v;
 }
 
-// A batch edge whose looked-up end b has more than kTcHubDeg neighbours and at least
-// kTcHubEdges batch edges is a hub edge: its S1 term is counted by k_tc_hub, which loads b's
-// neighbourhood into an LDS hash set once for all of them (a hub with fewer batch edges costs
-// less by probing).  Every other term is counted by k_tc_batch, one group per batch arc.
+// A vertex with more than kTcHubDeg neighbours and at least kTcHubEdges batch edges is a hub.
+// The S1 terms of the batch edges whose looked-up end is a hub, and the S2 terms of every
+// batch arc leaving a hub, are counted by k_tc_hub, which loads the hub's neighbourhood into
+// an LDS hash set once for all of them (a hub with fewer batch edges costs less by probing).
+// Every other term is counted by k_tc_batch, one group per batch arc.
 constexpr uint32_t kTcHubDeg = 1024;
 constexpr uint32_t kTcHubEdges = 8;
 __device__ inline bool tc_is_hub(const DView& U, uint32_t b, uint32_t batch_deg) {
@@ -864,7 +865,7 @@ __device__ inline bool tc_is_hub(const DView& U, uint32_t b, uint32_t batch_deg)
 // S1, S2 and S3 of the batch identity, one group per batch arc (u, v):
 //   S1 += |N_G(u) & N_G(v)|, S2 += |N_G(u) & N_B(v)|, S3 += |N_B(u) & N_B(v)|
 // with G the graph after the batch and B the graph of the batch alone (S1 and S3 on the
-// canonical direction u < v, counted twice).  S1 of hub edges is left to k_tc_hub.
+// canonical direction u < v, counted twice).  The terms k_tc_hub counts are skipped.
 __global__ void __launch_bounds__(kBlock) k_tc_batch(DView U, const uint64_t* keys, uint64_t nk,
                                                      const uint32_t* seg_lo, const uint32_t* seg_hi,
                                                      uint32_t nv, unsigned long long* S) {
@@ -884,16 +885,37 @@ __global__ void __launch_bounds__(kBlock) k_tc_batch(DView U, const uint64_t* ke
     // batch neighbourhoods: the segments of v and u in the sorted key list
     const uint64_t vlo = seg_lo[v], vhi = seg_hi[v];
     const uint64_t ulo = seg_lo[u], uhi = seg_hi[u];
+    auto in_seg = [&](uint64_t lo, uint64_t hi, uint32_t src, uint32_t x) {
+      const uint64_t want = ((uint64_t)src << 32) | x;
+      const uint64_t q = lower_bound_u64(keys + lo, hi - lo, want);
+      return q < hi - lo && keys[lo + q] == want;
+    };
     uint64_t c2 = 0, c3 = 0;
-    const Table tu = group_table(U, u);
-    for (uint64_t j = vlo + gl; j < vhi; j += kGroup) {
-      const uint32_t x = (uint32_t)keys[j];
-      if (x == u) continue;
-      c2 += lane_has(U, tu, x);
-      if (canon) {
-        const uint64_t want = ((uint64_t)u << 32) | x;
-        const uint64_t p = lower_bound_u64(keys + ulo, uhi - ulo, want);
-        c3 += 2 * ((p < uhi - ulo) && keys[ulo + p] == want);
+    if (tc_is_hub(U, u, (uint32_t)(uhi - ulo))) {
+      // S2 of a hub's directions is counted by k_tc_hub against its LDS sets
+    } else if (2ull * U.deg[u] < vhi - vlo) {
+      // S2 from the smaller side: walk N_G(u), look each key up in v's sorted segment
+      for_each_slab(U, u, [&](uint64_t w, bool data) {
+        const uint32_t x = (uint32_t)w;
+        if (data && valid_key(x)) c2 += in_seg(vlo, vhi, v, x);
+      });
+    } else {
+      // S2 by probing: every x of N_B(v) in u's table
+      const Table tu = group_table(U, u);
+      for (uint64_t j = vlo + gl; j < vhi; j += kGroup) {
+        const uint32_t x = (uint32_t)keys[j];
+        if (x != u) c2 += lane_has(U, tu, x);
+      }
+    }
+    if (canon) {
+      // S3: the smaller segment's entries looked up in the other segment
+      const bool u_short = uhi - ulo <= vhi - vlo;
+      const uint64_t lo = u_short ? ulo : vlo, hi = u_short ? uhi : vhi;
+      const uint64_t olo = u_short ? vlo : ulo, ohi = u_short ? vhi : uhi;
+      const uint32_t other = u_short ? v : u;
+      for (uint64_t j = lo + gl; j < hi; j += kGroup) {
+        const uint32_t x = (uint32_t)keys[j];
+        if (x != other) c3 += 2 * in_seg(olo, ohi, other, x);
       }
     }
     c2 = gsum_u64(c2);
@@ -917,7 +939,8 @@ __global__ void __launch_bounds__(kBlock) k_tc_batch(DView U, const uint64_t* ke
 // keys of N(b) whose partition hash is p (P_b passes, so that one pass fits the LDS set),
 // chunk c is a run of kTcHubChunk entries of b's segment.  An item loads its part of N(b) into
 // an LDS hash set, then walks N(a) of every partner a in its chunk (one bucket chain per lane,
-// spread over the whole block) and looks each key of the pass up.
+// spread over the whole block) and looks each key of the pass up (S1); it also looks up, for
+// the arcs (b, a), every entry of a's batch segment that falls in the pass (S2).
 //
 // The set is bucketized: 4 slots (16 bytes, one LDS read) per bucket, linear probing over
 // buckets.  At the set's load factor a lookup mostly reads one bucket, so the lanes of a wave
@@ -991,17 +1014,19 @@ __global__ void k_tc_hub_count(DView U, const uint64_t* keys, uint64_t nk, const
 
 // Persistent blocks take items from a counter until none is left.
 __global__ void __launch_bounds__(kTcHubThreads) k_tc_hub(DView U, const uint64_t* keys, uint64_t nk,
-                                                         const uint32_t* seg_hi, const uint32_t* cnt,
+                                                         const uint32_t* seg_lo, const uint32_t* seg_hi,
+                                                         const uint32_t* cnt,
                                                          const uint32_t* off, uint32_t* next,
                                                          unsigned long long* S) {
   __shared__ uint4 tab4[kTcHubSlots / 4];
   uint32_t* tab = reinterpret_cast<uint32_t*>(tab4);
   __shared__ uint32_t px[kTcHubChunk], pxb[kTcHubChunk], pnb[kTcHubChunk], pre[kTcHubChunk + 1];
+  __shared__ uint32_t pslo[kTcHubChunk], pre2[kTcHubChunk + 1];  // partners' batch segments
   __shared__ uint32_t item_s[8];
   __shared__ uint32_t full;  // a key found no free slot: this item looks keys up in b's slabs
-  __shared__ unsigned long long part[kTcHubThreads / 64];
+  __shared__ unsigned long long part[2][kTcHubThreads / 64];
   const uint32_t total = nk ? off[nk - 1] + cnt[nk - 1] : 0u;
-  uint64_t hits = 0;
+  uint64_t hits = 0, h2 = 0;  // S1 and S2 matches
   while (true) {
     if (threadIdx.x == 0) {
       const uint32_t t = atomicAdd(next, 1u);
@@ -1049,6 +1074,8 @@ __global__ void __launch_bounds__(kTcHubThreads) k_tc_hub(DView U, const uint64_
       px[j] = a;
       pnb[j] = nb;
       pxb[j] = xb;
+      pslo[j] = seg_lo[a];
+      pre2[j] = seg_hi[a] - seg_lo[a];  // segment length, scanned below
     }
     if (threadIdx.x == 64) {  // b's bucket count and first extra head slab
       const uint64_t* ps = slab_ptr(U, b);
@@ -1064,6 +1091,14 @@ __global__ void __launch_bounds__(kTcHubThreads) k_tc_hub(DView U, const uint64_
         acc += pnb[j];
       }
       pre[np] = acc;
+    } else if (threadIdx.x == 128) {  // batch-segment entries of the partners before each one
+      uint32_t acc = 0;
+      for (uint32_t j = 0; j < np; ++j) {
+        const uint32_t len = pre2[j];
+        pre2[j] = acc;
+        acc += len;
+      }
+      pre2[np] = acc;
     }
     // this pass's keys of N(b), one bucket chain per lane (each lane reads whole slabs, so a
     // wave keeps 64 slab reads in flight)
@@ -1088,6 +1123,20 @@ __global__ void __launch_bounds__(kTcHubThreads) k_tc_hub(DView U, const uint64_
     __syncthreads();
     const bool in_lds = full == 0;
     const Table tb{b, nbb, xbb};
+    // S2 of the arcs (b, a): N_B(a) of every partner a against this pass's keys of N(b), one
+    // segment entry per lane
+    const uint32_t tasks2 = pre2[np];
+    for (uint32_t t = threadIdx.x; t < tasks2; t += kTcHubThreads) {
+      uint32_t lo = 0, hi = np;  // the partner j with pre2[j] <= t < pre2[j + 1]
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (pre2[mid] <= t) lo = mid;
+        else hi = mid;
+      }
+      const uint32_t x = (uint32_t)keys[pslo[lo] + (t - pre2[lo])];
+      if (x == b || tc_part(x, P) != p) continue;
+      h2 += in_lds ? lds_has(tab, bmask, x) : lane_has(U, tb, x);
+    }
     // the partners' neighbourhoods, one bucket chain per lane, against this pass's keys of N(b)
     const uint32_t tasks = pre[np];
     for (uint32_t t = threadIdx.x; t < tasks; t += kTcHubThreads) {
@@ -1119,14 +1168,17 @@ __global__ void __launch_bounds__(kTcHubThreads) k_tc_hub(DView U, const uint64_
     }
     __syncthreads();  // the set and partner arrays are rebuilt by the next item
   }
-  // every match counts twice (S1 adds both directions of an edge)
-  for (int o = 32; o > 0; o >>= 1) hits += __shfl_xor(hits, o);
-  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = hits;
+  // an S1 match counts twice (S1 adds both directions of an edge)
+  uint64_t hs[2] = {2 * hits, h2};
+  for (int k = 0; k < 2; ++k) {
+    for (int o = 32; o > 0; o >>= 1) hs[k] += __shfl_xor(hs[k], o);
+    if ((threadIdx.x & 63) == 0) part[k][threadIdx.x >> 6] = hs[k];
+  }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < 2) {
     unsigned long long t = 0;
-    for (uint32_t i = 0; i < kTcHubThreads / 64; ++i) t += part[i];
-    if (t) atomicAdd(S, 2 * t);
+    for (uint32_t i = 0; i < kTcHubThreads / 64; ++i) t += part[threadIdx.x][i];
+    if (t) atomicAdd(S + threadIdx.x, t);
   }
 }
 
@@ -1447,7 +1499,7 @@ mk_status mk_count_triangles(mk_graph* g, uint64_t* d_count, mk_mode mode, hipSt
     }
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, &g->ctr->tc_work, 1u);
     hipLaunchKernelGGL(k_tc_hub, dim3(kTcHubBlocks), dim3(kTcHubThreads), 0, stream, U, g->tc_keys[1], nk,
-                       g->fq[5], hcnt, hoff, &g->ctr->tc_work, g->ctr->tc_s);
+                       g->fq[4], g->fq[5], hcnt, hoff, &g->ctr->tc_work, g->ctr->tc_s);
     hipLaunchKernelGGL(k_tc_finish, dim3(1), dim3(64), 0, stream, g->ctr,
                        p.kinds == 1 ? 0 : 1, out);
   }
