@@ -513,7 +513,7 @@ __global__ void __launch_bounds__(kBlock) k_pr_gather(DView R, const float* __re
 // order), so that many gathers are in flight.  Single-bucket vertices take a lane,
 // 2..16-bucket ones a 16-lane group, heavy ones work items of kPullItem in-arcs (partial sums
 // into hacc, as in k_pr_gather).
-constexpr uint32_t kPullRound = 16;
+constexpr uint32_t kPullRound = 8;
 constexpr uint32_t kPullItem = kGroup * kPullRound * 4;
 
 __global__ void k_pull_items(const uint32_t* deg, const uint32_t* heavy, const uint32_t* nheavy,
