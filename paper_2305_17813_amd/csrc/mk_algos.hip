@@ -948,9 +948,11 @@ __global__ void __launch_bounds__(kBlock) k_tc_batch(DView U, const uint64_t* ke
 // much in the measurements).
 constexpr uint32_t kTcHubThreads = 1024;
 constexpr uint32_t kTcHubSlots = 32768;               // 128 KiB of u32 keys
-constexpr uint32_t kTcHubKeys = kTcHubSlots * 5 / 8;  // keys per pass (load factor <= 0.625)
-constexpr uint32_t kTcHubChunk = 128;                 // segment entries per item
+constexpr uint32_t kTcHubKeys = kTcHubSlots * 5 / 16;  // keys per pass (load factor <= 0.3125)
+constexpr uint32_t kTcHubChunk = 512;                 // segment entries per item
 constexpr uint32_t kTcHubBlocks = 512;                // persistent blocks (one LDS set each)
+constexpr uint32_t kTcHubRun = 8;                     // list tasks a wave loads at once
+static_assert(kTcHubChunk % 64 == 0 && kTcHubChunk <= kTcHubThreads, "a wave scans a chunk");
 
 __device__ inline uint32_t tc_part(uint32_t k, uint32_t P) {
   return (uint32_t)(((uint64_t)(k * 0x85EBCA6Bu) * P) >> 32);
@@ -971,8 +973,9 @@ __device__ inline bool lds_insert(uint32_t* tab, uint32_t bmask, uint32_t key) {
   }
   return false;
 }
-__device__ inline bool lds_has(const uint32_t* tab, uint32_t bmask, uint32_t key) {
-  uint32_t h = tc_bucket(key, bmask);
+// Whether `key` is in the set, probing from bucket h on (its hash bucket, or a later one
+// when the earlier ones are known full and without it).
+__device__ inline bool lds_has_from(const uint32_t* tab, uint32_t bmask, uint32_t key, uint32_t h) {
   for (uint32_t n = 0; n <= bmask; ++n) {
     const uint4 q = reinterpret_cast<const uint4*>(tab)[h];
     if (q.x == key || q.y == key || q.z == key || q.w == key) return true;
@@ -981,19 +984,127 @@ __device__ inline bool lds_has(const uint32_t* tab, uint32_t bmask, uint32_t key
   }
   return false;
 }
+__device__ inline bool lds_has(const uint32_t* tab, uint32_t bmask, uint32_t key) {
+  return lds_has_from(tab, bmask, key, tc_bucket(key, bmask));
+}
 
-// The lookups of one slab's keys in b's slab table, when the pass overflowed its LDS set.
-// Out of line and not unrolled: it is the rare path, and the unrolled fast loop stays small.
-__device__ __attribute__((noinline)) uint64_t tc_slow_lookups(const DView& U, const Table& tb,
-                                                              const uint64_t* slab, int nd, uint32_t p,
-                                                              uint32_t P) {
-  uint64_t hits = 0;
-#pragma unroll 1
-  for (int i = 0; i < nd; ++i) {
-    const uint32_t key = (uint32_t)ld_word(slab + i);
-    if (valid_key(key) && key != tb.u && tc_part(key, P) == p) hits += lane_has(U, tb, key);
+// The last position i < n with off[i] <= t, for a non-decreasing off with off[0] <= t,
+// searched by a whole wave at once: each round the 64 lanes test 64 evenly spaced
+// positions, so a range of n entries takes ceil(log64 n) rounds of dependent loads instead
+// of log2 n.  Every lane of the wave must call it; every lane gets the result.
+__device__ inline uint64_t wave_last_le(const uint32_t* off, uint64_t n, uint32_t t) {
+  const uint64_t lane = __lane_id();
+  uint64_t lo = 0, end = n;
+  while (end - lo > 1) {
+    const uint64_t step = (end - lo + 63) / 64;
+    const uint64_t i = lo + lane * step;
+    const unsigned long long m = __ballot(i < end && off[i] <= t);  // a prefix of the lanes
+    lo += (uint64_t)(63 - __clzll(m)) * step;
+    end = min(end, lo + step);
   }
-  return hits;
+  return lo;
+}
+
+// Packed neighbour lists.  A partner's neighbourhood is read once per hub edge and pass, so
+// the partners' keys are first copied out of their slabs into contiguous u32 lists: each
+// later read is a coalesced 256-byte run instead of a chain of scattered 128-byte slabs
+// that are 15/16 filled with 8-byte words.
+//
+// k_tc_need marks every vertex walked against a hub's set (the walked end of a batch edge
+// whose other end is a hub), exactly the partners k_tc_hub reads.
+__global__ void k_tc_need(DView U, const uint64_t* keys, uint64_t nk, const uint32_t* seg_lo,
+                          const uint32_t* seg_hi, uint32_t nv, uint32_t* need) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nk;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t key = keys[i];
+    const uint32_t b = (uint32_t)(key >> 32), a = (uint32_t)key;
+    if (b >= nv) continue;  // sentinels
+    if (tc_is_hub(U, b, seg_hi[b] - seg_lo[b]) && tc_walked(U, a, b) == a) need[a] = 1;
+  }
+}
+
+constexpr uint32_t kPackBuckets = 256;  // buckets per packing item (one wave, 4 rounds of 64)
+
+// Per vertex: its list length (the live degree when marked, else 0) and its packing items;
+// the mark becomes the vertex's write cursor (0).
+__global__ void k_tc_pack_count(DView U, uint32_t nv, uint32_t* need, uint32_t* dcnt, uint32_t* icnt) {
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
+    const bool on = need[v] != 0 && U.deg[v] > 0;
+    need[v] = 0;
+    dcnt[v] = on ? U.deg[v] : 0u;
+    icnt[v] = on ? (U.nbk[v] + kPackBuckets - 1) / kPackBuckets : 0u;
+  }
+}
+
+// One wave per item <vertex a, buckets [q * kPackBuckets, ...)>: a lane walks one bucket
+// chain, reading whole slabs; per round the wave reserves room for its valid keys (with one
+// atomic on a's cursor when a has several items) and each lane writes its keys at its
+// prefix (key order in a list is arbitrary).  Writes stay inside a's range
+// [doff[a], doff[a] + deg(a)).
+__global__ void __launch_bounds__(kBlock) k_tc_pack(DView U, uint32_t nv, const uint64_t* doff,
+                                                    const uint32_t* icnt, const uint32_t* ioff,
+                                                    uint32_t* cur, uint32_t* list) {
+  if (nv == 0) return;
+  const uint32_t total = ioff[nv - 1] + icnt[nv - 1];
+  const uint32_t ln = threadIdx.x & 63;
+  const uint32_t nw = gridDim.x * (blockDim.x / 64);
+  for (uint32_t t = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64; t < total; t += nw) {
+    const uint32_t a = (uint32_t)wave_last_le(ioff, nv, t);  // ioff[a] <= t < ioff[a] + icnt[a]
+    const uint32_t q = t - ioff[a], dv = U.deg[a];
+    const uint64_t* hs = slab_ptr(U, a);
+    const uint32_t nb = (uint32_t)(ld_word(hs + 15) >> 32);
+    const uint32_t xb = nb > 1 ? (uint32_t)ld_word(hs + 14) : 0u;
+    const uint32_t bend = min(nb, (q + 1) * kPackBuckets);
+    uint32_t* out = list + doff[a];
+    const bool single = icnt[a] == 1;  // one item: no other wave writes a's list
+    uint32_t own = 0;
+    for (uint32_t b0 = q * kPackBuckets; b0 < bend; b0 += 64) {
+      const uint32_t bk = b0 + ln;
+      uint32_t s = kInvalid;
+      int nd = kKeysPerSlab;
+      if (bk < bend) {
+        s = bk == 0 ? a : xb + bk - 1;
+        nd = (bk == 0 && nb > 1) ? kKeysPerSlab - 1 : kKeysPerSlab;
+      }
+      while (__ballot(s != kInvalid) != 0) {  // wave-uniform: every lane takes every round
+        Slab sl;
+        uint32_t n = 0;
+        const bool act = s != kInvalid;
+        if (act) {
+          load_slab(U, s, sl);
+#pragma unroll
+          for (int i = 0; i < kKeysPerSlab; ++i) n += (i < nd && valid_key((uint32_t)sl.w[i])) ? 1u : 0u;
+        }
+        uint32_t incl = n;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+          const uint32_t y = __shfl_up(incl, o);
+          if ((int)ln >= o) incl += y;
+        }
+        uint32_t base = 0;
+        if (single) {  // the wave owns a's whole list
+          base = own;
+          own += __shfl(incl, 63);
+        } else {
+          if (ln == 63 && incl) base = atomicAdd(cur + a, incl);
+          base = __shfl(base, 63);
+        }
+        base += incl - n;
+        if (act) {
+#pragma unroll
+          for (int i = 0; i < kKeysPerSlab; ++i) {
+            const uint32_t key = (uint32_t)sl.w[i];
+            if (i < nd && valid_key(key)) {
+              if (base < dv) out[base] = key;
+              ++base;
+            }
+          }
+          s = (uint32_t)sl.w[15];
+          nd = kKeysPerSlab;
+        }
+      }
+    }
+  }
 }
 
 // Work items per segment start: P_b * ceil(|segment| / kTcHubChunk) at the first key of a hub's
@@ -1017,10 +1128,13 @@ __global__ void __launch_bounds__(kTcHubThreads) k_tc_hub(DView U, const uint64_
                                                          const uint32_t* seg_lo, const uint32_t* seg_hi,
                                                          const uint32_t* cnt,
                                                          const uint32_t* off, uint32_t* next,
+                                                         const uint32_t* list, const uint64_t* loff,
                                                          unsigned long long* S) {
   __shared__ uint4 tab4[kTcHubSlots / 4];
   uint32_t* tab = reinterpret_cast<uint32_t*>(tab4);
-  __shared__ uint32_t px[kTcHubChunk], pxb[kTcHubChunk], pnb[kTcHubChunk], pre[kTcHubChunk + 1];
+  // per partner: its packed list (start, length) and its 64-key tasks, scanned into pre
+  __shared__ uint64_t pbase[kTcHubChunk], qb[kTcHubChunk];
+  __shared__ uint32_t plen[kTcHubChunk], ql[kTcHubChunk], qpre[kTcHubChunk + 1], nq_s;
   __shared__ uint32_t pslo[kTcHubChunk], pre2[kTcHubChunk + 1];  // partners' batch segments
   __shared__ uint32_t item_s[8];
   __shared__ uint32_t full;  // a key found no free slot: this item looks keys up in b's slabs
@@ -1028,17 +1142,14 @@ __global__ void __launch_bounds__(kTcHubThreads) k_tc_hub(DView U, const uint64_
   const uint32_t total = nk ? off[nk - 1] + cnt[nk - 1] : 0u;
   uint64_t hits = 0, h2 = 0;  // S1 and S2 matches
   while (true) {
-    if (threadIdx.x == 0) {
-      const uint32_t t = atomicAdd(next, 1u);
-      item_s[0] = t;
-      if (t < total) {
-        // the segment start of item t: the last key position with off <= t
-        uint64_t lo = 0, hi = nk;
-        while (hi - lo > 1) {
-          const uint64_t mid = (lo + hi) >> 1;
-          if (off[mid] <= t) lo = mid;
-          else hi = mid;
-        }
+    if (threadIdx.x < 64) {  // wave 0 fetches the next item
+      uint32_t t = 0;
+      if (threadIdx.x == 0) t = atomicAdd(next, 1u);
+      t = __shfl(t, 0);
+      // the segment start of item t: the last key position with off <= t
+      const uint64_t lo = t < total ? wave_last_le(off, nk, t) : 0;
+      if (threadIdx.x == 0) item_s[0] = t;
+      if (threadIdx.x == 0 && t < total) {
         const uint32_t b = (uint32_t)(keys[lo] >> 32);
         const uint32_t P = tc_hub_passes(U.deg[b]);
         const uint32_t C = cnt[lo] / P;
@@ -1053,27 +1164,24 @@ __global__ void __launch_bounds__(kTcHubThreads) k_tc_hub(DView U, const uint64_
     }
     __syncthreads();
     if (item_s[0] >= total) break;  // every thread reads the same value
-    const uint32_t b = item_s[1], P = item_s[2], p = item_s[3], c0 = item_s[4], np = item_s[5];
-    // buckets: a power of two, at least 1.6 slots per key of the pass, within the LDS array
+    // the item, wave-uniform: in scalar registers
+    const uint32_t b = __builtin_amdgcn_readfirstlane(item_s[1]), P = __builtin_amdgcn_readfirstlane(item_s[2]);
+    const uint32_t p = __builtin_amdgcn_readfirstlane(item_s[3]), c0 = __builtin_amdgcn_readfirstlane(item_s[4]);
+    const uint32_t np = __builtin_amdgcn_readfirstlane(item_s[5]);
+    // buckets: a power of two, at least 3.2 slots per key of the pass, within the LDS array (a
+    // key's first bucket is then rarely full, and a probe rarely reads a second one)
     const uint32_t want = (U.deg[b] + P - 1) / P;
     uint32_t slots = 64;
-    while (slots < kTcHubSlots && slots * 5 < want * 8) slots <<= 1;
-    const uint32_t bmask = slots / 4 - 1;
+    while (slots < kTcHubSlots && slots * 5 < want * 16) slots <<= 1;
+    const uint32_t bmask = __builtin_amdgcn_readfirstlane(slots / 4 - 1);
     for (uint32_t i = threadIdx.x; i < slots; i += kTcHubThreads) tab[i] = kInvalid;
     if (threadIdx.x == 0) full = 0;
     // partners of this chunk: a is walked when tc_walked picks it over b
     for (uint32_t j = threadIdx.x; j < np; j += kTcHubThreads) {
       const uint32_t a = (uint32_t)keys[c0 + j];
-      const bool mine = tc_walked(U, a, b) == a;
-      uint32_t nb = 0, xb = 0;
-      if (mine && U.deg[a] > 0) {
-        const uint64_t* ps = slab_ptr(U, a);
-        nb = (uint32_t)(ld_word(ps + 15) >> 32);
-        xb = nb > 1 ? (uint32_t)ld_word(ps + 14) : 0u;
-      }
-      px[j] = a;
-      pnb[j] = nb;
-      pxb[j] = xb;
+      const uint32_t len = tc_walked(U, a, b) == a ? U.deg[a] : 0u;
+      pbase[j] = len ? loff[a] : 0;
+      plen[j] = len;
       pslo[j] = seg_lo[a];
       pre2[j] = seg_hi[a] - seg_lo[a];  // segment length, scanned below
     }
@@ -1084,21 +1192,55 @@ __global__ void __launch_bounds__(kTcHubThreads) k_tc_hub(DView U, const uint64_
       item_s[7] = nbb0 > 1 ? (uint32_t)ld_word(ps + 14) : 0u;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {  // bucket chains of the partners before each one
-      uint32_t acc = 0;
-      for (uint32_t j = 0; j < np; ++j) {
-        pre[j] = acc;
-        acc += pnb[j];
+    if (threadIdx.x < 128) {
+      // two scans, one wave each, a lane owning kTcHubChunk / 64 consecutive partners.
+      // Wave 0 compacts the partners with a non-empty list, in order, into qb / ql with the
+      // exclusive prefix of their 64-key tasks in qpre (qpre[nq] = all tasks); wave 1 turns
+      // the partners' batch-segment lengths in pre2 into their exclusive prefix.
+      constexpr uint32_t kPer = kTcHubChunk / 64;
+      const uint32_t ln = threadIdx.x & 63;
+      const bool w0 = threadIdx.x < 64;
+      uint32_t v[kPer], sum = 0, nz = 0;
+#pragma unroll
+      for (uint32_t k = 0; k < kPer; ++k) {
+        const uint32_t j = ln * kPer + k;
+        v[k] = j >= np ? 0u : w0 ? (plen[j] + 63) / 64 : pre2[j];
+        sum += v[k];
+        nz += v[k] != 0;
       }
-      pre[np] = acc;
-    } else if (threadIdx.x == 128) {  // batch-segment entries of the partners before each one
-      uint32_t acc = 0;
-      for (uint32_t j = 0; j < np; ++j) {
-        const uint32_t len = pre2[j];
-        pre2[j] = acc;
-        acc += len;
+      uint32_t incl = sum, zincl = nz;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(incl, o), z = __shfl_up(zincl, o);
+        if ((int)ln >= o) {
+          incl += t;
+          zincl += z;
+        }
       }
-      pre2[np] = acc;
+      uint32_t acc = incl - sum, q = zincl - nz;
+#pragma unroll
+      for (uint32_t k = 0; k < kPer; ++k) {
+        const uint32_t j = ln * kPer + k;
+        if (w0) {
+          if (v[k]) {
+            qpre[q] = acc;
+            qb[q] = pbase[j];
+            ql[q] = plen[j];
+            ++q;
+          }
+        } else if (j < np) {
+          pre2[j] = acc;
+        }
+        acc += v[k];
+      }
+      if (ln == 63) {
+        if (w0) {
+          qpre[zincl] = incl;
+          nq_s = zincl;
+        } else {
+          pre2[np] = incl;
+        }
+      }
     }
     // this pass's keys of N(b), one bucket chain per lane (each lane reads whole slabs, so a
     // wave keeps 64 slab reads in flight)
@@ -1137,34 +1279,106 @@ __global__ void __launch_bounds__(kTcHubThreads) k_tc_hub(DView U, const uint64_
       if (x == b || tc_part(x, P) != p) continue;
       h2 += in_lds ? lds_has(tab, bmask, x) : lane_has(U, tb, x);
     }
-    // the partners' neighbourhoods, one bucket chain per lane, against this pass's keys of N(b)
-    const uint32_t tasks = pre[np];
-    for (uint32_t t = threadIdx.x; t < tasks; t += kTcHubThreads) {
-      uint32_t lo = 0, hi = np;  // the partner j with pre[j] <= t < pre[j + 1]
-      while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (pre[mid] <= t) lo = mid;
+    // the partners' packed lists against this pass's keys of N(b).  Wave w takes a run of
+    // consecutive 64-key tasks, kTcHubRun at a time: the tasks' partners come from kTcHubRun
+    // lookahead prefixes (a partner has at least one task), the keys from one coalesced load
+    // per task, and each key's first bucket from one LDS read, all issued before any is used.
+    // Everything that selects a task's partner is wave-uniform and kept in scalar registers
+    // (readfirstlane), so the vector units only form addresses, hash and compare keys.
+    const uint32_t nq = __builtin_amdgcn_readfirstlane(nq_s);
+    const uint32_t tasks = __builtin_amdgcn_readfirstlane(qpre[nq]);
+    const uint32_t per = (tasks + kTcHubThreads / 64 - 1) / (kTcHubThreads / 64);
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t tb0 = min(tasks, wv * per), te = min(tasks, tb0 + per);
+    const uint32_t lane = threadIdx.x & 63;
+    uint32_t j = 0;  // the partner of task tb0: the last j with qpre[j] <= tb0
+    if (tb0 < te) {
+      uint32_t hi = nq;
+      while (hi - j > 1) {
+        const uint32_t mid = (j + hi) >> 1;
+        if (__builtin_amdgcn_readfirstlane(qpre[mid]) <= tb0) j = mid;
         else hi = mid;
       }
-      const uint32_t a = px[lo], k = t - pre[lo], nba = pnb[lo];
-      uint32_t s = k == 0 ? a : pxb[lo] + k - 1;
-      int nd = (k == 0 && nba > 1) ? kKeysPerSlab - 1 : kKeysPerSlab;
-      while (true) {
-        Slab sl;
-        load_slab(U, s, sl);
-        if (in_lds) {
+    }
+    // a run's partners are j .. j + kTcHubRun - 1: their prefixes, lengths and list starts are
+    // read at once, and each task selects its own by the count of prefixes at or below it
+    auto runs = [&](auto&& probe) {
+      for (uint32_t t0 = tb0; t0 < te; t0 += kTcHubRun) {
+        uint32_t nx[kTcHubRun], ln_[kTcHubRun], blo[kTcHubRun], bhi[kTcHubRun];
 #pragma unroll
-          for (int i = 0; i < kKeysPerSlab; ++i) {
-            const uint32_t key = (uint32_t)sl.w[i];
-            if (i < nd && valid_key(key) && key != b && tc_part(key, P) == p) hits += lds_has(tab, bmask, key);
-          }
-        } else {
-          hits += tc_slow_lookups(U, tb, slab_ptr(U, s), nd, p, P);
+        for (uint32_t k = 0; k < kTcHubRun; ++k) {
+          nx[k] = __builtin_amdgcn_readfirstlane(qpre[min(j + 1 + k, nq)]);
+          ln_[k] = __builtin_amdgcn_readfirstlane(ql[min(j + k, nq - 1)]);
+          const uint64_t bq = qb[min(j + k, nq - 1)];
+          blo[k] = __builtin_amdgcn_readfirstlane((uint32_t)bq);
+          bhi[k] = __builtin_amdgcn_readfirstlane((uint32_t)(bq >> 32));
         }
-        s = (uint32_t)sl.w[15];
-        if (s == kInvalid) break;
-        nd = kKeysPerSlab;
+        const uint32_t pj = __builtin_amdgcn_readfirstlane(qpre[j]);
+        uint32_t key[kTcHubRun];
+#pragma unroll
+        for (uint32_t r = 0; r < kTcHubRun; ++r) {
+          const uint32_t t = t0 + r;  // its partner is j + c, c <= r (a partner has >= 1 task)
+          uint32_t start = pj, len = ln_[0], lo = blo[0], hi = bhi[0];
+#pragma unroll
+          for (uint32_t k = 0; k + 1 < kTcHubRun; ++k)
+            if (nx[k] <= t) {
+              start = nx[k];
+              len = ln_[k + 1];
+              lo = blo[k + 1];
+              hi = bhi[k + 1];
+            }
+          const uint32_t pos = (t - start) * 64 + lane;
+          const uint32_t* src = list + (((uint64_t)hi << 32) | lo);
+          key[r] = t < te && pos < len ? src[pos] : kInvalid;
+        }
+        uint32_t cn = 0;  // the partner of the next run's first task, t0 + kTcHubRun: j + cn
+#pragma unroll
+        for (uint32_t k = 0; k < kTcHubRun; ++k) cn += nx[k] <= t0 + kTcHubRun;
+        j = min(j + cn, nq - 1);
+        hits += probe(key);
       }
+    };
+    // keys of this pass: all of them when b takes one pass
+    auto wanted = [&](uint32_t x) { return x != kInvalid && x != b && (P == 1 || tc_part(x, P) == p); };
+    if (in_lds) {
+      runs([&](const uint32_t (&key)[kTcHubRun]) -> uint32_t {
+        uint32_t h[kTcHubRun];
+        uint4 q4[kTcHubRun];
+#pragma unroll
+        for (uint32_t r = 0; r < kTcHubRun; ++r) {  // every first bucket, before any is tested
+          h[r] = tc_bucket(key[r], bmask);
+          q4[r] = tab4[h[r]];
+        }
+        uint32_t n = 0, pend = 0;
+#pragma unroll
+        for (uint32_t r = 0; r < kTcHubRun; ++r) {
+          const uint32_t x = key[r];
+          if (!wanted(x)) continue;
+          if (q4[r].x == x || q4[r].y == x || q4[r].z == x || q4[r].w == x) {
+            ++n;
+          } else if (q4[r].x != kInvalid && q4[r].y != kInvalid && q4[r].z != kInvalid && q4[r].w != kInvalid) {
+            pend |= 1u << r;
+          }
+        }
+        while (pend) {  // keys whose first bucket was full, all runs of the wave at once
+          const uint32_t r = __builtin_ctz(pend);
+          pend &= pend - 1;
+          uint32_t x = key[0], hh = h[0];
+#pragma unroll
+          for (uint32_t k = 1; k < kTcHubRun; ++k)
+            if (k == r) { x = key[k]; hh = h[k]; }
+          n += lds_has_from(tab, bmask, x, (hh + 1) & bmask);
+        }
+        return n;
+      });
+    } else {  // the pass overflowed its set: look the keys up in b's slabs
+      runs([&](const uint32_t (&key)[kTcHubRun]) -> uint32_t {
+        uint32_t n = 0;
+#pragma unroll 1
+        for (uint32_t r = 0; r < kTcHubRun; ++r)
+          if (wanted(key[r])) n += lane_has(U, tb, key[r]);
+        return n;
+      });
     }
     __syncthreads();  // the set and partner arrays are rebuilt by the next item
   }
@@ -1497,9 +1711,28 @@ mk_status mk_count_triangles(mk_graph* g, uint64_t* d_count, mk_mode mode, hipSt
                                   stream) != hipSuccess)
         return MK_ERR_HIP;
     }
+    // packed lists of the hub partners (scratch: the other traversal queues)
+    uint32_t *dcnt = g->fq[0], *icnt = g->fq[1], *ioff = g->fq[2], *need = g->fq[3];
+    hipLaunchKernelGGL(k_zero_u32, dim3(blocks_for(N)), dim3(kBlock), 0, stream, need, N);
+    hipLaunchKernelGGL(k_tc_need, dim3(blocks_for(nk)), dim3(kBlock), 0, stream, U, g->tc_keys[1], nk,
+                       g->fq[4], g->fq[5], N, need);
+    hipLaunchKernelGGL(k_tc_pack_count, dim3(blocks_for(N)), dim3(kBlock), 0, stream, U, N, need, dcnt, icnt);
+    {
+      size_t tb2 = g->scan_tmp_bytes;
+      if (rocprim::exclusive_scan(g->scan_tmp, tb2, dcnt, g->tc_off, (uint64_t)0, (size_t)N,
+                                  rocprim::plus<uint64_t>(), stream) != hipSuccess)
+        return MK_ERR_HIP;
+      tb2 = g->scan_tmp_bytes;
+      if (rocprim::exclusive_scan(g->scan_tmp, tb2, icnt, ioff, 0u, (size_t)N, rocprim::plus<uint32_t>(),
+                                  stream) != hipSuccess)
+        return MK_ERR_HIP;
+    }
+    hipLaunchKernelGGL(k_tc_pack, dim3(kWalkBlocks), dim3(kBlock), 0, stream, U, N, g->tc_off, icnt, ioff, need,
+                       g->tc_list);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, &g->ctr->tc_work, 1u);
     hipLaunchKernelGGL(k_tc_hub, dim3(kTcHubBlocks), dim3(kTcHubThreads), 0, stream, U, g->tc_keys[1], nk,
-                       g->fq[4], g->fq[5], hcnt, hoff, &g->ctr->tc_work, g->ctr->tc_s);
+                       g->fq[4], g->fq[5], hcnt, hoff, &g->ctr->tc_work, g->tc_list, g->tc_off,
+                       g->ctr->tc_s);
     hipLaunchKernelGGL(k_tc_finish, dim3(1), dim3(64), 0, stream, g->ctr,
                        p.kinds == 1 ? 0 : 1, out);
   }

@@ -710,7 +710,7 @@ bool layout(const mk_config* c, uint64_t m, char* base, mk_graph* g, size_t* tot
   Carver cv{base};
   const uint32_t N = c->n_vertices;
   const uint32_t views = c->views | MK_VIEW_FWD;
-  uint64_t hb_fwd = 0, hb_rev = 0;
+  uint64_t hb_fwd = 0, hb_rev = 0, und_words = 0;
   for (int v = 0; v < 3; ++v) {
     const bool on = views & (1u << v);
     if (!on) continue;
@@ -731,6 +731,7 @@ bool layout(const mk_config* c, uint64_t m, char* base, mk_graph* g, size_t* tot
       pair_off = cv.take<uint32_t>(N);
     }
     if (v == VR) hb_rev = hb;
+    if (v == VU) und_words = (hb + pc) * kKeysPerSlab;  // bounds the live keys of the view
     if (g) {
       ViewHost& vh = g->view[v];
       vh.on = true;
@@ -802,10 +803,17 @@ bool layout(const mk_config* c, uint64_t m, char* base, mk_graph* g, size_t* tot
   uint32_t* lvm1 = cv.take<uint32_t>(lv_cap);
   uint64_t* tk0 = nullptr;
   uint64_t* tk1 = nullptr;
-  size_t sort_bytes = 0, scan_bytes = 0;
+  uint32_t* tclist = nullptr;
+  uint64_t* tcoff = nullptr;
+  size_t sort_bytes = 0, scan_bytes = 0, scan64_bytes = 0;
   if (views & MK_VIEW_UND) {
     tk0 = cv.take<uint64_t>(2 * L);
     tk1 = cv.take<uint64_t>(2 * L);
+    tclist = cv.take<uint32_t>(und_words);
+    tcoff = cv.take<uint64_t>(N);
+    if (rocprim::exclusive_scan(nullptr, scan64_bytes, (uint32_t*)nullptr, (uint64_t*)nullptr, (uint64_t)0,
+                                (size_t)N, rocprim::plus<uint64_t>()) != hipSuccess)
+      return false;
     if (rocprim::radix_sort_keys(nullptr, sort_bytes, (uint64_t*)nullptr, (uint64_t*)nullptr,
                                  (size_t)(2 * L), 0, 64) != hipSuccess)
       return false;
@@ -815,6 +823,7 @@ bool layout(const mk_config* c, uint64_t m, char* base, mk_graph* g, size_t* tot
   if (rocprim::exclusive_scan(nullptr, scan_bytes, (uint32_t*)nullptr, (uint32_t*)nullptr, 0u,
                               std::max<size_t>(N, 2 * L), rocprim::plus<uint32_t>()) != hipSuccess)
     return false;
+  scan_bytes = std::max(scan_bytes, scan64_bytes);  // and the u64 offsets of the packed lists
   void* scan_tmp = cv.take<char>(scan_bytes + 256);
   if (g) {
     g->log = lg;
@@ -853,6 +862,8 @@ bool layout(const mk_config* c, uint64_t m, char* base, mk_graph* g, size_t* tot
     g->lv_multi[1] = lvm1;
     g->tc_keys[0] = tk0;
     g->tc_keys[1] = tk1;
+    g->tc_list = tclist;
+    g->tc_off = tcoff;
     g->sort_tmp = sort_tmp;
     g->sort_tmp_bytes = sort_bytes;
     g->scan_tmp = scan_tmp;

@@ -153,6 +153,10 @@ struct mk_graph {
   bool heavy_rev_ok = false;
 
   uint64_t* tc_keys[2] = {nullptr, nullptr};
+  // packed neighbour lists of the triangle update: the keys of the vertices whose
+  // neighbourhood is walked against a hub's set, one u32 per key, at tc_off[v]
+  uint32_t* tc_list = nullptr;
+  uint64_t* tc_off = nullptr;
   void* sort_tmp = nullptr;
   size_t sort_tmp_bytes = 0;
   void* scan_tmp = nullptr;
