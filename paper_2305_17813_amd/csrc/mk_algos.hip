@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "mk_internal.h"
 
@@ -856,8 +857,8 @@ __device__ inline uint32_t tc_walked(const DView& U, uint32_t x, uint32_t y) {
 // batch arc leaving a hub, are counted by k_tc_hub, which loads the hub's neighbourhood into
 // an LDS hash set once for all of them (a hub with fewer batch edges costs less by probing).
 // Every other term is counted by k_tc_batch, one group per batch arc.
-constexpr uint32_t kTcHubDeg = 1024;
-constexpr uint32_t kTcHubEdges = 8;
+constexpr uint32_t kTcHubDeg = 512;
+constexpr uint32_t kTcHubEdges = 4;
 __device__ inline bool tc_is_hub(const DView& U, uint32_t b, uint32_t batch_deg) {
   return U.deg[b] > kTcHubDeg && batch_deg >= kTcHubEdges;
 }
@@ -937,28 +938,40 @@ __global__ void __launch_bounds__(kBlock) k_tc_batch(DView U, const uint64_t* ke
 // A hub b (tc_is_hub, with its segment in the sorted batch keys) owns the batch edges {a, b}
 // whose walked end is a.  Its work is split into items <b, pass p, chunk c>: pass p keeps the
 // keys of N(b) whose partition hash is p (P_b passes, so that one pass fits the LDS set),
-// chunk c is a run of kTcHubChunk entries of b's segment.  An item loads its part of N(b) into
-// an LDS hash set, then walks N(a) of every partner a in its chunk (one bucket chain per lane,
-// spread over the whole block) and looks each key of the pass up (S1); it also looks up, for
-// the arcs (b, a), every entry of a's batch segment that falls in the pass (S2).
+// chunk c is a run of entries of b's segment.  An item loads its part of N(b) into an LDS
+// hash set, then reads the packed list of every partner a in its chunk (spread over the
+// whole block) and looks each key of the pass up (S1); it also looks up, for the arcs
+// (b, a), every entry of a's batch segment that falls in the pass (S2).
 //
 // The set is bucketized: 4 slots (16 bytes, one LDS read) per bucket, linear probing over
 // buckets.  At the set's load factor a lookup mostly reads one bucket, so the lanes of a wave
 // rarely wait for each other's probe chains (one slot per probe step cost about twice as
 // much in the measurements).
-constexpr uint32_t kTcHubThreads = 1024;
-constexpr uint32_t kTcHubSlots = 32768;               // 128 KiB of u32 keys
-constexpr uint32_t kTcHubKeys = kTcHubSlots * 5 / 16;  // keys per pass (load factor <= 0.3125)
-constexpr uint32_t kTcHubChunk = 512;                 // segment entries per item
-constexpr uint32_t kTcHubBlocks = 512;                // persistent blocks (one LDS set each)
-constexpr uint32_t kTcHubRun = 8;                     // list tasks a wave loads at once
-static_assert(kTcHubChunk % 64 == 0 && kTcHubChunk <= kTcHubThreads, "a wave scans a chunk");
+//
+// Two classes of hubs, one launch each: a small hub (at most HubClass<true>::kKeys
+// neighbours) takes a 256-thread block with a 32 KiB set, four blocks to a CU, so that the
+// latency of one item's dependent steps overlaps the others'; a large one takes a
+// 1024-thread block with a 128 KiB set, one to a CU, in as many passes as it needs.
+template <bool Small>
+struct HubClass {
+  static constexpr uint32_t kThreads = Small ? 256 : 1024;
+  static constexpr uint32_t kSlots = Small ? 8192 : 32768;  // u32 keys of the LDS set
+  static constexpr uint32_t kKeys = kSlots * 5 / 16;        // keys per pass (load <= 0.3125)
+  static constexpr uint32_t kChunk = Small ? 128 : 512;     // segment entries per item
+  static constexpr uint32_t kBlocks = Small ? 1024 : 512;   // persistent blocks
+  static_assert(kChunk % 64 == 0 && kChunk <= kThreads && kThreads >= 128, "a wave scans a chunk");
+};
+constexpr uint32_t kTcHubRun = 8;  // list tasks a wave loads at once
+__device__ inline bool tc_small_hub(const DView& U, uint32_t b) { return U.deg[b] <= HubClass<true>::kKeys; }
 
 __device__ inline uint32_t tc_part(uint32_t k, uint32_t P) {
   return (uint32_t)(((uint64_t)(k * 0x85EBCA6Bu) * P) >> 32);
 }
 __device__ inline uint32_t tc_bucket(uint32_t k, uint32_t bmask) { return (k * 0x9E3779B1u) >> 9 & bmask; }
-__device__ inline uint32_t tc_hub_passes(uint32_t deg) { return max(1u, (deg + kTcHubKeys - 1) / kTcHubKeys); }
+template <bool Small>
+__device__ inline uint32_t tc_hub_passes(uint32_t deg) {
+  return max(1u, (deg + HubClass<Small>::kKeys - 1) / HubClass<Small>::kKeys);
+}
 
 // Insert `key` into the bucketized LDS set of bmask + 1 buckets; false when the set is full.
 __device__ inline bool lds_insert(uint32_t* tab, uint32_t bmask, uint32_t key) {
@@ -1107,38 +1120,43 @@ __global__ void __launch_bounds__(kBlock) k_tc_pack(DView U, uint32_t nv, const 
   }
 }
 
-// Work items per segment start: P_b * ceil(|segment| / kTcHubChunk) at the first key of a hub's
-// segment, 0 elsewhere (an exclusive scan of these numbers the items).
+// Work items per segment start: P_b * ceil(|segment| / chunk) at the first key of a hub's
+// segment when the hub is of the class, 0 elsewhere (an exclusive scan numbers the items).
+template <bool Small>
 __global__ void k_tc_hub_count(DView U, const uint64_t* keys, uint64_t nk, const uint32_t* seg_hi,
                                uint32_t nv, uint32_t* cnt) {
+  using H = HubClass<Small>;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nk;
        i += (uint64_t)gridDim.x * blockDim.x) {
     const uint32_t b = (uint32_t)(keys[i] >> 32);
     uint32_t c = 0;
-    if (b < nv && (i == 0 || (uint32_t)(keys[i - 1] >> 32) != b) && tc_is_hub(U, b, seg_hi[b] - (uint32_t)i)) {
+    if (b < nv && (i == 0 || (uint32_t)(keys[i - 1] >> 32) != b) && tc_is_hub(U, b, seg_hi[b] - (uint32_t)i) &&
+        tc_small_hub(U, b) == Small) {
       const uint64_t len = seg_hi[b] - i;
-      c = tc_hub_passes(U.deg[b]) * (uint32_t)((len + kTcHubChunk - 1) / kTcHubChunk);
+      c = tc_hub_passes<Small>(U.deg[b]) * (uint32_t)((len + H::kChunk - 1) / H::kChunk);
     }
     cnt[i] = c;
   }
 }
 
 // Persistent blocks take items from a counter until none is left.
-__global__ void __launch_bounds__(kTcHubThreads) k_tc_hub(DView U, const uint64_t* keys, uint64_t nk,
+template <bool Small>
+__global__ void __launch_bounds__(HubClass<Small>::kThreads) k_tc_hub(DView U, const uint64_t* keys, uint64_t nk,
                                                          const uint32_t* seg_lo, const uint32_t* seg_hi,
                                                          const uint32_t* cnt,
                                                          const uint32_t* off, uint32_t* next,
                                                          const uint32_t* list, const uint64_t* loff,
                                                          unsigned long long* S) {
-  __shared__ uint4 tab4[kTcHubSlots / 4];
+  using H = HubClass<Small>;
+  __shared__ uint4 tab4[H::kSlots / 4];
   uint32_t* tab = reinterpret_cast<uint32_t*>(tab4);
   // per partner: its packed list (start, length) and its 64-key tasks, scanned into pre
-  __shared__ uint64_t pbase[kTcHubChunk], qb[kTcHubChunk];
-  __shared__ uint32_t plen[kTcHubChunk], ql[kTcHubChunk], qpre[kTcHubChunk + 1], nq_s;
-  __shared__ uint32_t pslo[kTcHubChunk], pre2[kTcHubChunk + 1];  // partners' batch segments
+  __shared__ uint64_t pbase[H::kChunk], qb[H::kChunk];
+  __shared__ uint32_t plen[H::kChunk], ql[H::kChunk], qpre[H::kChunk + 1], nq_s;
+  __shared__ uint32_t pslo[H::kChunk], pre2[H::kChunk + 1];  // partners' batch segments
   __shared__ uint32_t item_s[8];
   __shared__ uint32_t full;  // a key found no free slot: this item looks keys up in b's slabs
-  __shared__ unsigned long long part[2][kTcHubThreads / 64];
+  __shared__ unsigned long long part[2][H::kThreads / 64];
   const uint32_t total = nk ? off[nk - 1] + cnt[nk - 1] : 0u;
   uint64_t hits = 0, h2 = 0;  // S1 and S2 matches
   while (true) {
@@ -1151,15 +1169,15 @@ __global__ void __launch_bounds__(kTcHubThreads) k_tc_hub(DView U, const uint64_
       if (threadIdx.x == 0) item_s[0] = t;
       if (threadIdx.x == 0 && t < total) {
         const uint32_t b = (uint32_t)(keys[lo] >> 32);
-        const uint32_t P = tc_hub_passes(U.deg[b]);
+        const uint32_t P = tc_hub_passes<Small>(U.deg[b]);
         const uint32_t C = cnt[lo] / P;
         const uint32_t local = t - off[lo];
-        const uint64_t c0 = lo + (uint64_t)(local % C) * kTcHubChunk;
+        const uint64_t c0 = lo + (uint64_t)(local % C) * H::kChunk;
         item_s[1] = b;
         item_s[2] = P;
         item_s[3] = local / C;
         item_s[4] = (uint32_t)c0;
-        item_s[5] = (uint32_t)min<uint64_t>(c0 + kTcHubChunk, seg_hi[b]) - (uint32_t)c0;
+        item_s[5] = (uint32_t)min<uint64_t>(c0 + H::kChunk, seg_hi[b]) - (uint32_t)c0;
       }
     }
     __syncthreads();
@@ -1172,12 +1190,12 @@ __global__ void __launch_bounds__(kTcHubThreads) k_tc_hub(DView U, const uint64_
     // key's first bucket is then rarely full, and a probe rarely reads a second one)
     const uint32_t want = (U.deg[b] + P - 1) / P;
     uint32_t slots = 64;
-    while (slots < kTcHubSlots && slots * 5 < want * 16) slots <<= 1;
+    while (slots < H::kSlots && slots * 5 < want * 16) slots <<= 1;
     const uint32_t bmask = __builtin_amdgcn_readfirstlane(slots / 4 - 1);
-    for (uint32_t i = threadIdx.x; i < slots; i += kTcHubThreads) tab[i] = kInvalid;
+    for (uint32_t i = threadIdx.x; i < slots; i += H::kThreads) tab[i] = kInvalid;
     if (threadIdx.x == 0) full = 0;
     // partners of this chunk: a is walked when tc_walked picks it over b
-    for (uint32_t j = threadIdx.x; j < np; j += kTcHubThreads) {
+    for (uint32_t j = threadIdx.x; j < np; j += H::kThreads) {
       const uint32_t a = (uint32_t)keys[c0 + j];
       const uint32_t len = tc_walked(U, a, b) == a ? U.deg[a] : 0u;
       pbase[j] = len ? loff[a] : 0;
@@ -1193,11 +1211,11 @@ __global__ void __launch_bounds__(kTcHubThreads) k_tc_hub(DView U, const uint64_
     }
     __syncthreads();
     if (threadIdx.x < 128) {
-      // two scans, one wave each, a lane owning kTcHubChunk / 64 consecutive partners.
+      // two scans, one wave each, a lane owning H::kChunk / 64 consecutive partners.
       // Wave 0 compacts the partners with a non-empty list, in order, into qb / ql with the
       // exclusive prefix of their 64-key tasks in qpre (qpre[nq] = all tasks); wave 1 turns
       // the partners' batch-segment lengths in pre2 into their exclusive prefix.
-      constexpr uint32_t kPer = kTcHubChunk / 64;
+      constexpr uint32_t kPer = H::kChunk / 64;
       const uint32_t ln = threadIdx.x & 63;
       const bool w0 = threadIdx.x < 64;
       uint32_t v[kPer], sum = 0, nz = 0;
@@ -1245,7 +1263,7 @@ __global__ void __launch_bounds__(kTcHubThreads) k_tc_hub(DView U, const uint64_
     // this pass's keys of N(b), one bucket chain per lane (each lane reads whole slabs, so a
     // wave keeps 64 slab reads in flight)
     const uint32_t nbb = item_s[6], xbb = item_s[7];
-    for (uint32_t k = threadIdx.x; k < nbb; k += kTcHubThreads) {
+    for (uint32_t k = threadIdx.x; k < nbb; k += H::kThreads) {
       uint32_t s = k == 0 ? b : xbb + k - 1;
       int nd = (k == 0 && nbb > 1) ? kKeysPerSlab - 1 : kKeysPerSlab;
       while (true) {
@@ -1268,7 +1286,7 @@ __global__ void __launch_bounds__(kTcHubThreads) k_tc_hub(DView U, const uint64_
     // S2 of the arcs (b, a): N_B(a) of every partner a against this pass's keys of N(b), one
     // segment entry per lane
     const uint32_t tasks2 = pre2[np];
-    for (uint32_t t = threadIdx.x; t < tasks2; t += kTcHubThreads) {
+    for (uint32_t t = threadIdx.x; t < tasks2; t += H::kThreads) {
       uint32_t lo = 0, hi = np;  // the partner j with pre2[j] <= t < pre2[j + 1]
       while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) >> 1;
@@ -1287,7 +1305,7 @@ __global__ void __launch_bounds__(kTcHubThreads) k_tc_hub(DView U, const uint64_
     // (readfirstlane), so the vector units only form addresses, hash and compare keys.
     const uint32_t nq = __builtin_amdgcn_readfirstlane(nq_s);
     const uint32_t tasks = __builtin_amdgcn_readfirstlane(qpre[nq]);
-    const uint32_t per = (tasks + kTcHubThreads / 64 - 1) / (kTcHubThreads / 64);
+    const uint32_t per = (tasks + H::kThreads / 64 - 1) / (H::kThreads / 64);
     const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t tb0 = min(tasks, wv * per), te = min(tasks, tb0 + per);
     const uint32_t lane = threadIdx.x & 63;
@@ -1391,7 +1409,7 @@ __global__ void __launch_bounds__(kTcHubThreads) k_tc_hub(DView U, const uint64_
   __syncthreads();
   if (threadIdx.x < 2) {
     unsigned long long t = 0;
-    for (uint32_t i = 0; i < kTcHubThreads / 64; ++i) t += part[threadIdx.x][i];
+    for (uint32_t i = 0; i < H::kThreads / 64; ++i) t += part[threadIdx.x][i];
     if (t) atomicAdd(S + threadIdx.x, t);
   }
 }
@@ -1703,14 +1721,6 @@ mk_status mk_count_triangles(mk_graph* g, uint64_t* d_count, mk_mode mode, hipSt
     // positions, in the sort's input buffer (free after the sort; 2 * nk u32 fit in it)
     uint32_t* hcnt = reinterpret_cast<uint32_t*>(g->tc_keys[0]);
     uint32_t* hoff = hcnt + nk;
-    hipLaunchKernelGGL(k_tc_hub_count, dim3(blocks_for(nk)), dim3(kBlock), 0, stream, U, g->tc_keys[1], nk,
-                       g->fq[5], N, hcnt);
-    {
-      size_t tb2 = g->scan_tmp_bytes;
-      if (rocprim::exclusive_scan(g->scan_tmp, tb2, hcnt, hoff, 0u, (size_t)nk, rocprim::plus<uint32_t>(),
-                                  stream) != hipSuccess)
-        return MK_ERR_HIP;
-    }
     // packed lists of the hub partners (scratch: the other traversal queues)
     uint32_t *dcnt = g->fq[0], *icnt = g->fq[1], *ioff = g->fq[2], *need = g->fq[3];
     hipLaunchKernelGGL(k_zero_u32, dim3(blocks_for(N)), dim3(kBlock), 0, stream, need, N);
@@ -1729,10 +1739,23 @@ mk_status mk_count_triangles(mk_graph* g, uint64_t* d_count, mk_mode mode, hipSt
     }
     hipLaunchKernelGGL(k_tc_pack, dim3(kWalkBlocks), dim3(kBlock), 0, stream, U, N, g->tc_off, icnt, ioff, need,
                        g->tc_list);
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, &g->ctr->tc_work, 1u);
-    hipLaunchKernelGGL(k_tc_hub, dim3(kTcHubBlocks), dim3(kTcHubThreads), 0, stream, U, g->tc_keys[1], nk,
-                       g->fq[4], g->fq[5], hcnt, hoff, &g->ctr->tc_work, g->tc_list, g->tc_off,
-                       g->ctr->tc_s);
+    // the small hubs' items, then the large ones' (the item numbering is redone per class)
+    auto hub_launch = [&](auto cls) -> bool {
+      constexpr bool kSmall = decltype(cls)::value;
+      using H = HubClass<kSmall>;
+      hipLaunchKernelGGL(k_tc_hub_count<kSmall>, dim3(blocks_for(nk)), dim3(kBlock), 0, stream, U,
+                         g->tc_keys[1], nk, g->fq[5], N, hcnt);
+      size_t tb2 = g->scan_tmp_bytes;
+      if (rocprim::exclusive_scan(g->scan_tmp, tb2, hcnt, hoff, 0u, (size_t)nk, rocprim::plus<uint32_t>(),
+                                  stream) != hipSuccess)
+        return false;
+      hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, &g->ctr->tc_work, 1u);
+      hipLaunchKernelGGL(k_tc_hub<kSmall>, dim3(H::kBlocks), dim3(H::kThreads), 0, stream, U, g->tc_keys[1], nk,
+                         g->fq[4], g->fq[5], hcnt, hoff, &g->ctr->tc_work, g->tc_list, g->tc_off,
+                         g->ctr->tc_s);
+      return true;
+    };
+    if (!hub_launch(std::true_type{}) || !hub_launch(std::false_type{})) return MK_ERR_HIP;
     hipLaunchKernelGGL(k_tc_finish, dim3(1), dim3(64), 0, stream, g->ctr,
                        p.kinds == 1 ? 0 : 1, out);
   }

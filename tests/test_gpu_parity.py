@@ -703,21 +703,23 @@ def test_cost_model_on_the_graph_decides_auto_mode():
 
 
 def test_triangle_updates_around_hubs():
-    """Triangle counts after batches whose edges touch hubs of 3,000, 24,000 and 49,999
+    """Triangle counts after batches whose edges touch hubs of 1,500, 3,000, 24,000 and 49,999
     neighbours: the batch-identity sum S1 of those edges runs through LDS hash sets of the hub
-    neighbourhoods, split into 1, 2 and 3 hash passes; every count equals the oracle's."""
+    neighbourhoods: the small-hub class (one 32 KiB set) for the first, the large class in 1,
+    3 and 5 hash passes for the others; every count equals the oracle's."""
     say("case: triangle updates around hubs")
     n = 50_000
     rng = np.random.default_rng(17)
     others = np.arange(1, n)
-    hub_s = np.concatenate([np.zeros(n - 1, np.int64), np.ones(24_000, np.int64), np.full(3_000, 2)])
+    hub_s = np.concatenate([np.zeros(n - 1, np.int64), np.ones(24_000, np.int64), np.full(3_000, 2),
+                            np.full(1_500, 3)])
     hub_d = np.concatenate([others, rng.permutation(np.arange(2, n))[:24_000],
-                            rng.permutation(np.arange(3, n))[:3_000]])
+                            rng.permutation(np.arange(3, n))[:3_000], rng.permutation(np.arange(4, n))[:1_500]])
     flip = rng.random(hub_s.size) < 0.5  # both arc directions occur
     s = np.where(flip, hub_d, hub_s)
     d = np.where(flip, hub_s, hub_d)
-    bs = rng.integers(3, n, 150_000)
-    bd = rng.integers(3, n, 150_000)
+    bs = rng.integers(4, n, 150_000)
+    bd = rng.integers(4, n, 150_000)
     keep = bs != bd
     s = np.concatenate([s, bs[keep]])
     d = np.concatenate([d, bd[keep]])
@@ -730,7 +732,7 @@ def test_triangle_updates_around_hubs():
         pick = arcs[rng.choice(len(arcs), b, replace=False)]  # hub-biased: most arcs touch a hub
         p.delete(pick[:, 0], pick[:, 1])
         p.check_tc()
-        ins_s = np.concatenate([np.zeros(b // 2, np.int64), rng.integers(3, n, b // 2)])
+        ins_s = np.concatenate([np.zeros(b // 2, np.int64), rng.integers(4, n, b // 2)])
         ins_d = rng.integers(1, n, b)
         ik = np.unique(ins_s[ins_s != ins_d] * n + ins_d[ins_s != ins_d])  # no in-batch duplicates
         p.insert(ik // n, ik % n, np.full(ik.size, 3))
