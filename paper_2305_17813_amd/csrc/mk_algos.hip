@@ -852,15 +852,20 @@ __device__ inline uint32_t tc_walked(const DView& U, uint32_t x, uint32_t y) {
   return tc_walk_u(U, u, v) ? u : v;
 }
 
-// A vertex with more than kTcHubDeg neighbours and at least kTcHubEdges batch edges is a hub.
+// A vertex with more than kTcHubDeg neighbours and at least kTcHubEdges batch edges, or with
+// more than kTcHubBig neighbours, is a hub.  (A large vertex with one batch edge would
+// otherwise leave a whole walk of thousands of slabs to one 16-lane group, the tail of a
+// small batch.)
 // The S1 terms of the batch edges whose looked-up end is a hub, and the S2 terms of every
 // batch arc leaving a hub, are counted by k_tc_hub, which loads the hub's neighbourhood into
-// an LDS hash set once for all of them (a hub with fewer batch edges costs less by probing).
+// an LDS hash set once for all of them (a smaller vertex with few batch edges costs less by
+// probing).
 // Every other term is counted by k_tc_batch, one group per batch arc.
 constexpr uint32_t kTcHubDeg = 512;
 constexpr uint32_t kTcHubEdges = 4;
+constexpr uint32_t kTcHubBig = 2048;
 __device__ inline bool tc_is_hub(const DView& U, uint32_t b, uint32_t batch_deg) {
-  return U.deg[b] > kTcHubDeg && batch_deg >= kTcHubEdges;
+  return U.deg[b] > kTcHubDeg && (batch_deg >= kTcHubEdges || U.deg[b] > kTcHubBig);
 }
 
 // S1, S2 and S3 of the batch identity, one group per batch arc (u, v):

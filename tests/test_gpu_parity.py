@@ -706,7 +706,8 @@ def test_triangle_updates_around_hubs():
     """Triangle counts after batches whose edges touch hubs of 1,500, 3,000, 24,000 and 49,999
     neighbours: the batch-identity sum S1 of those edges runs through LDS hash sets of the hub
     neighbourhoods: the small-hub class (one 32 KiB set) for the first, the large class in 1,
-    3 and 5 hash passes for the others; every count equals the oracle's."""
+    3 and 5 hash passes for the others, also for a batch of two edges of the 3,000-neighbour
+    hub (a hub by its degree alone); every count equals the oracle's."""
     say("case: triangle updates around hubs")
     n = 50_000
     rng = np.random.default_rng(17)
@@ -739,3 +740,9 @@ def test_triangle_updates_around_hubs():
         p.check_tc()
         p.insert(pick[:, 0], pick[:, 1], np.full(b, 5))  # the deleted arcs come back
         p.check_tc()
+    # two batch edges of the 3,000-neighbour hub: a hub by its degree alone
+    two = arcs[(arcs[:, 0] == 2) | (arcs[:, 1] == 2)][:2]
+    p.delete(two[:, 0], two[:, 1])
+    p.check_tc()
+    p.insert(two[:, 0], two[:, 1], np.full(2, 7))
+    p.check_tc()
