@@ -86,8 +86,13 @@ __global__ void k_wcc_init(uint32_t* P, uint32_t nv) {
 // Static WCC: union over every arc.  A neighbour whose parent already is u's root (as
 // found once per vertex; a stale root only means an older member of the same component)
 // is skipped without a union, and a lane issues the parent loads of a whole slab together.
+//
+// With `big` set (the sampled static WCC below), a vertex whose root is *big is skipped: its
+// arcs are left to their other ends, which then walk both directions (the undirected view).
 __global__ void __launch_bounds__(kBlock) k_wcc_all(DView F, uint32_t* P, uint32_t nv,
-                                                    const uint32_t* heavy, const uint32_t* nheavy) {
+                                                    const uint32_t* heavy, const uint32_t* nheavy,
+                                                    const uint32_t* big) {
+  const uint32_t skip = big ? *big : kInvalid;
   const uint32_t g0 = (blockIdx.x * kBlock + threadIdx.x) / kGroup;
   const uint32_t ng = gridDim.x * kGroupsPerBlock;
   auto body = [&](uint32_t u, uint32_t ru, uint64_t x, bool data) {
@@ -98,6 +103,7 @@ __global__ void __launch_bounds__(kBlock) k_wcc_all(DView F, uint32_t* P, uint32
   for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < nv; u += gridDim.x * blockDim.x) {
     if (F.nbk[u] != 1 || F.deg[u] == 0) continue;
     const uint32_t ru = uf_find(P, u);
+    if (ru == skip) continue;
     Slab sl;
     uint32_t t = u;
     while (true) {
@@ -119,14 +125,73 @@ __global__ void __launch_bounds__(kBlock) k_wcc_all(DView F, uint32_t* P, uint32
     const uint32_t nb = F.nbk[u];
     if (nb == 1 || nb > kHeavyBuckets || F.deg[u] == 0) continue;
     const uint32_t ru = uf_find(P, u);
+    if (ru == skip) continue;
     for_each_slab(F, u, [&](uint64_t x, bool data) { body(u, ru, x, data); });
   }
   const uint32_t nh = *nheavy, gib = threadIdx.x / kGroup;
   for (uint32_t j = blockIdx.x; j < nh; j += gridDim.x) {
     const uint32_t u = heavy[j];
     const uint32_t ru = uf_find(P, u);
+    if (ru == skip) continue;
     for_each_slab_strided(F, u, gib, kGroupsPerBlock, [&](uint64_t x, bool data) { body(u, ru, x, data); });
   }
+}
+
+// Sampled static WCC (after the subgraph-sampling method of Sutton, Ben-Nun and Barak,
+// "Optimizing parallel graph connectivity computation via subgraph sampling", IPDPS 2018).
+// First every vertex points its parent at the smallest id among itself and the neighbours in
+// its primary slab of the undirected view (at most 15, one 128-byte read, no atomics): a
+// forest whose every edge is an arc, which on a power-law graph already holds most of the
+// giant component in one tree.  After flattening, the most frequent root among kWccSamples
+// sampled vertices is taken as the largest component, and only vertices outside it walk their
+// neighbourhoods (both directions, with unions), so the giant component's arcs are not read.
+// The partition is the plain one (labels are still component minima): every arc with an end
+// outside the largest component is united from that end, and an arc with both ends inside
+// joins nothing new.
+constexpr uint32_t kWccLinks = 2;
+constexpr uint32_t kWccSamples = 1024;
+
+__global__ void k_wcc_link_first(DView U, uint32_t* P, uint32_t nv) {
+  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < nv; u += gridDim.x * blockDim.x) {
+    if (U.deg[u] == 0) continue;
+    const uint64_t* hs = slab_ptr(U, u);
+    const int nd = (uint32_t)(ld_word(hs + 15) >> 32) > 1 ? kKeysPerSlab - 1 : kKeysPerSlab;
+    const uint32_t ru = uf_find(P, u);
+    uint32_t linked = 0;
+    for (int i = 0; i < nd && linked < kWccLinks; ++i) {
+      const uint32_t v = (uint32_t)ld_word(hs + i);
+      if (!valid_key(v)) continue;
+      if (ld_u32(P + v) != ru) uf_union(P, u, v);
+      ++linked;
+    }
+  }
+}
+
+// Every parent made a root (no labels written); a plain walk to the root, as in k_wcc_compress.
+__global__ void k_wcc_flatten(uint32_t* P, uint32_t nv) {
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
+    uint32_t r = v;
+    for (uint32_t p = ld_u32(P + r); p != r; p = ld_u32(P + r)) r = p;
+    __hip_atomic_store(P + v, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// One block of kWccSamples threads: the most frequent root among the sampled vertices
+// (ties: the smaller root) into *big.  Samples are spread over the ids by a Weyl sequence.
+__global__ void __launch_bounds__(kWccSamples) k_wcc_big(const uint32_t* P, uint32_t nv, uint32_t* big) {
+  __shared__ uint32_t root[kWccSamples];
+  __shared__ unsigned long long best;
+  const uint32_t v = (uint32_t)(((uint64_t)threadIdx.x * 0x9E3779B97F4A7C15ull >> 32) % nv);
+  root[threadIdx.x] = ld_u32(P + v);
+  if (threadIdx.x == 0) best = 0;
+  __syncthreads();
+  const uint32_t r = root[threadIdx.x];
+  uint32_t n = 0;
+  for (uint32_t i = 0; i < kWccSamples; ++i) n += root[i] == r;
+  // larger count first, then the smaller root
+  atomicMax(&best, ((unsigned long long)n << 32) | (0xFFFFFFFFu - r));
+  __syncthreads();
+  if (threadIdx.x == 0) *big = 0xFFFFFFFFu - (uint32_t)best;
 }
 
 // IterationScheme2 (section 3.4): one 16-lane group per bucket chain <v, i>, in a
@@ -1520,12 +1585,30 @@ mk_status mk_incr_wcc_scheme(mk_graph* g, uint32_t* d_label, mk_mode mode, mk_wc
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, nh, 1u);
     hipLaunchKernelGGL(k_collect_heavy, dim3(blocks_for(N)), dim3(kBlock), 0, stream,
                        g->view[VF].nbk, N, g->fq[2], nh);
-    hipLaunchKernelGGL(k_wcc_all, dim3(kWalkBlocks), dim3(kBlock), 0, stream, F, P, N, g->fq[2], nh);
+    hipLaunchKernelGGL(k_wcc_all, dim3(kWalkBlocks), dim3(kBlock), 0, stream, F, P, N, g->fq[2], nh,
+                       nullptr);
     return MK_OK;
+  };
+  // the sampled static WCC: needs the undirected view (both directions of a skipped arc)
+  auto sampled = [&]() {
+    const DView U = g->view[VU].d;
+    uint32_t* nh = &g->ctr->n_heavy_wcc;
+    hipLaunchKernelGGL(k_wcc_link_first, dim3(blocks_for(N)), dim3(kBlock), 0, stream, U, P, N);
+    hipLaunchKernelGGL(k_wcc_flatten, dim3(blocks_for(N)), dim3(kBlock), 0, stream, P, N);
+    hipLaunchKernelGGL(k_wcc_big, dim3(1), dim3(kWccSamples), 0, stream, P, N, &g->ctr->wcc_big);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, nh, 1u);
+    hipLaunchKernelGGL(k_collect_heavy, dim3(blocks_for(N)), dim3(kBlock), 0, stream,
+                       g->view[VU].nbk, N, g->fq[2], nh);
+    hipLaunchKernelGGL(k_wcc_all, dim3(kWalkBlocks), dim3(kBlock), 0, stream, U, P, N, g->fq[2], nh,
+                       &g->ctr->wcc_big);
   };
   if (full) {
     hipLaunchKernelGGL(k_wcc_init, dim3(blocks_for(N)), dim3(kBlock), 0, stream, P, N);
-    if (mk_status st = all_arcs(); st != MK_OK) return st;
+    if (g->view[VU].on && g->iter_scheme != MK_ITER_SCHEME2 && N > 0) {
+      sampled();
+    } else if (mk_status st = all_arcs(); st != MK_OK) {
+      return st;
+    }
     if (scheme == MK_WCC_UPDATE)
       hipLaunchKernelGGL(k_mark_all, dim3(grid_for_groups(std::min<uint64_t>(g->view[VF].n_head, 1u << 20))),
                          dim3(kBlock), 0, stream, F, g->upd_mark, g->view[VF].n_head, N);

@@ -66,6 +66,7 @@ struct Counters {          // device-side scalars, one 4 KiB block
   uint32_t tc_work;        // next hub work item of the triangle batch update
   uint32_t n_listed_light; // vertices listed for an incremental WCC pass: up to 16 buckets,
   uint32_t n_listed_heavy; //   and more (these two are cleared together)
+  uint32_t wcc_big;        // root of the sampled largest component of a static WCC
   unsigned long long tc_s[3];  // S1, S2, S3 of the triangle batch identity
   unsigned long long tc_total; // current triangle count
   unsigned long long u64tmp[4];

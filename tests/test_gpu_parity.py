@@ -511,6 +511,42 @@ def test_wcc_schemes_agree(scheme, lf):
         p.g.wcc(scheme=4)
 
 
+@pytest.mark.parametrize("lf", [0.7, 0.0])
+def test_sampled_static_wcc_with_all_views(lf):
+    """The static WCC of a graph with the undirected view (first unions from each primary
+    slab, the most frequent sampled root taken as the largest component, whose vertices then
+    skip their arcs) gives the oracle's labels: two equally large components, a low id reached
+    only through an in-arc, a low id that joins a large component through a vertex outside it,
+    small components and many isolated vertices; again after a delete batch that cuts one
+    large component in two at its only bridge, and after one that isolates the low ids."""
+    say(f"case: sampled static WCC, load factor {lf}")
+    rng = np.random.default_rng(91)
+    n = 20_000
+
+    def blob(lo, hi, m):
+        a, b = rng.integers(lo, hi, m), rng.integers(lo, hi, m)
+        return a[a != b], b[a != b]
+
+    a1s, a1d = blob(10_000, 12_500, 12_000)
+    a2s, a2d = blob(12_500, 15_000, 12_000)
+    bs, bd = blob(15_000, 20_000, 24_000)
+    src = np.concatenate([a1s, a2s, bs, [12_000, 12_600, 2, 100, 101, 500]])
+    dst = np.concatenate([a1d, a2d, bd, [12_600, 3, 15_500, 101, 102, 2]])
+    # 12000 -> 12600 is the only bridge between the halves of A; 3 has only an in-arc (from
+    # 12600); 2 joins B and 500 hangs off 2; 100-101-102 is a small chain
+    key = np.unique(src.astype(np.int64) * n + dst)
+    src, dst = key // n, key % n
+    p = Pair(n, src, dst, rng.integers(1, 100, src.size), views=7, load_factor=lf)
+    p.check_all(algos=("wcc",))
+    p.delete(np.array([12_000]), np.array([12_600]))
+    p.check_all(algos=("wcc",))
+    p.delete(np.array([12_600, 2]), np.array([3, 15_500]))
+    p.check_all(algos=("wcc",))
+    p.insert(np.array([3, 12_000]), np.array([15_000, 12_600]), np.array([1, 1]))
+    p.check_all(algos=("wcc",))
+    p.check_wcc(native.RECOMPUTE)
+
+
 @pytest.mark.parametrize("top_down_only", [False, True])
 def test_bfs_levels_distance_only(top_down_only):
     """The distance-only, direction-optimizing BFS gives the oracle's levels: R-MAT from the
