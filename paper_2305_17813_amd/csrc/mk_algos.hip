@@ -921,11 +921,11 @@ __device__ inline uint32_t tc_walked(const DView& U, uint32_t x, uint32_t y) {
 // more than kTcHubBig neighbours, is a hub.  (A large vertex with one batch edge would
 // otherwise leave a whole walk of thousands of slabs to one 16-lane group, the tail of a
 // small batch.)
-// The S1 terms of the batch edges whose looked-up end is a hub, and the S2 terms of every
-// batch arc leaving a hub, are counted by k_tc_hub, which loads the hub's neighbourhood into
-// an LDS hash set once for all of them (a smaller vertex with few batch edges costs less by
-// probing).
-// Every other term is counted by k_tc_batch, one group per batch arc.
+// The S1 terms of the batch edges whose looked-up end is a hub, the S2 terms of every batch
+// arc leaving a hub and of every arc into a hub from its walked end, are counted by k_tc_hub,
+// which loads the hub's neighbourhood into an LDS hash set once for all of them (a smaller
+// vertex with few batch edges costs less by probing).  Every other term is counted by
+// k_tc_batch, one group per batch arc.
 constexpr uint32_t kTcHubDeg = 512;
 constexpr uint32_t kTcHubEdges = 4;
 constexpr uint32_t kTcHubBig = 2048;
@@ -939,7 +939,7 @@ __device__ inline bool tc_is_hub(const DView& U, uint32_t b, uint32_t batch_deg)
 // canonical direction u < v, counted twice).  The terms k_tc_hub counts are skipped.
 __global__ void __launch_bounds__(kBlock) k_tc_batch(DView U, const uint64_t* keys, uint64_t nk,
                                                      const uint32_t* seg_lo, const uint32_t* seg_hi,
-                                                     uint32_t nv, unsigned long long* S) {
+                                                     uint32_t nv, bool s2in, unsigned long long* S) {
   const uint64_t g0 = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kGroup;
   const uint64_t ng = (uint64_t)gridDim.x * kGroupsPerBlock;
   uint64_t s1 = 0, s2 = 0, s3 = 0;
@@ -964,6 +964,8 @@ __global__ void __launch_bounds__(kBlock) k_tc_batch(DView U, const uint64_t* ke
     uint64_t c2 = 0, c3 = 0;
     if (tc_is_hub(U, u, (uint32_t)(uhi - ulo))) {
       // S2 of a hub's directions is counted by k_tc_hub against its LDS sets
+    } else if (s2in && tc_is_hub(U, v, (uint32_t)(vhi - vlo)) && a == u) {
+      // so is S2 of an arc into a hub from the end walked against the hub's set
     } else if (2ull * U.deg[u] < vhi - vlo) {
       // S2 from the smaller side: walk N_G(u), look each key up in v's sorted segment
       for_each_slab(U, u, [&](uint64_t w, bool data) {
@@ -1011,7 +1013,8 @@ __global__ void __launch_bounds__(kBlock) k_tc_batch(DView U, const uint64_t* ke
 // chunk c is a run of entries of b's segment.  An item loads its part of N(b) into an LDS
 // hash set, then reads the packed list of every partner a in its chunk (spread over the
 // whole block) and looks each key of the pass up (S1); it also looks up, for the arcs
-// (b, a), every entry of a's batch segment that falls in the pass (S2).
+// (b, a), every entry of a's batch segment that falls in the pass (S2), and, with b's own
+// batch segment in the set as tagged keys, counts S2 of the arcs (a, b) on the same lookups.
 //
 // The set is bucketized: 4 slots (16 bytes, one LDS read) per bucket, linear probing over
 // buckets.  At the set's load factor a lookup mostly reads one bucket, so the lanes of a wave
@@ -1037,7 +1040,13 @@ __device__ inline bool tc_small_hub(const DView& U, uint32_t b) { return U.deg[b
 __device__ inline uint32_t tc_part(uint32_t k, uint32_t P) {
   return (uint32_t)(((uint64_t)(k * 0x85EBCA6Bu) * P) >> 32);
 }
-__device__ inline uint32_t tc_bucket(uint32_t k, uint32_t bmask) { return (k * 0x9E3779B1u) >> 9 & bmask; }
+// Keys of b's batch segment share b's set, tagged with the top bit (vertex ids stay below
+// 2^31 when the tag is in use); the bucket hash ignores that bit, so a key and its tagged
+// copy share a home bucket and one probe sees both.
+constexpr uint32_t kTcTag = 0x80000000u;
+__device__ inline uint32_t tc_bucket(uint32_t k, uint32_t bmask) {
+  return ((k & ~kTcTag) * 0x9E3779B1u) >> 9 & bmask;
+}
 template <bool Small>
 __device__ inline uint32_t tc_hub_passes(uint32_t deg) {
   return max(1u, (deg + HubClass<Small>::kKeys - 1) / HubClass<Small>::kKeys);
@@ -1069,6 +1078,20 @@ __device__ inline bool lds_has_from(const uint32_t* tab, uint32_t bmask, uint32_
 }
 __device__ inline bool lds_has(const uint32_t* tab, uint32_t bmask, uint32_t key) {
   return lds_has_from(tab, bmask, key, tc_bucket(key, bmask));
+}
+// Whether `key` (bit 0) and `tkey` (bit 1) are in the set, probing from bucket h on: both
+// lie before the first bucket with an empty slot.
+__device__ inline uint32_t lds_has2_from(const uint32_t* tab, uint32_t bmask, uint32_t key, uint32_t tkey,
+                                         uint32_t h) {
+  uint32_t f = 0;
+  for (uint32_t n = 0; n <= bmask; ++n) {
+    const uint4 q = reinterpret_cast<const uint4*>(tab)[h];
+    if (q.x == key || q.y == key || q.z == key || q.w == key) f |= 1u;
+    if (q.x == tkey || q.y == tkey || q.z == tkey || q.w == tkey) f |= 2u;
+    if (q.x == kInvalid || q.y == kInvalid || q.z == kInvalid || q.w == kInvalid) break;
+    h = (h + 1) & bmask;
+  }
+  return f;
 }
 
 // The last position i < n with off[i] <= t, for a non-decreasing off with off[0] <= t,
@@ -1216,7 +1239,7 @@ __global__ void __launch_bounds__(HubClass<Small>::kThreads) k_tc_hub(DView U, c
                                                          const uint32_t* cnt,
                                                          const uint32_t* off, uint32_t* next,
                                                          const uint32_t* list, const uint64_t* loff,
-                                                         unsigned long long* S) {
+                                                         bool s2in, unsigned long long* S) {
   using H = HubClass<Small>;
   __shared__ uint4 tab4[H::kSlots / 4];
   uint32_t* tab = reinterpret_cast<uint32_t*>(tab4);
@@ -1258,7 +1281,8 @@ __global__ void __launch_bounds__(HubClass<Small>::kThreads) k_tc_hub(DView U, c
     const uint32_t np = __builtin_amdgcn_readfirstlane(item_s[5]);
     // buckets: a power of two, at least 3.2 slots per key of the pass, within the LDS array (a
     // key's first bucket is then rarely full, and a probe rarely reads a second one)
-    const uint32_t want = (U.deg[b] + P - 1) / P;
+    const uint32_t blo = seg_lo[b], bhi = seg_hi[b];  // b's batch segment: N_B(b)
+    const uint32_t want = (U.deg[b] + P - 1) / P + (s2in ? (bhi - blo + P - 1) / P : 0u);
     uint32_t slots = 64;
     while (slots < H::kSlots && slots * 5 < want * 16) slots <<= 1;
     const uint32_t bmask = __builtin_amdgcn_readfirstlane(slots / 4 - 1);
@@ -1271,7 +1295,10 @@ __global__ void __launch_bounds__(HubClass<Small>::kThreads) k_tc_hub(DView U, c
       pbase[j] = len ? loff[a] : 0;
       plen[j] = len;
       pslo[j] = seg_lo[a];
-      pre2[j] = seg_hi[a] - seg_lo[a];  // segment length, scanned below
+      // S2 of the arc (b, a), over a's segment (its length, scanned below); not when a is a
+      // hub that walks b against its own set: a's items count that arc with b's tagged keys
+      const bool by_a = s2in && tc_walked(U, a, b) == b && tc_is_hub(U, a, seg_hi[a] - seg_lo[a]);
+      pre2[j] = by_a ? 0u : seg_hi[a] - seg_lo[a];
     }
     if (threadIdx.x == 64) {  // b's bucket count and first extra head slab
       const uint64_t* ps = slab_ptr(U, b);
@@ -1350,6 +1377,12 @@ __global__ void __launch_bounds__(HubClass<Small>::kThreads) k_tc_hub(DView U, c
         nd = kKeysPerSlab;
       }
     }
+    if (s2in) {  // and this pass's keys of N_B(b), tagged
+      for (uint32_t j = blo + threadIdx.x; j < bhi; j += H::kThreads) {
+        const uint32_t x = (uint32_t)keys[j];
+        if (tc_part(x, P) == p && !lds_insert(tab, bmask, x | kTcTag)) full = 1;
+      }
+    }
     __syncthreads();
     const bool in_lds = full == 0;
     const Table tb{b, nbb, xbb};
@@ -1423,13 +1456,16 @@ __global__ void __launch_bounds__(HubClass<Small>::kThreads) k_tc_hub(DView U, c
 #pragma unroll
         for (uint32_t k = 0; k < kTcHubRun; ++k) cn += nx[k] <= t0 + kTcHubRun;
         j = min(j + cn, nq - 1);
-        hits += probe(key);
+        const uint64_t f = probe(key);  // S1 matches, and S2 matches << 32
+        hits += (uint32_t)f;
+        h2 += f >> 32;
       }
     };
     // keys of this pass: all of them when b takes one pass
     auto wanted = [&](uint32_t x) { return x != kInvalid && x != b && (P == 1 || tc_part(x, P) == p); };
+    // With s2in, a key x of N(a) found tagged counts S2 of the arc (a, b): x in N_B(b).
     if (in_lds) {
-      runs([&](const uint32_t (&key)[kTcHubRun]) -> uint32_t {
+      runs([&](const uint32_t (&key)[kTcHubRun]) -> uint64_t {
         uint32_t h[kTcHubRun];
         uint4 q4[kTcHubRun];
 #pragma unroll
@@ -1437,16 +1473,18 @@ __global__ void __launch_bounds__(HubClass<Small>::kThreads) k_tc_hub(DView U, c
           h[r] = tc_bucket(key[r], bmask);
           q4[r] = tab4[h[r]];
         }
-        uint32_t n = 0, pend = 0;
+        uint32_t n = 0, n2 = 0, pend = 0, got = 0;
 #pragma unroll
         for (uint32_t r = 0; r < kTcHubRun; ++r) {
-          const uint32_t x = key[r];
+          const uint32_t x = key[r], tx = s2in ? x | kTcTag : kInvalid;
           if (!wanted(x)) continue;
-          if (q4[r].x == x || q4[r].y == x || q4[r].z == x || q4[r].w == x) {
-            ++n;
-          } else if (q4[r].x != kInvalid && q4[r].y != kInvalid && q4[r].z != kInvalid && q4[r].w != kInvalid) {
-            pend |= 1u << r;
-          }
+          const bool f1 = q4[r].x == x || q4[r].y == x || q4[r].z == x || q4[r].w == x;
+          const bool f2 = s2in && (q4[r].x == tx || q4[r].y == tx || q4[r].z == tx || q4[r].w == tx);
+          n += f1;
+          n2 += f2;
+          got |= (f1 ? 1u : 0u) << (2 * r) | (f2 ? 2u : 0u) << (2 * r);
+          const bool fullb = q4[r].x != kInvalid && q4[r].y != kInvalid && q4[r].z != kInvalid && q4[r].w != kInvalid;
+          if (fullb && (!f1 || (s2in && !f2))) pend |= 1u << r;  // a full first bucket
         }
         while (pend) {  // keys whose first bucket was full, all runs of the wave at once
           const uint32_t r = __builtin_ctz(pend);
@@ -1454,18 +1492,31 @@ __global__ void __launch_bounds__(HubClass<Small>::kThreads) k_tc_hub(DView U, c
           uint32_t x = key[0], hh = h[0];
 #pragma unroll
           for (uint32_t k = 1; k < kTcHubRun; ++k)
-            if (k == r) { x = key[k]; hh = h[k]; }
-          n += lds_has_from(tab, bmask, x, (hh + 1) & bmask);
+            if (k == r) {
+              x = key[k];
+              hh = h[k];
+            }
+          const uint32_t f = lds_has2_from(tab, bmask, x, s2in ? x | kTcTag : kInvalid, (hh + 1) & bmask) &
+                             ~(got >> (2 * r));
+          n += f & 1u;
+          n2 += s2in ? (f >> 1) & 1u : 0u;
         }
-        return n;
+        return ((uint64_t)n2 << 32) | n;
       });
-    } else {  // the pass overflowed its set: look the keys up in b's slabs
-      runs([&](const uint32_t (&key)[kTcHubRun]) -> uint32_t {
-        uint32_t n = 0;
+    } else {  // the pass overflowed its set: look the keys up in b's slabs and b's segment
+      runs([&](const uint32_t (&key)[kTcHubRun]) -> uint64_t {
+        uint32_t n = 0, n2 = 0;
 #pragma unroll 1
-        for (uint32_t r = 0; r < kTcHubRun; ++r)
-          if (wanted(key[r])) n += lane_has(U, tb, key[r]);
-        return n;
+        for (uint32_t r = 0; r < kTcHubRun; ++r) {
+          if (!wanted(key[r])) continue;
+          n += lane_has(U, tb, key[r]);
+          if (s2in) {
+            const uint64_t want_k = ((uint64_t)b << 32) | key[r];
+            const uint64_t q = lower_bound_u64(keys + blo, bhi - blo, want_k);
+            n2 += q < bhi - blo && keys[blo + q] == want_k;
+          }
+        }
+        return ((uint64_t)n2 << 32) | n;
       });
     }
     __syncthreads();  // the set and partner arrays are rebuilt by the next item
@@ -1803,8 +1854,11 @@ mk_status mk_count_triangles(mk_graph* g, uint64_t* d_count, mk_mode mode, hipSt
     // segment bounds per source vertex (scratch: two traversal queues, unused here)
     hipLaunchKernelGGL(k_tc_segs, dim3(blocks_for(nk)), dim3(kBlock), 0, stream, g->tc_keys[1], nk, N,
                        g->fq[4], g->fq[5]);
+    // S2 of arcs into hubs goes through the hubs' sets when ids leave the tag bit free
+    const bool s2in = N <= 0x7FFFFFFFu;
     hipLaunchKernelGGL(k_tc_batch, dim3(grid_for_groups(std::min<uint64_t>(nk, 1u << 20))),
-                       dim3(kBlock), 0, stream, U, g->tc_keys[1], nk, g->fq[4], g->fq[5], N, g->ctr->tc_s);
+                       dim3(kBlock), 0, stream, U, g->tc_keys[1], nk, g->fq[4], g->fq[5], N, s2in,
+                       g->ctr->tc_s);
     // hub edges: work items numbered by an exclusive scan over the key
     // positions, in the sort's input buffer (free after the sort; 2 * nk u32 fit in it)
     uint32_t* hcnt = reinterpret_cast<uint32_t*>(g->tc_keys[0]);
@@ -1839,7 +1893,7 @@ mk_status mk_count_triangles(mk_graph* g, uint64_t* d_count, mk_mode mode, hipSt
         return false;
       hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, &g->ctr->tc_work, 1u);
       hipLaunchKernelGGL(k_tc_hub<kSmall>, dim3(H::kBlocks), dim3(H::kThreads), 0, stream, U, g->tc_keys[1], nk,
-                         g->fq[4], g->fq[5], hcnt, hoff, &g->ctr->tc_work, g->tc_list, g->tc_off,
+                         g->fq[4], g->fq[5], hcnt, hoff, &g->ctr->tc_work, g->tc_list, g->tc_off, s2in,
                          g->ctr->tc_s);
       return true;
     };
