@@ -398,17 +398,23 @@ __global__ void k_pr_fill(float* x, uint32_t nv, float v) {
 
 // Contribution per vertex C[u] = PR[u] / out[u] (the FindContributionPerVertex kernel),
 // plus the FP64 sum of the ranks of zero-out-degree vertices (FindTeleportProb).
+//
+// With `cr` (the packing iteration), the contribution goes beside the vertex's hot-first rank,
+// cr[v] = <rank[v], contribution bits>, so the packing pull reads both with one 8-byte load.
 __global__ void __launch_bounds__(kBlock) k_pr_contrib(const float* __restrict__ x,
                                                        const uint32_t* __restrict__ outdeg,
                                                        float* __restrict__ c, uint32_t nv,
-                                                       double* dpart, const uint32_t* state) {
+                                                       double* dpart, const uint32_t* state,
+                                                       const uint32_t* __restrict__ rank, uint2* __restrict__ cr) {
   __shared__ double lds[kBlock / 64];
   if (state[0]) return;
   double local = 0;
   for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
     const uint32_t o = outdeg[v];
     const float xv = x[v];
-    c[v] = o ? xv / (float)o : 0.f;
+    const float cv = o ? xv / (float)o : 0.f;
+    if (cr) cr[v] = make_uint2(rank[v], __float_as_uint(cv));
+    else c[v] = cv;
     if (!o) local += xv;
   }
   const double s = block_sum(local, lds);
@@ -448,11 +454,21 @@ __global__ void __launch_bounds__(kBlock) k_pr_gather(DView R, const float* __re
                                                       const uint32_t* hcnt, const uint32_t* hoff,
                                                       double* hacc, const uint32_t* state,
                                                       uint32_t* __restrict__ list, const uint32_t* __restrict__ off,
-                                                      uint32_t* cur, const uint32_t* __restrict__ rank) {
+                                                      uint32_t* cur, const uint2* __restrict__ cr) {
   __shared__ double lds[kBlock / 64];
   if (state[0]) return;
   const double base = (1.0 - (double)damping) / nv + (double)damping * (*dang) / nv;
   double local = 0;
+  // u's contribution, and with `list` its hot-first rank r (both from one load of cr[u])
+  auto term = [&](uint32_t u, uint32_t& r) -> float {
+    if (list) {
+      const uint2 q = cr[u];
+      r = q.x;
+      return __uint_as_float(q.y);
+    }
+    r = 0;
+    return c[u];
+  };
   // single-bucket vertices (most of a power-law graph): one lane per vertex, so a wave keeps
   // 64 slab reads and their gathers in flight
   for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
@@ -470,8 +486,9 @@ __global__ void __launch_bounds__(kBlock) k_pr_gather(DView R, const float* __re
         for (int j = 0; j < kKeysPerSlab; ++j) {
           const uint32_t u = (uint32_t)sl.w[j];
           if (valid_key(u)) {
-            s += (double)c[u];
-            if (out && n < dv) out[n] = rank[u];
+            uint32_t r;
+            s += (double)term(u, r);
+            if (out && n < dv) out[n] = r;
             ++n;
           }
         }
@@ -498,10 +515,10 @@ __global__ void __launch_bounds__(kBlock) k_pr_gather(DView R, const float* __re
     uint32_t* out = list ? list + off[v] : nullptr;
     const uint32_t dv = list ? R.deg[v] : 0u;
     uint32_t n = 0;  // keys packed so far (the same in every lane of the group)
-    auto pack = [&](bool valid, uint32_t u) {
+    auto pack = [&](bool valid, uint32_t r) {
       const uint32_t m = gballot(valid);
       const uint32_t at = n + (uint32_t)__popc(m & ((1u << gl) - 1u));
-      if (valid && at < dv) out[at] = rank[u];
+      if (valid && at < dv) out[at] = r;
       n += (uint32_t)__popc(m);
     };
     for (uint32_t b0 = 0; b0 < nb; b0 += kPrBatch) {
@@ -515,8 +532,9 @@ __global__ void __launch_bounds__(kBlock) k_pr_gather(DView R, const float* __re
       for (uint32_t j = 0; j < kPrBatch; ++j) {
         const uint32_t u = (uint32_t)hw[j];
         const bool data = gl < (b0 + j == 0 ? kKeysPerSlab - 1 : kKeysPerSlab);
-        if (data && valid_key(u)) s += (double)c[u];
-        if (out) pack(data && valid_key(u), u);
+        uint32_t r = 0;
+        if (data && valid_key(u)) s += (double)term(u, r);
+        if (out) pack(data && valid_key(u), r);
       }
 #pragma unroll
       for (uint32_t j = 0; j < kPrBatch; ++j) {  // chained slabs after a full head slab
@@ -525,8 +543,9 @@ __global__ void __launch_bounds__(kBlock) k_pr_gather(DView R, const float* __re
         if (next == kInvalid) continue;
         walk_chain(R, next, ld_word(slab_ptr(R, next) + gl), kKeysPerSlab, [&](uint64_t w, bool data) {
           const uint32_t u = (uint32_t)w;
-          if (data && valid_key(u)) s += (double)c[u];
-          if (out) pack(data && valid_key(u), u);
+          uint32_t r = 0;
+          if (data && valid_key(u)) s += (double)term(u, r);
+          if (out) pack(data && valid_key(u), r);
         });
       }
     }
@@ -556,13 +575,14 @@ __global__ void __launch_bounds__(kBlock) k_pr_gather(DView R, const float* __re
       for_each_bucket_range(R, v, b0, b0 + kPrChunk, [&](uint64_t w, bool data) {
         const uint32_t u = (uint32_t)w;
         const bool valid = data && valid_key(u);
-        if (valid) s += (double)c[u];
+        uint32_t r = 0;
+        if (valid) s += (double)term(u, r);
         if (list) {  // room for this slab's keys in v's segment, one reservation per slab
           const uint32_t m = gballot(valid);
           uint32_t at = 0;
           if (glane() == 0 && m) at = atomicAdd(cur + lo, (uint32_t)__popc(m));
           at = gbcast(at, 0) + (uint32_t)__popc(m & ((1u << glane()) - 1u));
-          if (valid && at < end) list[at] = rank[u];
+          if (valid && at < end) list[at] = r;
         }
       });
       s = gsum(s);
@@ -1582,7 +1602,7 @@ mk_status pagerank_scheme2(mk_graph* g, float damping, double tol_l1, uint32_t m
       float* y = buf[(it + 1) & 1];
       double* dang = &g->ctr->pr_acc[2 * slot];
       hipLaunchKernelGGL(k_pr_contrib, dim3(cb), dim3(kBlock), 0, stream, x, g->view[VF].d.deg, g->pr_c,
-                         N, g->pr_part, g->ctr->pr_state);
+                         N, g->pr_part, g->ctr->pr_state, nullptr, nullptr);
       hipLaunchKernelGGL(k_pr_sum, dim3(1), dim3(kBlock), 0, stream, g->pr_part, cb, dang, g->ctr->pr_state);
       hipLaunchKernelGGL(k_pr_gather_s2, dim3(kWalkBlocks), dim3(kBlock), 0, stream, vh.d, g->pr_c,
                          vh.pair_v, vh.pair_i, (uint32_t)vh.n_head, N, g->pr_pair, g->ctr->pr_state);
@@ -1783,9 +1803,10 @@ mk_status mk_incr_pagerank(mk_graph* g, float damping, double tol_l1, uint32_t m
       if (packed && it > 0)
         hipLaunchKernelGGL(k_pr_contrib_perm, dim3(cb), dim3(kBlock), 0, stream, x, g->view[VF].d.deg,
                            g->pr_perm, g->pr_cp, N, g->pr_part, g->ctr->pr_state);
-      else
+      else  // the first iteration; with packing, <rank, contribution> pairs
         hipLaunchKernelGGL(k_pr_contrib, dim3(cb), dim3(kBlock), 0, stream, x, g->view[VF].d.deg, g->pr_c,
-                           N, g->pr_part, g->ctr->pr_state);
+                           N, g->pr_part, g->ctr->pr_state, packed ? g->pr_rank : nullptr,
+                           packed ? reinterpret_cast<uint2*>(g->pr_cr) : nullptr);
       hipLaunchKernelGGL(k_pr_sum, dim3(1), dim3(kBlock), 0, stream, g->pr_part, cb, dang, g->ctr->pr_state);
       if (packed && it > 0)
         hipLaunchKernelGGL(k_pr_pull, dim3(kWalkBlocks), dim3(kBlock), 0, stream, Rd.nbk, Rd.deg, g->pr_off,
@@ -1794,7 +1815,8 @@ mk_status mk_incr_pagerank(mk_graph* g, float damping, double tol_l1, uint32_t m
       else
         hipLaunchKernelGGL(k_pr_gather, dim3(kWalkBlocks), dim3(kBlock), 0, stream, Rd, g->pr_c, x, y, N,
                            damping, dang, dpart, g->heavy_rev, nh, hcnt, hoff, hacc, g->ctr->pr_state,
-                           packed ? g->pr_list : nullptr, g->pr_off, pcur, g->pr_rank);
+                           packed ? g->pr_list : nullptr, g->pr_off, pcur,
+                           reinterpret_cast<const uint2*>(g->pr_cr));
       hipLaunchKernelGGL(k_pr_heavy_final, dim3(hb), dim3(kBlock), 0, stream, g->heavy_rev, nh, hacc, x, y,
                          N, damping, dang, dpart + kWalkBlocks, g->ctr->pr_state);
       hipLaunchKernelGGL(k_pr_check, dim3(1), dim3(kBlock), 0, stream, g->ctr, slot, tol_l1, max_iter, dpart,

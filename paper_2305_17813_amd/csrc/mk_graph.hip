@@ -781,6 +781,7 @@ bool layout(const mk_config* c, uint64_t m, char* base, mk_graph* g, size_t* tot
   uint32_t* proff = hb_rev ? cv.take<uint32_t>((uint64_t)N + 1) : nullptr;
   uint32_t *prperm = nullptr, *prrank = nullptr, *prk0 = nullptr, *prk1 = nullptr, *pridx = nullptr;
   float* prcp = nullptr;
+  uint64_t* prcr = nullptr;
   void* prsort = nullptr;
   size_t prsort_bytes = 0;
   if (hb_rev) {
@@ -790,6 +791,7 @@ bool layout(const mk_config* c, uint64_t m, char* base, mk_graph* g, size_t* tot
     prk1 = cv.take<uint32_t>(N);
     pridx = cv.take<uint32_t>(N);
     prcp = cv.take<float>(N);
+    prcr = cv.take<uint64_t>(N);
     if (rocprim::radix_sort_pairs(nullptr, prsort_bytes, (uint32_t*)nullptr, (uint32_t*)nullptr,
                                   (uint32_t*)nullptr, (uint32_t*)nullptr, (size_t)N, 0, 6) != hipSuccess)
       return false;
@@ -853,6 +855,7 @@ bool layout(const mk_config* c, uint64_t m, char* base, mk_graph* g, size_t* tot
     g->pr_skey[1] = prk1;
     g->pr_sidx = pridx;
     g->pr_cp = prcp;
+    g->pr_cr = prcr;
     g->pr_sort_tmp = prsort;
     g->pr_sort_bytes = prsort_bytes;
     g->upd_mark = umark;

@@ -146,6 +146,7 @@ struct mk_graph {
   uint32_t* pr_skey[2] = {};      // sort keys (out-degree classes) and their sorted copy
   uint32_t* pr_sidx = nullptr;    // 0 .. N-1, the sort's values
   float* pr_cp = nullptr;
+  uint64_t* pr_cr = nullptr;     // packing iteration: <rank, contribution bits> per vertex
   void* pr_sort_tmp = nullptr;
   size_t pr_sort_bytes = 0;
   int iter_scheme = MK_ITER_PACKED;   // how all-vertex walks are scheduled
