@@ -937,10 +937,12 @@ __device__ inline uint32_t tc_walked(const DView& U, uint32_t x, uint32_t y) {
   return tc_walk_u(U, u, v) ? u : v;
 }
 
-// A vertex with more than kTcHubDeg neighbours and at least kTcHubEdges batch edges, or with
-// more than kTcHubBig neighbours, is a hub.  (A large vertex with one batch edge would
-// otherwise leave a whole walk of thousands of slabs to one 16-lane group, the tail of a
-// small batch.)
+// A vertex b with more than kTcHubDeg neighbours and at least kTcHubEdges batch edges is a
+// hub; so is one with more than kTcHubBig neighbours and fewer batch edges when one of its
+// batch partners has more than kTcHubDeg neighbours (that edge's walk would otherwise take
+// hundreds of slabs on one 16-lane group, the tail of a small batch; a large vertex whose few
+// partners are small costs less by probing, the common case after uniform inserts).  Every
+// caller sees b's segment [lo, hi) of the sorted batch keys.
 // The S1 terms of the batch edges whose looked-up end is a hub, the S2 terms of every batch
 // arc leaving a hub and of every arc into a hub from its walked end, are counted by k_tc_hub,
 // which loads the hub's neighbourhood into an LDS hash set once for all of them (a smaller
@@ -949,8 +951,14 @@ __device__ inline uint32_t tc_walked(const DView& U, uint32_t x, uint32_t y) {
 constexpr uint32_t kTcHubDeg = 512;
 constexpr uint32_t kTcHubEdges = 4;
 constexpr uint32_t kTcHubBig = 2048;
-__device__ inline bool tc_is_hub(const DView& U, uint32_t b, uint32_t batch_deg) {
-  return U.deg[b] > kTcHubDeg && (batch_deg >= kTcHubEdges || U.deg[b] > kTcHubBig);
+__device__ inline bool tc_is_hub(const DView& U, uint32_t b, const uint64_t* keys, uint32_t lo, uint32_t hi) {
+  const uint32_t d = U.deg[b];
+  if (d <= kTcHubDeg) return false;
+  if (hi - lo >= kTcHubEdges) return true;
+  if (d <= kTcHubBig) return false;
+  for (uint32_t i = lo; i < hi; ++i)  // fewer than kTcHubEdges entries
+    if (U.deg[(uint32_t)keys[i]] > kTcHubDeg) return true;
+  return false;
 }
 
 // S1, S2 and S3 of the batch identity, one group per batch arc (u, v):
@@ -970,7 +978,7 @@ __global__ void __launch_bounds__(kBlock) k_tc_batch(DView U, const uint64_t* ke
     if (u >= nv) break;  // sentinels sort last
     const bool canon = u < v;
     const uint32_t a = tc_walked(U, u, v), b = a == u ? v : u;
-    const bool hub = tc_is_hub(U, b, seg_hi[b] - seg_lo[b]);
+    const bool hub = tc_is_hub(U, b, keys, seg_lo[b], seg_hi[b]);
     uint64_t c1 = 0;
     if (canon && !hub) c1 = 2 * group_intersect(U, a, b);  // walk the smaller side, probe the other
     // batch neighbourhoods: the segments of v and u in the sorted key list
@@ -982,9 +990,9 @@ __global__ void __launch_bounds__(kBlock) k_tc_batch(DView U, const uint64_t* ke
       return q < hi - lo && keys[lo + q] == want;
     };
     uint64_t c2 = 0, c3 = 0;
-    if (tc_is_hub(U, u, (uint32_t)(uhi - ulo))) {
+    if (tc_is_hub(U, u, keys, (uint32_t)ulo, (uint32_t)uhi)) {
       // S2 of a hub's directions is counted by k_tc_hub against its LDS sets
-    } else if (s2in && tc_is_hub(U, v, (uint32_t)(vhi - vlo)) && a == u) {
+    } else if (s2in && tc_is_hub(U, v, keys, (uint32_t)vlo, (uint32_t)vhi) && a == u) {
       // so is S2 of an arc into a hub from the end walked against the hub's set
     } else if (2ull * U.deg[u] < vhi - vlo) {
       // S2 from the smaller side: walk N_G(u), look each key up in v's sorted segment
@@ -1145,7 +1153,7 @@ __global__ void k_tc_need(DView U, const uint64_t* keys, uint64_t nk, const uint
     const uint64_t key = keys[i];
     const uint32_t b = (uint32_t)(key >> 32), a = (uint32_t)key;
     if (b >= nv) continue;  // sentinels
-    if (tc_is_hub(U, b, seg_hi[b] - seg_lo[b]) && tc_walked(U, a, b) == a) need[a] = 1;
+    if (tc_is_hub(U, b, keys, seg_lo[b], seg_hi[b]) && tc_walked(U, a, b) == a) need[a] = 1;
   }
 }
 
@@ -1243,7 +1251,7 @@ __global__ void k_tc_hub_count(DView U, const uint64_t* keys, uint64_t nk, const
        i += (uint64_t)gridDim.x * blockDim.x) {
     const uint32_t b = (uint32_t)(keys[i] >> 32);
     uint32_t c = 0;
-    if (b < nv && (i == 0 || (uint32_t)(keys[i - 1] >> 32) != b) && tc_is_hub(U, b, seg_hi[b] - (uint32_t)i) &&
+    if (b < nv && (i == 0 || (uint32_t)(keys[i - 1] >> 32) != b) && tc_is_hub(U, b, keys, (uint32_t)i, seg_hi[b]) &&
         tc_small_hub(U, b) == Small) {
       const uint64_t len = seg_hi[b] - i;
       c = tc_hub_passes<Small>(U.deg[b]) * (uint32_t)((len + H::kChunk - 1) / H::kChunk);
@@ -1317,7 +1325,7 @@ __global__ void __launch_bounds__(HubClass<Small>::kThreads) k_tc_hub(DView U, c
       pslo[j] = seg_lo[a];
       // S2 of the arc (b, a), over a's segment (its length, scanned below); not when a is a
       // hub that walks b against its own set: a's items count that arc with b's tagged keys
-      const bool by_a = s2in && tc_walked(U, a, b) == b && tc_is_hub(U, a, seg_hi[a] - seg_lo[a]);
+      const bool by_a = s2in && tc_walked(U, a, b) == b && tc_is_hub(U, a, keys, seg_lo[a], seg_hi[a]);
       pre2[j] = by_a ? 0u : seg_hi[a] - seg_lo[a];
     }
     if (threadIdx.x == 64) {  // b's bucket count and first extra head slab

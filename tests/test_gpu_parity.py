@@ -743,7 +743,8 @@ def test_triangle_updates_around_hubs():
     neighbours: the batch-identity sum S1 of those edges runs through LDS hash sets of the hub
     neighbourhoods: the small-hub class (one 32 KiB set) for the first, the large class in 1,
     3 and 5 hash passes for the others, also for a batch of two edges of the 3,000-neighbour
-    hub (a hub by its degree alone); every count equals the oracle's."""
+    hub, one to the largest hub (a hub by its degree and that partner's); every count equals
+    the oracle's."""
     say("case: triangle updates around hubs")
     n = 50_000
     rng = np.random.default_rng(17)
@@ -776,8 +777,12 @@ def test_triangle_updates_around_hubs():
         p.check_tc()
         p.insert(pick[:, 0], pick[:, 1], np.full(b, 5))  # the deleted arcs come back
         p.check_tc()
-    # two batch edges of the 3,000-neighbour hub: a hub by its degree alone
-    two = arcs[(arcs[:, 0] == 2) | (arcs[:, 1] == 2)][:2]
+    # two batch edges of the 3,000-neighbour hub, one of them to the 49,999-neighbour hub: a
+    # hub by its degree and that large partner, with fewer than 4 batch edges
+    e02 = arcs[((arcs[:, 0] == 0) & (arcs[:, 1] == 2)) | ((arcs[:, 0] == 2) & (arcs[:, 1] == 0))][:1]
+    e2x = arcs[((arcs[:, 0] == 2) & (arcs[:, 1] > 3)) | ((arcs[:, 1] == 2) & (arcs[:, 0] > 3))][:1]
+    two = np.concatenate([e02, e2x])
+    assert len(two) == 2
     p.delete(two[:, 0], two[:, 1])
     p.check_tc()
     p.insert(two[:, 0], two[:, 1], np.full(2, 7))
